@@ -1,0 +1,159 @@
+/*
+ * bqs.h -- C ABI of a BlockQuicksort-style sort for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Operation (Edelkamp & Weiss, "BlockQuicksort: How Branch Mispredictions
+ * don't affect Quicksort", arXiv 1604.06697, Introduction and Section 2):
+ * rearrange a sequence of elements of a totally ordered universe into
+ * ascending order, in place from the caller's point of view.  The library
+ * runs Quicksort whose partitioning step is the paper's block partition
+ * (Section 3, Algorithm 3) re-organised for a GPU: keys are compared with
+ * the pivot a tile at a time, the comparison outcomes become offsets, and a
+ * second pass moves the elements without comparison-dependent branches.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named keys / vals / offsets / workspace are DEVICE pointers
+ *     owned by the caller.  The library never allocates or frees device
+ *     memory; it only owns host-side state inside a context.
+ *   - Calls enqueue work on the context's HIP stream (default: the null
+ *     stream).  The current implementation waits on that stream between
+ *     recursion levels, so a call returns after the sort has finished on
+ *     the device.
+ *   - Argument errors are reported at once and nothing is enqueued.
+ *     Device-detected errors (a work list overflowing its capacity, a
+ *     malformed offsets array) are latched in the context and returned by
+ *     the call that detects them and by bqs_ctx_sync_status().
+ *   - Keys are 1-D and contiguous.  Integer keys use their usual order;
+ *     float keys use IEEE-754 totalOrder restricted to non-NaN values, so
+ *     -0.0 sorts before +0.0.  NaN keys violate the precondition (their
+ *     position is unspecified).
+ *   - The result is unique for keys.  For key-value pairs the payload
+ *     travels with its key; the order of payloads among equal keys is not
+ *     specified (Quicksort is unstable, Introduction) but is deterministic
+ *     for identical inputs and parameters.
+ */
+#ifndef BQS_H
+#define BQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BQS_I32 = 1,
+    BQS_U32 = 2,
+    BQS_I64 = 3,
+    BQS_U64 = 4,
+    BQS_F32 = 5,
+    BQS_F64 = 6
+} bqs_dtype;
+
+typedef enum {
+    BQS_OK = 0,
+    BQS_EINVAL = 1,     /* bad argument: null pointer, negative size, workspace too small, ... */
+    BQS_EDTYPE = 2,     /* unsupported key dtype or payload width                          */
+    BQS_ENOMEM = 3,     /* host-side allocation inside the context failed                  */
+    BQS_EHIP = 4,       /* a HIP runtime call failed                                        */
+    BQS_ENAN = 5,       /* reserved: NaN detected (not checked by the current kernels)      */
+    BQS_EOVERFLOW = 6   /* a device work list or the level cap was exceeded                 */
+} bqs_status;
+
+/* Tunable parameters (bqs_ctx_set_param).  Values <= 0 restore defaults. */
+typedef enum {
+    BQS_PARAM_SMALL_CUTOFF = 1, /* segments of at most this many keys are sorted inside one
+                                   workgroup's LDS (clamped to the compiled maximum)          */
+    BQS_PARAM_SAMPLE_MAX = 2,   /* largest pivot sample (odd, <= 255); the pivot is the median
+                                   of the sample (Section 2, pivot selection)                  */
+    BQS_PARAM_PIVOT_MODE = 3,   /* 0: median of a stratified sample; 3: median of first, middle
+                                   and last key (median-of-three, Section 2)                    */
+    BQS_PARAM_TIMING = 4,       /* 1: time every partition / small-sort launch with HIP events */
+    BQS_PARAM_TILE_EPT = 5,     /* keys per thread in a partition tile (8, 16 or 32; 0 = auto)  */
+    BQS_PARAM_GRID = 6          /* workgroups per launch of the persistent kernels (0 = auto)  */
+} bqs_param;
+
+typedef struct {
+    int64_t levels;             /* partition passes executed by the last call                  */
+    int64_t partitioned_keys;   /* sum of segment sizes over all partition passes              */
+    int64_t small_sorted_keys;  /* keys finished by the in-LDS small sort                       */
+    int64_t filled_keys;        /* keys equal to a pivot, written by the fill step             */
+    int64_t tiles;              /* partition tiles processed                                    */
+    double partition_ms;        /* summed partition-kernel time (BQS_PARAM_TIMING only)         */
+    int64_t partition_launches;
+    double small_ms;            /* summed small-sort kernel time (BQS_PARAM_TIMING only)        */
+    int64_t small_launches;
+    double plan_ms;             /* summed pivot/fill kernel time (BQS_PARAM_TIMING only)        */
+    int64_t tile_keys;          /* compiled tile size used (keys per tile)                      */
+    int64_t small_cutoff;       /* small-sort cutoff used                                       */
+} bqs_stats;
+
+typedef struct bqs_ctx bqs_ctx; /* opaque, host-side */
+
+/* Creates a context.  Host memory only; no GPU call is made.  *out receives
+ * the handle; returns BQS_EINVAL if out is NULL, BQS_ENOMEM on failure. */
+bqs_status bqs_ctx_create(bqs_ctx** out);
+
+/* Destroys a context (NULL is allowed).  Does not touch caller memory. */
+void bqs_ctx_destroy(bqs_ctx* ctx);
+
+/* Sets the HIP stream (a hipStream_t passed as void*) on which all work of
+ * this context is enqueued.  NULL selects the null stream. */
+bqs_status bqs_ctx_set_stream(bqs_ctx* ctx, void* hip_stream);
+
+/* Hands the context a caller-owned device buffer of `bytes` bytes used as
+ * scratch by the next calls (double buffer, work lists, tile status words).
+ * Its size must be at least bqs_workspace_bytes() of the call.  The library
+ * keeps the pointer only; the caller keeps it alive while calls run. */
+bqs_status bqs_ctx_set_workspace(bqs_ctx* ctx, void* dev_ptr, size_t bytes);
+
+bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value);
+int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param);
+
+/* Statistics of the most recent successful call on this context. */
+bqs_status bqs_ctx_get_stats(const bqs_ctx* ctx, bqs_stats* out);
+
+/* Workspace needed to sort n_total keys of `key` type with `val_bytes`-byte
+ * payloads (0 for keys only) split into k_segments segments (1 for a single
+ * array), under the context's current parameters (ctx may be NULL for the
+ * defaults).  Returns 0 for an unsupported dtype / payload width. */
+size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, int32_t val_bytes,
+                           int64_t k_segments);
+
+/* Sorts keys[0..n) ascending (Introduction: the problem statement; the
+ * recursion follows Algorithm 1 with the improvements of Section 2).
+ * keys: device pointer, n elements of `dtype`, 4-byte aligned (8 for 64-bit
+ * keys).  n < 0 or keys == NULL with n > 0 -> BQS_EINVAL.  n <= 1 is a
+ * no-op.  Each segment handled by a partition pass must hold fewer than
+ * 2^31 keys. */
+bqs_status bqs_sort(void* keys, int64_t n, bqs_dtype dtype, bqs_ctx* ctx);
+
+/* Sorts (keys[i], vals[i]) records by key: the payload moves with its key.
+ * vals: device pointer to n payloads of val_bytes (4 or 8) bytes each;
+ * keys and vals must not overlap each other or the workspace. */
+bqs_status bqs_sort_pairs(void* keys, void* vals, int64_t n, bqs_dtype key, int32_t val_bytes,
+                          bqs_ctx* ctx);
+
+/* Sorts k independent segments keys[offsets[i] .. offsets[i+1]) in one
+ * batched launch sequence.  offsets: device pointer to k+1 int64 values,
+ * offsets[0] = 0, non-decreasing, offsets[k] = n_total (the caller passes
+ * n_total so no device read-back is needed to size the work).  A malformed
+ * offsets array is detected on the device and reported as BQS_EINVAL. */
+bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int64_t n_total,
+                             bqs_dtype dtype, bqs_ctx* ctx);
+
+/* Synchronises the context's stream and returns the latched device status. */
+bqs_status bqs_ctx_sync_status(bqs_ctx* ctx);
+
+/* Static, human-readable name of a status code. */
+const char* bqs_status_str(bqs_status status);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int bqs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BQS_H */

@@ -1,0 +1,513 @@
+// Host runtime behind include/bqs.h: argument checks, workspace layout,
+// kernel selection and the level loop that drives the partition passes.
+//
+// The Quicksort main loop of the paper (Algorithm 1 with an explicit stack,
+// Section 2) becomes a breadth-first loop over recursion levels: all
+// segments of one level are partitioned by one launch, their children form
+// the next level's list on the device.  Segments of at most small_cut keys
+// leave the loop and are sorted in LDS; runs of keys equal to a pivot leave
+// it as well (the pivot is excluded from the recursion, Section 2).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "bqs.h"
+#include "bqs_internal.h"
+
+namespace bqs {
+
+// ---------------------------------------------------------------- set-up --
+
+__global__ void k_init_single(Args a) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    Ctl* c = a.ctl;
+    for (int s = 0; s < 2; ++s) {
+        c->lc[s].segs = 0;
+        c->lc[s].fills = 0;
+        c->lc[s].smalls = 0;
+        c->lc[s].tile_next = 0;
+        c->lc[s].pad = 0;
+    }
+    c->error = 0;
+    c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
+    const int64_t n = a.n;
+    if (n > a.small_cut) {
+        const int64_t T = a.tile_keys;
+        const uint32_t nt = static_cast<uint32_t>((n + T - 1) / T);
+        SegDesc d{};
+        d.lo = 0;
+        d.hi = n;
+        d.t0 = 0;
+        d.nt = nt;
+        a.segs[0][0] = d;
+        c->lc[0].segs = (static_cast<unsigned long long>(nt) << 32) | 1ull;
+    } else if (n >= 2) {
+        a.smalls[0][0] = SmallItem{0, n};
+        c->lc[0].smalls = 1;
+    }
+}
+
+__global__ void k_zero_ctl(Args a) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    Ctl* c = a.ctl;
+    for (int s = 0; s < 2; ++s) {
+        c->lc[s].segs = 0;
+        c->lc[s].fills = 0;
+        c->lc[s].smalls = 0;
+        c->lc[s].tile_next = 0;
+        c->lc[s].pad = 0;
+    }
+    c->error = 0;
+    c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
+}
+
+// One thread per segment: validate the offsets, then route the segment to
+// the level-0 partition list or straight to the small sort.
+__global__ void k_init_segments(Args a) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.k) return;
+    const int64_t lo = a.offsets[i], hi = a.offsets[i + 1];
+    const bool bad = lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) ||
+                     (i == a.k - 1 && hi != a.n) || hi - lo >= (int64_t(1) << 31);
+    if (bad) {
+        atomicOr(&a.ctl->error, ERR_OFFSETS);
+        return;
+    }
+    const int64_t m = hi - lo;
+    Ctl* c = a.ctl;
+    if (m > a.small_cut) {
+        const int64_t T = a.tile_keys;
+        const uint32_t nt = static_cast<uint32_t>((hi + T - 1) / T - lo / T);
+        const unsigned long long r =
+            atomicAdd(&c->lc[0].segs, (static_cast<unsigned long long>(nt) << 32) | 1ull);
+        const uint32_t idx = static_cast<uint32_t>(r);
+        const uint64_t t0 = r >> 32;
+        if (idx >= a.cap_seg || t0 + nt > a.cap_tile) {
+            atomicOr(&c->error, ERR_OVERFLOW);
+            return;
+        }
+        SegDesc d{};
+        d.lo = lo;
+        d.hi = hi;
+        d.t0 = static_cast<uint32_t>(t0);
+        d.nt = nt;
+        a.segs[0][idx] = d;
+    } else if (m >= 2) {
+        const uint32_t idx = atomicAdd(&c->lc[0].smalls, 1u);
+        if (idx >= a.cap_small) {
+            atomicOr(&c->error, ERR_OVERFLOW);
+            return;
+        }
+        a.smalls[0][idx] = SmallItem{lo, hi};
+    }
+}
+
+void launch_init_single(const Args& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_single, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch_init_segments(const Args& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, s, a);
+    const int64_t blocks = (a.k + 255) / 256;
+    if (blocks > 0) hipLaunchKernelGGL(k_init_segments, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+}
+
+// -------------------------------------------------------------- layout ----
+
+struct Layout {
+    size_t ctl, yk, yv, side, segs[2], smalls[2], fills[2], tile_seg, status, total;
+    uint64_t cap_seg, cap_tile, cap_small, cap_fill;
+};
+
+static size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S) {
+    Layout L{};
+    const uint64_t un = static_cast<uint64_t>(n);
+    L.cap_seg = un / static_cast<uint64_t>(S + 1) + 1;
+    L.cap_tile = un / static_cast<uint64_t>(T) + 2 * L.cap_seg + 2;
+    L.cap_small = 2 * L.cap_seg + static_cast<uint64_t>(k) + 2;
+    L.cap_fill = L.cap_seg + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.ctl = take(sizeof(Ctl));
+    L.yk = take(un * kb);
+    L.yv = take(vb ? un * vb : 0);
+    L.side = take(vb ? un * vb : 0);
+    for (int s = 0; s < 2; ++s) L.segs[s] = take(L.cap_seg * sizeof(SegDesc));
+    for (int s = 0; s < 2; ++s) L.smalls[s] = take(L.cap_small * sizeof(SmallItem));
+    for (int s = 0; s < 2; ++s) L.fills[s] = take(L.cap_fill * sizeof(FillItem));
+    L.tile_seg = take(L.cap_tile * sizeof(uint32_t));
+    L.status = take(L.cap_tile * sizeof(unsigned long long));
+    L.total = off;
+    return L;
+}
+
+static size_t key_bytes(int dtype) {
+    switch (dtype) {
+        case BQS_I32: case BQS_U32: case BQS_F32: return 4;
+        case BQS_I64: case BQS_U64: case BQS_F64: return 8;
+        default: return 0;
+    }
+}
+
+}  // namespace bqs
+
+// ----------------------------------------------------------------- ctx ----
+
+struct bqs_ctx {
+    hipStream_t stream = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t small_cut = 0;
+    int64_t sample_max = 0;
+    int64_t pivot_mode = 0;
+    int64_t timing = 0;
+    int64_t ept = 0;
+    int64_t grid = 0;
+    bqs_stats stats{};
+    bqs_status latched = BQS_OK;
+    bqs::Ctl* pinned = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+using namespace bqs;
+
+namespace {
+
+const Ops* select_ops(const bqs_ctx* ctx, int dtype, int val_bytes) {
+    if (val_bytes == 0) return ops_keys(dtype, ctx ? static_cast<int>(ctx->ept) : 0);
+    if (val_bytes == 4) return ops_pairs32(dtype);
+    if (val_bytes == 8) return ops_pairs64(dtype);
+    return nullptr;
+}
+
+int64_t eff_small_cut(const bqs_ctx* ctx, const Ops* o) {
+    int64_t s = ctx && ctx->small_cut > 0 ? ctx->small_cut : o->small_max;
+    if (s > o->small_max) s = o->small_max;
+    if (s < 2) s = 2;
+    return s;
+}
+
+int64_t floor_log2(int64_t n) {
+    int64_t k = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++k;
+    }
+    return k;
+}
+
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+    if (!a || !b || !an || !bn) return false;
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bn && y < x + an;
+}
+
+bqs_status hip_ok(hipError_t e) { return e == hipSuccess ? BQS_OK : BQS_EHIP; }
+
+bqs_status ensure_device_state(bqs_ctx* ctx) {
+    if (!ctx->pinned) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return BQS_EHIP;
+        ctx->pinned = static_cast<Ctl*>(p);
+    }
+    if (!ctx->ev[0]) {
+        if (hipEventCreate(&ctx->ev[0]) != hipSuccess) return BQS_EHIP;
+        if (hipEventCreate(&ctx->ev[1]) != hipSuccess) return BQS_EHIP;
+    }
+    return BQS_OK;
+}
+
+// Copies the device control block to pinned host memory and waits.
+bqs_status read_ctl(bqs_ctx* ctx, const Ctl* dev) {
+    if (hipMemcpyAsync(ctx->pinned, dev, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+        return BQS_EHIP;
+    return hip_ok(hipStreamSynchronize(ctx->stream));
+}
+
+struct Timer {
+    bqs_ctx* ctx;
+    bool on;
+    void start() {
+        if (on) hipEventRecord(ctx->ev[0], ctx->stream);
+    }
+    double stop() {
+        if (!on) return 0.0;
+        hipEventRecord(ctx->ev[1], ctx->stream);
+        hipEventSynchronize(ctx->ev[1]);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]);
+        return ms;
+    }
+};
+
+int clamp_grid(uint64_t want, int64_t cap) {
+    if (want < 1) want = 1;
+    if (want > static_cast<uint64_t>(cap)) want = static_cast<uint64_t>(cap);
+    return static_cast<int>(want);
+}
+
+// The level loop shared by all entry points.
+bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
+    bqs_status st = ensure_device_state(ctx);
+    if (st != BQS_OK) return st;
+    const hipStream_t s = ctx->stream;
+    Timer tm{ctx, ctx->timing != 0};
+    bqs_stats stats{};
+    stats.tile_keys = o->tile_keys;
+    stats.small_cutoff = a.small_cut;
+
+    if (segmented) launch_init_segments(a, s);
+    else launch_init_single(a, s);
+    if (hipGetLastError() != hipSuccess) return BQS_EHIP;
+    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+    if (ctx->pinned->error) return (ctx->pinned->error & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
+    LevelCtr cur = ctx->pinned->lc[0];
+
+    const int64_t level_cap = 4 * static_cast<int64_t>(a.depth_limit) + 64;
+    const int64_t tile_grid_cap = ctx->grid > 0 ? ctx->grid : 256 * 16;
+    for (int L = 0;; ++L) {
+        a.level = L;
+        const uint32_t nseg = static_cast<uint32_t>(cur.segs);
+        const uint32_t ntile = static_cast<uint32_t>(cur.segs >> 32);
+        const uint32_t nchunk = static_cast<uint32_t>(cur.fills >> 32);
+        tm.start();
+        o->plan(a, clamp_grid(std::max<uint64_t>(nseg, nchunk), 8192), s);
+        stats.plan_ms += tm.stop();
+        if (cur.smalls) {
+            tm.start();
+            o->small(a, clamp_grid(cur.smalls, 8192), s);
+            stats.small_ms += tm.stop();
+            stats.small_launches++;
+        }
+        if (hipGetLastError() != hipSuccess) return BQS_EHIP;
+        if (nseg == 0) break;
+        if (L >= level_cap) return BQS_EOVERFLOW;
+        tm.start();
+        o->tile(a, clamp_grid(ntile, tile_grid_cap), s);
+        stats.partition_ms += tm.stop();
+        stats.partition_launches++;
+        stats.levels++;
+        if (hipGetLastError() != hipSuccess) return BQS_EHIP;
+        if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+        if (ctx->pinned->error) return BQS_EOVERFLOW;
+        cur = ctx->pinned->lc[(L + 1) & 1];
+    }
+    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+    if (ctx->pinned->error) return BQS_EOVERFLOW;
+    stats.partitioned_keys = static_cast<int64_t>(ctx->pinned->part_keys);
+    stats.small_sorted_keys = static_cast<int64_t>(ctx->pinned->small_keys);
+    stats.filled_keys = static_cast<int64_t>(ctx->pinned->fill_keys);
+    stats.tiles = static_cast<int64_t>(ctx->pinned->tiles);
+    ctx->stats = stats;
+    return BQS_OK;
+}
+
+bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int64_t k, void* keys,
+                   void* vals, Args& a) {
+    const size_t kb = key_bytes(dtype);
+    const int64_t S = eff_small_cut(ctx, o);
+    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, o->tile_keys, S);
+    if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull)
+        return BQS_EINVAL;
+    if (!ctx->ws || ctx->ws_bytes < L.total) return BQS_EINVAL;
+    if (overlaps(keys, static_cast<size_t>(n) * kb, ctx->ws, ctx->ws_bytes)) return BQS_EINVAL;
+    if (vals && (overlaps(vals, static_cast<size_t>(n) * vb, ctx->ws, ctx->ws_bytes) ||
+                 overlaps(vals, static_cast<size_t>(n) * vb, keys, static_cast<size_t>(n) * kb)))
+        return BQS_EINVAL;
+    char* w = static_cast<char*>(ctx->ws);
+    a = Args{};
+    a.ctl = reinterpret_cast<Ctl*>(w + L.ctl);
+    a.x_keys = keys;
+    a.y_keys = w + L.yk;
+    a.x_vals = vals;
+    a.y_vals = vb ? w + L.yv : nullptr;
+    a.side = vb ? w + L.side : nullptr;
+    for (int s = 0; s < 2; ++s) {
+        a.segs[s] = reinterpret_cast<SegDesc*>(w + L.segs[s]);
+        a.smalls[s] = reinterpret_cast<SmallItem*>(w + L.smalls[s]);
+        a.fills[s] = reinterpret_cast<FillItem*>(w + L.fills[s]);
+    }
+    a.tile_seg = reinterpret_cast<uint32_t*>(w + L.tile_seg);
+    a.status = reinterpret_cast<unsigned long long*>(w + L.status);
+    a.cap_seg = static_cast<uint32_t>(L.cap_seg);
+    a.cap_tile = static_cast<uint32_t>(L.cap_tile);
+    a.cap_small = static_cast<uint32_t>(L.cap_small);
+    a.cap_fill = static_cast<uint32_t>(L.cap_fill);
+    a.n = n;
+    a.k = k;
+    a.small_cut = static_cast<int>(S);
+    a.sample_max = static_cast<int>(ctx->sample_max > 0 ? std::min<int64_t>(ctx->sample_max, kMaxSample)
+                                                        : kMaxSample);
+    a.pivot_mode = static_cast<int>(ctx->pivot_mode);
+    a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
+    a.tile_keys = o->tile_keys;
+    return BQS_OK;
+}
+
+bqs_status finish(bqs_ctx* ctx, bqs_status st) {
+    if (st != BQS_OK) ctx->latched = st;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+bqs_status bqs_ctx_create(bqs_ctx** out) {
+    if (!out) return BQS_EINVAL;
+    *out = new (std::nothrow) bqs_ctx();
+    return *out ? BQS_OK : BQS_ENOMEM;
+}
+
+void bqs_ctx_destroy(bqs_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->pinned) hipHostFree(ctx->pinned);
+    for (hipEvent_t e : ctx->ev)
+        if (e) hipEventDestroy(e);
+    delete ctx;
+}
+
+bqs_status bqs_ctx_set_stream(bqs_ctx* ctx, void* hip_stream) {
+    if (!ctx) return BQS_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return BQS_OK;
+}
+
+bqs_status bqs_ctx_set_workspace(bqs_ctx* ctx, void* dev_ptr, size_t bytes) {
+    if (!ctx || (bytes && !dev_ptr)) return BQS_EINVAL;
+    ctx->ws = dev_ptr;
+    ctx->ws_bytes = bytes;
+    return BQS_OK;
+}
+
+bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
+    if (!ctx) return BQS_EINVAL;
+    if (value < 0) value = 0;
+    switch (param) {
+        case BQS_PARAM_SMALL_CUTOFF: ctx->small_cut = value; break;
+        case BQS_PARAM_SAMPLE_MAX: ctx->sample_max = value; break;
+        case BQS_PARAM_PIVOT_MODE:
+            if (value != 0 && value != 3) return BQS_EINVAL;
+            ctx->pivot_mode = value;
+            break;
+        case BQS_PARAM_TIMING: ctx->timing = value ? 1 : 0; break;
+        case BQS_PARAM_TILE_EPT:
+            if (value != 0 && value != 8 && value != 16 && value != 32) return BQS_EINVAL;
+            ctx->ept = value;
+            break;
+        case BQS_PARAM_GRID: ctx->grid = value; break;
+        default: return BQS_EINVAL;
+    }
+    return BQS_OK;
+}
+
+int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
+    if (!ctx) return -1;
+    switch (param) {
+        case BQS_PARAM_SMALL_CUTOFF: return ctx->small_cut;
+        case BQS_PARAM_SAMPLE_MAX: return ctx->sample_max;
+        case BQS_PARAM_PIVOT_MODE: return ctx->pivot_mode;
+        case BQS_PARAM_TIMING: return ctx->timing;
+        case BQS_PARAM_TILE_EPT: return ctx->ept;
+        case BQS_PARAM_GRID: return ctx->grid;
+        default: return -1;
+    }
+}
+
+bqs_status bqs_ctx_get_stats(const bqs_ctx* ctx, bqs_stats* out) {
+    if (!ctx || !out) return BQS_EINVAL;
+    *out = ctx->stats;
+    return BQS_OK;
+}
+
+size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, int32_t val_bytes,
+                           int64_t k_segments) {
+    if (n_total < 0 || k_segments < 0) return 0;
+    const Ops* o = select_ops(ctx, key, val_bytes);
+    if (!o) return 0;
+    const Layout L = make_layout(n_total, key_bytes(key), static_cast<size_t>(val_bytes),
+                                 std::max<int64_t>(k_segments, 1), o->tile_keys, eff_small_cut(ctx, o));
+    return L.total;
+}
+
+bqs_status bqs_sort(void* keys, int64_t n, bqs_dtype dtype, bqs_ctx* ctx) {
+    if (!ctx || n < 0 || (n > 0 && !keys)) return BQS_EINVAL;
+    const Ops* o = select_ops(ctx, dtype, 0);
+    if (!o) return BQS_EDTYPE;
+    if (n <= 1) {
+        ctx->stats = bqs_stats{};
+        return BQS_OK;
+    }
+    if (n >= (int64_t(1) << 31)) return BQS_EINVAL;
+    Args a;
+    bqs_status st = prepare(ctx, o, n, dtype, 0, 1, keys, nullptr, a);
+    if (st != BQS_OK) return st;
+    return finish(ctx, run_sort(ctx, o, a, false));
+}
+
+bqs_status bqs_sort_pairs(void* keys, void* vals, int64_t n, bqs_dtype key, int32_t val_bytes,
+                          bqs_ctx* ctx) {
+    if (!ctx || n < 0 || (n > 0 && (!keys || !vals))) return BQS_EINVAL;
+    if (val_bytes != 4 && val_bytes != 8) return BQS_EDTYPE;
+    const Ops* o = select_ops(ctx, key, val_bytes);
+    if (!o) return BQS_EDTYPE;
+    if (n <= 1) {
+        ctx->stats = bqs_stats{};
+        return BQS_OK;
+    }
+    if (n >= (int64_t(1) << 31)) return BQS_EINVAL;
+    Args a;
+    bqs_status st = prepare(ctx, o, n, key, val_bytes, 1, keys, vals, a);
+    if (st != BQS_OK) return st;
+    return finish(ctx, run_sort(ctx, o, a, false));
+}
+
+bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int64_t n_total,
+                             bqs_dtype dtype, bqs_ctx* ctx) {
+    if (!ctx || k < 0 || n_total < 0 || (n_total > 0 && !keys) || (k > 0 && !offsets)) return BQS_EINVAL;
+    const Ops* o = select_ops(ctx, dtype, 0);
+    if (!o) return BQS_EDTYPE;
+    if (k == 0 || n_total <= 1) {
+        ctx->stats = bqs_stats{};
+        return BQS_OK;
+    }
+    Args a;
+    bqs_status st = prepare(ctx, o, n_total, dtype, 0, k, keys, nullptr, a);
+    if (st != BQS_OK) return st;
+    a.offsets = offsets;
+    return finish(ctx, run_sort(ctx, o, a, true));
+}
+
+bqs_status bqs_ctx_sync_status(bqs_ctx* ctx) {
+    if (!ctx) return BQS_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return BQS_EHIP;
+    return ctx->latched;
+}
+
+const char* bqs_status_str(bqs_status s) {
+    switch (s) {
+        case BQS_OK: return "ok";
+        case BQS_EINVAL: return "invalid argument";
+        case BQS_EDTYPE: return "unsupported dtype";
+        case BQS_ENOMEM: return "out of host memory";
+        case BQS_EHIP: return "HIP runtime error";
+        case BQS_ENAN: return "NaN key";
+        case BQS_EOVERFLOW: return "device work list overflow";
+        default: return "unknown status";
+    }
+}
+
+int bqs_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal interface between the host runtime (bqs_api.hip) and the kernel
+// translation units.  Not part of the public ABI (include/bqs.h).
+//
+// Work is organised by recursion level L (Quicksort, Algorithm 1, unrolled
+// breadth first).  Level L reads its segments from buffer (L & 1) -- 0 is the
+// caller's array X, 1 the workspace copy Y -- and writes the partitioned
+// result to buffer ((L + 1) & 1).  Every list that level L consumes lives in
+// slot (L & 1) and is produced by level L-1 (or by the init kernels for L=0):
+//   segs   : segments partitioned at level L (more than small_cut keys)
+//   smalls : segments finished at level L by the in-LDS sort
+//   fills  : runs of keys equal to a level L-1 pivot, written at level L
+// The kernels of one level, in stream order: plan (pivots, tile map, fills),
+// small (in-LDS sorts), partition (tiles; appends the level L+1 lists).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bqs.h"
+
+namespace bqs {
+
+constexpr int kFillChunk = 4096;  // keys per fill work unit
+constexpr int kMaxSample = 255;   // largest pivot sample
+
+struct SegDesc {
+    int64_t lo, hi;      // [lo, hi) in the level's source buffer
+    uint64_t pivot;      // pivot as an order key (set by the plan kernel)
+    uint64_t pivot_raw;  // pivot as stored bits
+    uint32_t t0, nt;     // tiles [t0, t0 + nt) of this level belong to the segment
+    uint32_t depth, pad;
+};
+
+struct SmallItem {
+    int64_t lo, hi;
+};
+
+struct FillItem {
+    int64_t dst;     // first position of the equal run in X
+    int64_t len;     // run length
+    int64_t side;    // first position of the run's payloads in the side buffer
+    uint64_t raw;    // key bits of the pivot
+    uint32_t chunk0; // first fill work unit of this item
+    uint32_t pad0;
+    uint64_t pad1;
+};
+
+struct LevelCtr {
+    unsigned long long segs;   // low 32 bits: segments, high 32 bits: tiles
+    unsigned long long fills;  // low 32 bits: items, high 32 bits: work units
+    unsigned int smalls;
+    unsigned int tile_next;    // tile claim counter of the level that consumes this slot
+    unsigned long long pad;
+};
+
+enum : unsigned { ERR_OVERFLOW = 1u, ERR_OFFSETS = 2u };
+
+struct Ctl {
+    LevelCtr lc[2];
+    unsigned int error;
+    unsigned int pad;
+    unsigned long long part_keys;
+    unsigned long long small_keys;
+    unsigned long long fill_keys;
+    unsigned long long tiles;
+};
+
+struct Args {
+    Ctl* ctl;
+    void* x_keys;
+    void* y_keys;
+    void* x_vals;
+    void* y_vals;
+    void* side;
+    SegDesc* segs[2];
+    SmallItem* smalls[2];
+    FillItem* fills[2];
+    uint32_t* tile_seg;
+    unsigned long long* status;
+    uint32_t cap_seg, cap_tile, cap_small, cap_fill;
+    int64_t n;
+    const int64_t* offsets;
+    int64_t k;
+    int level;
+    int small_cut;
+    int sample_max;
+    int pivot_mode;
+    int depth_limit;
+    int tile_keys;
+};
+
+struct Ops {
+    int tile_keys;  // keys per partition tile
+    int small_max;  // capacity of the in-LDS small sort
+    void (*plan)(const Args&, int grid, hipStream_t);
+    void (*small)(const Args&, int grid, hipStream_t);
+    void (*tile)(const Args&, int grid, hipStream_t);
+};
+
+// Kernel tables, one per payload kind; nullptr for an unsupported request.
+const Ops* ops_keys(int dtype, int ept);
+const Ops* ops_pairs32(int dtype);
+const Ops* ops_pairs64(int dtype);
+
+// Dtype-independent set-up kernels (bqs_api.hip).
+void launch_init_single(const Args& a, hipStream_t s);
+void launch_init_segments(const Args& a, hipStream_t s);
+
+}  // namespace bqs

@@ -1,0 +1,309 @@
+"""GPU parity tests: the HIP library against the CPU oracle, element by
+element, on the same seeded inputs.  Keys must match bit for bit (the sorted
+sequence of a totally ordered key set is unique).  For key-value pairs the
+keys must match and every payload must travel with its key (the order of
+payloads among equal keys is not unique: Quicksort is unstable).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bqs():
+    import paper_1604_06697_amd as bqs_mod
+
+    return bqs_mod
+
+
+_KT = {np.dtype(np.int32): "i32", np.dtype(np.uint32): "u32", np.dtype(np.float32): "f32",
+       np.dtype(np.int64): "i64", np.dtype(np.uint64): "u64", np.dtype(np.float64): "f64"}
+_HOLD = {np.dtype(np.uint32): np.int32, np.dtype(np.uint64): np.int64}
+
+
+def to_dev(torch, a):
+    hold = _HOLD.get(a.dtype)
+    src = a.view(hold) if hold is not None else a
+    return torch.from_numpy(np.ascontiguousarray(src)).cuda()
+
+
+def from_dev(t, dtype):
+    return t.cpu().numpy().view(dtype)
+
+
+def gpu_sort(torch, bqs, a, ctx=None):
+    t = to_dev(torch, a)
+    (ctx or bqs.default_context()).sort(t, key_type=_KT[a.dtype])
+    torch.cuda.synchronize()
+    return from_dev(t, a.dtype)
+
+
+def assert_same_bits(got, expect):
+    assert got.dtype == expect.dtype and got.shape == expect.shape
+    if not np.array_equal(got.view(f"u{got.itemsize}"), expect.view(f"u{expect.itemsize}")):
+        diff = np.flatnonzero(got.view(f"u{got.itemsize}") != expect.view(f"u{expect.itemsize}"))
+        raise AssertionError(f"{diff.size} positions differ, first at {diff[:8]}: "
+                             f"got {got[diff[:4]]} expect {expect[diff[:4]]}")
+
+
+# ------------------------------------------------------------------ keys --
+
+def test_config0_million_uniform_int32(torch_mod, bqs, oracle):
+    """1,000,000 uniform int32 keys: the oracle with the paper's parameters
+    (median-of-three, B = 128, insertion sort <= 16) against the GPU, with
+    both the default pivot sample and median-of-three on the GPU."""
+    for seed in range(3):
+        a = W.uniform_i32(1_000_000, seed)
+        expect = oracle.sort(a)
+        note(f"config0 seed={seed} default plan")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a), expect)
+        note(f"config0 seed={seed} median-of-3")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, bqs.Context(pivot_mode=3)), expect)
+
+
+RAGGED = [0, 1, 2, 3, 5, 17, 64, 65, 100, 1000, 4095, 4096, 4097, 8191, 8192, 8193, 8194,
+          12295, 16384, 65537, 100_003, (1 << 20) + 13]
+
+
+@pytest.mark.parametrize("family", sorted(W.I32_FAMILIES))
+def test_i32_families_ragged_sizes(torch_mod, bqs, oracle, family):
+    gen = W.I32_FAMILIES[family]
+    for n in RAGGED:
+        a = gen(n, n + 1)
+        note(f"i32 {family} n={n}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a), oracle.sort(a))
+
+
+@pytest.mark.parametrize("family", sorted(W.I32_EXTRA_FAMILIES))
+def test_i32_paper_families(torch_mod, bqs, oracle, family):
+    gen = W.I32_EXTRA_FAMILIES[family]
+    for n in [1000, 50_000, 300_001]:
+        a = gen(n, 7) if family != "neighbour_swaps" else gen(n, 7, k=n // 10)
+        note(f"i32 {family} n={n}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a), oracle.sort(a))
+
+
+@pytest.mark.parametrize("cutoff,ept", [(2, 16), (16, 8), (100, 32), (300, 16), (1000, 8)])
+def test_deep_recursion_small_cutoffs(torch_mod, bqs, oracle, cutoff, ept):
+    """Tiny small-sort cutoffs force many partition levels, one-tile and
+    multi-tile segments, and every tile shape."""
+    ctx = bqs.Context(small_cutoff=cutoff, tile_ept=ept)
+    for fam, n in [("uniform", 200_003), ("few_distinct", 100_000), ("sorted", 70_001),
+                   ("reverse", 33_333), ("all_equal", 50_000)]:
+        a = W.I32_FAMILIES[fam](n, 3)
+        note(f"cutoff={cutoff} ept={ept} {fam} n={n}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.int64, np.uint64])
+def test_integer_dtypes(torch_mod, bqs, oracle, dtype):
+    info = np.iinfo(dtype)
+    for n in [3, 1000, 9000, 250_001]:
+        a = W.rng(n).integers(info.min, info.max, size=n, dtype=dtype, endpoint=True)
+        a[: min(4, n)] = [info.min, info.max, info.min, info.max][: min(4, n)]
+        note(f"{np.dtype(dtype).name} n={n}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a), oracle.sort(a))
+
+
+def test_float64_families(torch_mod, bqs, oracle):
+    for name, gen in W.F64_FAMILIES.items():
+        for n in [5000, 300_007]:
+            a = gen(n, 4)
+            note(f"f64 {name} n={n}")
+            assert_same_bits(gpu_sort(torch_mod, bqs, a), oracle.sort(a))
+
+
+def test_float_special_values(torch_mod, bqs, oracle):
+    for n in [100, 10_000, 200_000]:
+        a = W.special_f64(n, n)
+        note(f"f64 special n={n}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a), oracle.sort(a))
+        with np.errstate(over="ignore"):
+            f = a.astype(np.float32)
+        note(f"f32 special n={n}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, f), oracle.sort(f))
+    z = np.array([0.0, -0.0] * 6000)
+    note("f64 zeros")
+    out = gpu_sort(torch_mod, bqs, z)
+    assert np.all(np.signbit(out[:6000])) and not np.any(np.signbit(out[6000:]))
+
+
+# ----------------------------------------------------------------- pairs --
+
+def check_pairs(keys_in, ko, vo, expect_keys):
+    assert_same_bits(ko, expect_keys)
+    n = keys_in.size
+    assert np.array_equal(np.sort(vo.astype(np.int64)), np.arange(n))
+    assert np.array_equal(keys_in[vo.astype(np.int64)].view(np.uint64 if keys_in.itemsize == 8 else np.uint32),
+                          ko.view(np.uint64 if ko.itemsize == 8 else np.uint32))
+
+
+def gpu_pairs(torch, bqs, k, v, ctx=None):
+    tk = to_dev(torch, k)
+    tv = to_dev(torch, v)
+    (ctx or bqs.default_context()).sort_pairs(tk, tv, key_type=_KT[k.dtype])
+    torch.cuda.synchronize()
+    return from_dev(tk, k.dtype), from_dev(tv, v.dtype)
+
+
+@pytest.mark.parametrize("n", [2, 17, 2047, 2048, 2049, 4097, 100_000, 1 << 20])
+def test_pairs_u64_u32(torch_mod, bqs, oracle, n):
+    k, v = W.uniform_u64_pairs(n, n)
+    note(f"pairs u64/u32 n={n}")
+    ko, vo = gpu_pairs(torch_mod, bqs, k, v)
+    check_pairs(k, ko, vo, oracle.sort(k))
+
+
+def test_pairs_with_ties_and_payload_widths(torch_mod, bqs, oracle):
+    for n in [5000, 300_000]:
+        k, v = W.tied_u64_pairs(n, 3)
+        note(f"pairs tied u64/u32 n={n}")
+        ko, vo = gpu_pairs(torch_mod, bqs, k, v)
+        check_pairs(k, ko, vo, oracle.sort(k))
+        note(f"pairs tied u64/u64 n={n}")
+        ko, vo = gpu_pairs(torch_mod, bqs, k, v.astype(np.uint64))
+        check_pairs(k, ko, vo, oracle.sort(k))
+        a = W.few_distinct_i32(n, 5)
+        note(f"pairs i32/u32 few-distinct n={n}")
+        ko, vo = gpu_pairs(torch_mod, bqs, a, np.arange(n, dtype=np.uint32))
+        check_pairs(a, ko, vo, oracle.sort(a))
+        f = W.special_f64(n, 2)
+        note(f"pairs f64/u32 specials n={n}")
+        ko, vo = gpu_pairs(torch_mod, bqs, f, np.arange(n, dtype=np.uint32))
+        check_pairs(f, ko, vo, oracle.sort(f))
+
+
+def test_pairs_deterministic(torch_mod, bqs):
+    k, v = W.tied_u64_pairs(400_000, 8, distinct=16)
+    note("pairs determinism")
+    a = gpu_pairs(torch_mod, bqs, k, v)
+    b = gpu_pairs(torch_mod, bqs, k, v)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# -------------------------------------------------------------- segments --
+
+def gpu_segments(torch, bqs, keys, offsets, ctx=None):
+    t = to_dev(torch, keys)
+    o = torch.from_numpy(offsets).cuda()
+    (ctx or bqs.default_context()).sort_segments(t, o, key_type=_KT[keys.dtype])
+    torch.cuda.synchronize()
+    return from_dev(t, keys.dtype)
+
+
+def test_segments_log_uniform(torch_mod, bqs, oracle):
+    for k, hi in [(1, 10.0), (50, 14.0), (2000, 16.0)]:
+        keys, offsets = W.segmented_i32(k, k, 0.0, hi)
+        note(f"segments k={k} n={keys.size}")
+        assert_same_bits(gpu_segments(torch_mod, bqs, keys, offsets),
+                         oracle.sort_segments(keys, offsets))
+
+
+def test_segments_with_empty_and_single(torch_mod, bqs, oracle):
+    sizes = np.array([0, 1, 0, 2, 9000, 0, 1, 30_000, 3, 0], dtype=np.int64)
+    offsets = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    keys = W.uniform_i32(int(offsets[-1]), 1)
+    note("segments with empties")
+    assert_same_bits(gpu_segments(torch_mod, bqs, keys, offsets), oracle.sort_segments(keys, offsets))
+
+
+def test_segments_exhaustive_permutations(torch_mod, bqs, oracle):
+    """Every permutation of 8 keys (40,320 segments) in one call."""
+    import itertools
+
+    perms = np.array(list(itertools.permutations(range(8))), dtype=np.int32).reshape(-1)
+    offsets = np.arange(perms.size // 8 + 1, dtype=np.int64) * 8
+    note("segments all 8! permutations")
+    out = gpu_segments(torch_mod, bqs, perms, offsets)
+    assert np.array_equal(out, np.tile(np.arange(8, dtype=np.int32), perms.size // 8))
+    seqs = np.array(list(itertools.product(range(6), repeat=6)), dtype=np.int32).reshape(-1)
+    offs = np.arange(seqs.size // 6 + 1, dtype=np.int64) * 6
+    note("segments all 6^6 sequences")
+    assert_same_bits(gpu_segments(torch_mod, bqs, seqs, offs), oracle.sort_segments(seqs, offs))
+
+
+def test_segments_bad_offsets_reported(torch_mod, bqs):
+    keys = W.uniform_i32(1000, 0)
+    bad = np.array([0, 600, 500, 1000], dtype=np.int64)
+    note("segments bad offsets")
+    with pytest.raises(bqs.BqsError) as e:
+        gpu_segments(torch_mod, bqs, keys, bad)
+    assert e.value.status == 1
+
+
+# ------------------------------------------------------------- contract --
+
+def test_workspace_too_small_is_rejected(torch_mod, bqs):
+    import ctypes
+
+    t = to_dev(torch_mod, W.uniform_i32(100_000, 0))
+    ws = torch_mod.empty(1024, dtype=torch_mod.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    assert bqs.lib.bqs_ctx_create(ctypes.byref(h)) == 0
+    try:
+        assert bqs.lib.bqs_ctx_set_workspace(h, ctypes.c_void_p(ws.data_ptr()), 1024) == 0
+        assert bqs.lib.bqs_sort(ctypes.c_void_p(t.data_ptr()), t.numel(), bqs.I32, h) == 1
+    finally:
+        bqs.lib.bqs_ctx_destroy(h)
+
+
+def test_stats_account_for_every_key(torch_mod, bqs):
+    ctx = bqs.Context(timing=1)
+    for fam in ("uniform", "few_distinct", "all_equal"):
+        a = W.I32_FAMILIES[fam](1 << 20, 0)
+        note(f"stats {fam}")
+        gpu_sort(torch_mod, bqs, a, ctx)
+        s = ctx.stats()
+        # every key ends in exactly one small segment or one equal run,
+        # except single keys already in place
+        done = s["small_sorted_keys"] + s["filled_keys"]
+        assert 0.99 * a.size <= done <= a.size
+        assert s["levels"] == s["partition_launches"] >= 1
+        assert s["partition_ms"] > 0
+
+
+def test_full_size_2p28_uniform_properties(torch_mod, bqs):
+    """2^28 int32 keys at the benchmark's configuration: sorted, and the
+    same multiset as the input (compared through torch.sort of the input as
+    an independent library routine), plus sampled order statistics from
+    numpy's selection."""
+    torch = torch_mod
+    n = 1 << 28
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    note("2^28 uniform int32")
+    t = torch.randint(-(2**31), 2**31, (n,), dtype=torch.int32, device="cuda", generator=g)
+    ref = torch.sort(t).values
+    bqs.sort(t)
+    torch.cuda.synchronize()
+    assert bool((t[1:] >= t[:-1]).all())
+    assert bool(torch.equal(t, ref))
+    del ref
+    idx = np.random.default_rng(0).integers(0, n, size=16)
+    t.copy_(torch.randint(-(2**31), 2**31, (n,), dtype=torch.int32, device="cuda",
+                          generator=g.manual_seed(0)))
+    host = t.cpu().numpy()
+    bqs.sort(t)
+    torch.cuda.synchronize()
+    for i in idx[:4]:
+        assert int(t[int(i)]) == int(np.partition(host, int(i))[int(i)])
