@@ -1,0 +1,265 @@
+"""Benchmark of the block-partition sort on one MI355X.
+
+One step = one complete sort of a fresh copy of the workload (every
+partition pass, the small-segment sorts and the equal-key fills).  The
+headline workload is a single array of 2^28 uniform random int32 keys; the
+other single-array distributions of the same size class are reported in
+`distributions`.  Inputs are generated on the device (seeded) and are
+resident in HBM before the timed region starts: each step sorts its own
+pre-made copy, so no copy runs inside the timed region.
+
+Prints one JSON line (see the README of the repository for the fields).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+N_HEADLINE = 1 << 28
+PAPER_CPU_GKEYS = 1.0 / 45.0  # 45 ns per element at n = 2^28 (i5-2500K), context only
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=N_HEADLINE, help="keys of the headline workload")
+    ap.add_argument("--no-dists", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-log2", type=int, default=26, help="CPU sample: arrays of 2^x keys")
+    ap.add_argument("--cpu-arrays", type=int, default=2)
+    return ap.parse_args()
+
+
+def make_inputs(torch, kind: str, n: int, copies: int, seed: int):
+    """`copies` device arrays holding the same seeded input."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    dev = "cuda"
+    if kind == "i32_uniform":
+        src = torch.randint(-(2**31), 2**31, (n,), dtype=torch.int32, device=dev, generator=g)
+    elif kind == "i32_sorted":
+        src = torch.arange(n, dtype=torch.int32, device=dev)
+    elif kind == "i32_reverse":
+        src = torch.arange(n - 1, -1, -1, dtype=torch.int32, device=dev)
+    elif kind == "i32_few_distinct":
+        src = torch.randint(0, 1024, (n,), dtype=torch.int32, device=dev, generator=g)
+    elif kind == "i32_all_equal":
+        src = torch.full((n,), 0x2A, dtype=torch.int32, device=dev)
+    elif kind == "f64_uniform":
+        u = torch.randint(0, 2**53, (n,), dtype=torch.int64, device=dev, generator=g)
+        src = u.to(torch.float64) * (2.0 ** -53)
+    elif kind == "f64_normal":
+        src = torch.randn(n, dtype=torch.float64, device=dev, generator=g)
+    elif kind == "f64_sorted_swaps":
+        u = torch.randint(0, 2**53, (n,), dtype=torch.int64, device=dev, generator=g)
+        src = torch.sort(u.to(torch.float64) * (2.0 ** -53)).values
+        k = n // 100
+        # floor(n/100) swaps of disjoint, uniformly drawn index pairs
+        perm = torch.randperm(n, device=dev, generator=g)[: 2 * k]
+        i, j = perm[:k], perm[k:]
+        vi, vj = src[i].clone(), src[j].clone()
+        src[i] = vj
+        src[j] = vi
+    else:
+        raise ValueError(kind)
+    out = [src] + [src.clone() for _ in range(copies - 1)]
+    return out
+
+
+def make_pairs(torch, n: int, copies: int, seed: int):
+    """uint64 keys uniform over the full range (held in an int64 tensor),
+    uint32 payload = original index."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    hi = torch.randint(-(2**31), 2**31, (n,), dtype=torch.int64, device="cuda", generator=g)
+    lo = torch.randint(0, 2**32, (n,), dtype=torch.int64, device="cuda", generator=g)
+    k = (hi << 32) | lo
+    v = torch.arange(n, dtype=torch.int32, device="cuda")
+    return [(k.clone(), v.clone()) for _ in range(copies)]
+
+
+def run_workload(torch, bqs, ctx, kind, n, steps, warmup, seed=0):
+    """Times `steps` sorts; returns (ms_per_step, stats dict, per-level list)."""
+    pairs = kind == "pairs_u64_u32"
+    copies = steps + warmup
+    data = make_pairs(torch, n, copies, seed) if pairs else make_inputs(torch, kind, n, copies, seed)
+
+    def one(i):
+        if pairs:
+            ctx.sort_pairs(data[i][0], data[i][1], key_type="u64")
+        else:
+            ctx.sort(data[i])
+
+    for i in range(warmup):
+        one(i)
+    torch.cuda.synchronize()
+    part_ms, part_keys, levels = 0.0, 0, []
+    t0 = time.perf_counter()
+    for i in range(warmup, copies):
+        one(i)
+        st = ctx.stats()
+        part_ms += st["partition_ms"]
+        part_keys += st["partitioned_keys"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    levels = ctx.levels()
+    st = ctx.stats()
+    # correctness of the last step (cheap device-side checks)
+    last = data[-1][0] if pairs else data[-1]
+    if pairs:
+        kk = last
+        # order of the uint64 keys: compare as signed after flipping the sign bit
+        flipped = kk ^ torch.tensor(-(2**63), dtype=torch.int64, device="cuda")
+        ok = bool((flipped[1:] >= flipped[:-1]).all())
+    else:
+        ok = bool((last[1:] >= last[:-1]).all())
+    del data
+    torch.cuda.empty_cache()
+    ms = (t1 - t0) * 1e3 / steps
+    return ms, st, levels, part_ms / steps, part_keys / steps, ok
+
+
+def record_bytes(kind):
+    if kind.startswith("i32"):
+        return 4
+    if kind.startswith("f64"):
+        return 8
+    return 12  # u64 key + u32 payload
+
+
+def cpu_baseline(log2n: int, arrays: int):
+    import oracle
+    import workloads as W
+
+    orc = oracle.default()
+    n = 1 << log2n
+    total, keys = 0.0, 0
+    for s in range(arrays):
+        a = W.uniform_i32(n, 1000 + s)
+        t0 = time.perf_counter()
+        out = orc.sort(a)
+        total += time.perf_counter() - t0
+        keys += n
+        assert out[0] <= out[-1]
+    return {
+        "value": keys / total / 1e9,
+        "unit": "Gkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{arrays} arrays of 2^{log2n} uniform int32 keys (seeds {1000}..{1000 + arrays - 1}), "
+                  f"single-threaded BlockQuicksort oracle, {total:.1f} s",
+        "host": platform.processor() or platform.machine(),
+        "nproc": os.cpu_count(),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1604_06697_amd as bqs
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    ctx = bqs.Context(timing=1)
+
+    ms, st, levels, part_ms, part_keys, ok = run_workload(
+        torch, bqs, ctx, "i32_uniform", args.n, args.steps, args.warmup)
+    n = args.n
+    value = n / (ms * 1e-3) / 1e9
+    r = 4
+    # dominant kernel: the partition pass; algorithmic bytes = read + write of
+    # every key of every partitioned segment (2 * 4 B per key)
+    achieved = 2 * r * part_keys / (part_ms * 1e-3) / 1e9 if part_ms > 0 else None
+    launches = st["partition_launches"]
+    passes = [{"level": i, "keys": k, "ms": round(t, 4),
+               "GBps": round(2 * r * k / (t * 1e-3) / 1e9, 1) if t > 0 else None}
+              for i, (k, t) in enumerate(levels)]
+    alg_bytes = 2 * r * (st["partitioned_keys"] + st["small_sorted_keys"]) + r * st["filled_keys"]
+    out = {
+        "metric": "Gkeys/s and HBM GB/s fraction per distribution; batched p50/p99 latency",
+        "value": round(value, 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"single array of {n} uniform random int32 keys (full range), "
+                               "sorted ascending in place",
+                   "n": n, "distribution": "uniform", "seed": 0},
+        "correct": ok,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": None,
+            "kernel": "k_partition (int32 keys, 256 threads x 16 keys per tile)",
+            "bytes_per_launch": round(2 * r * part_keys / max(launches, 1)),
+            "avg_launch_ms": round(part_ms / max(launches, 1), 4),
+        },
+        "whole_sort": {
+            "algorithmic_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
+            "frac_of_hbm_peak": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "effective_passes": round(alg_bytes / (2 * r * n), 2),
+            "partition_ms": round(part_ms, 3),
+            "small_ms": round(st["small_ms"], 3),
+            "plan_ms": round(st["plan_ms"], 3),
+            "levels": st["levels"],
+        },
+        "passes": passes,
+        "paper_cpu_context_gkeys": round(PAPER_CPU_GKEYS, 4),
+    }
+
+    if not args.no_dists:
+        dists = {}
+        for kind, nn in [("i32_sorted", n), ("i32_reverse", n), ("i32_few_distinct", n),
+                         ("i32_all_equal", n), ("f64_uniform", n // 2), ("f64_normal", n // 2),
+                         ("f64_sorted_swaps", n // 2), ("pairs_u64_u32", n // 4)]:
+            dms, dst, _, dpart_ms, dpart_keys, dok = run_workload(
+                torch, bqs, ctx, kind, nn, max(2, args.steps // 2), 1, seed=1)
+            rb = record_bytes(kind)
+            ab = 2 * rb * (dst["partitioned_keys"] + dst["small_sorted_keys"]) + \
+                (rb if kind != "pairs_u64_u32" else 8) * dst["filled_keys"]
+            dists[kind] = {
+                "n": nn, "ms": round(dms, 3), "Gkeys/s": round(nn / (dms * 1e-3) / 1e9, 3),
+                "alg_GBps": round(ab / (dms * 1e-3) / 1e9, 1),
+                "frac": round(ab / (dms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "partition_GBps": round(2 * rb * dpart_keys / (dpart_ms * 1e-3) / 1e9, 1)
+                if dpart_ms > 0 else None,
+                "levels": dst["levels"], "correct": dok,
+            }
+        out["distributions"] = dists
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_log2, args.cpu_arrays)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

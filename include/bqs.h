@@ -114,6 +114,12 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param);
 /* Statistics of the most recent successful call on this context. */
 bqs_status bqs_ctx_get_stats(const bqs_ctx* ctx, bqs_stats* out);
 
+/* Per-level statistics of the most recent call: keys partitioned by level
+ * `level` (0-based) and, with BQS_PARAM_TIMING, that level's partition
+ * kernel time in ms.  Either output pointer may be NULL.  Returns
+ * BQS_EINVAL for a level the call did not run. */
+bqs_status bqs_ctx_get_level(const bqs_ctx* ctx, int level, int64_t* keys, double* partition_ms);
+
 /* Workspace needed to sort n_total keys of `key` type with `val_bytes`-byte
  * payloads (0 for keys only) split into k_segments segments (1 for a single
  * array), under the context's current parameters (ctx may be NULL for the

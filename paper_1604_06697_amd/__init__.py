@@ -54,7 +54,8 @@ for _name, _code in (("uint32", U32), ("uint64", U64)):
 
 EXPORTED = [
     "bqs_ctx_create", "bqs_ctx_destroy", "bqs_ctx_set_stream", "bqs_ctx_set_workspace",
-    "bqs_ctx_set_param", "bqs_ctx_get_param", "bqs_ctx_get_stats", "bqs_workspace_bytes",
+    "bqs_ctx_set_param", "bqs_ctx_get_param", "bqs_ctx_get_stats", "bqs_ctx_get_level",
+    "bqs_workspace_bytes",
     "bqs_sort", "bqs_sort_pairs", "bqs_sort_segments", "bqs_ctx_sync_status",
     "bqs_status_str", "bqs_version",
 ]
@@ -102,6 +103,8 @@ def _load(path: str = LIBRARY) -> ctypes.CDLL:
         "bqs_ctx_set_param": ([vp, ctypes.c_int, i64], st),
         "bqs_ctx_get_param": ([vp, ctypes.c_int], i64),
         "bqs_ctx_get_stats": ([vp, ctypes.POINTER(Stats)], st),
+        "bqs_ctx_get_level": ([vp, ctypes.c_int, ctypes.POINTER(i64),
+                               ctypes.POINTER(ctypes.c_double)], st),
         "bqs_workspace_bytes": ([vp, i64, ctypes.c_int, i32, i64], sz),
         "bqs_sort": ([vp, i64, ctypes.c_int, vp], st),
         "bqs_sort_pairs": ([vp, vp, i64, ctypes.c_int, i32, vp], st),
@@ -186,6 +189,14 @@ class Context:
         s = Stats()
         _check(lib.bqs_ctx_get_stats(self._h, ctypes.byref(s)), "bqs_ctx_get_stats")
         return s.as_dict()
+
+    def levels(self) -> list:
+        """[(keys partitioned, partition ms), ...] per level of the last call."""
+        out = []
+        keys, ms = ctypes.c_int64(), ctypes.c_double()
+        while lib.bqs_ctx_get_level(self._h, len(out), ctypes.byref(keys), ctypes.byref(ms)) == 0:
+            out.append((int(keys.value), float(ms.value)))
+        return out
 
     def workspace_bytes(self, n: int, dtype_c: int, val_bytes: int = 0, k: int = 1) -> int:
         return int(lib.bqs_workspace_bytes(self._h, int(n), dtype_c, int(val_bytes), int(k)))

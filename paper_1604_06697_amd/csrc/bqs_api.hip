@@ -15,6 +15,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "bqs.h"
 #include "bqs_internal.h"
@@ -177,7 +178,17 @@ struct bqs_ctx {
     bqs_stats stats{};
     bqs_status latched = BQS_OK;
     bqs::Ctl* pinned = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    // timing: event pairs recorded around launches, resolved at the next
+    // host synchronisation so that timing adds no wait of its own
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending {
+        hipEvent_t a, b;
+        int kind;   // 0 plan, 1 small, 2 partition
+        int level;
+    };
+    std::vector<Pending> pending;
+    std::vector<int64_t> level_keys;
+    std::vector<double> level_ms;
 };
 
 using namespace bqs;
@@ -221,10 +232,6 @@ bqs_status ensure_device_state(bqs_ctx* ctx) {
         if (hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return BQS_EHIP;
         ctx->pinned = static_cast<Ctl*>(p);
     }
-    if (!ctx->ev[0]) {
-        if (hipEventCreate(&ctx->ev[0]) != hipSuccess) return BQS_EHIP;
-        if (hipEventCreate(&ctx->ev[1]) != hipSuccess) return BQS_EHIP;
-    }
     return BQS_OK;
 }
 
@@ -235,19 +242,49 @@ bqs_status read_ctl(bqs_ctx* ctx, const Ctl* dev) {
     return hip_ok(hipStreamSynchronize(ctx->stream));
 }
 
+hipEvent_t take_event(bqs_ctx* ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
 struct Timer {
     bqs_ctx* ctx;
     bool on;
+    hipEvent_t a = nullptr;
     void start() {
-        if (on) hipEventRecord(ctx->ev[0], ctx->stream);
+        if (!on) return;
+        a = take_event(ctx);
+        if (a) hipEventRecord(a, ctx->stream);
     }
-    double stop() {
-        if (!on) return 0.0;
-        hipEventRecord(ctx->ev[1], ctx->stream);
-        hipEventSynchronize(ctx->ev[1]);
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]);
-        return ms;
+    void stop(int kind, int level) {
+        if (!on || !a) return;
+        hipEvent_t b = take_event(ctx);
+        if (!b) return;
+        hipEventRecord(b, ctx->stream);
+        ctx->pending.push_back({a, b, kind, level});
+        a = nullptr;
+    }
+    // after a stream synchronisation: all recorded events are complete
+    void resolve(bqs_stats& st) {
+        for (auto& p : ctx->pending) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, p.a, p.b);
+            if (p.kind == 0) st.plan_ms += ms;
+            else if (p.kind == 1) st.small_ms += ms;
+            else {
+                st.partition_ms += ms;
+                if (static_cast<size_t>(p.level) < ctx->level_ms.size()) ctx->level_ms[p.level] += ms;
+            }
+            ctx->ev_pool.push_back(p.a);
+            ctx->ev_pool.push_back(p.b);
+        }
+        ctx->pending.clear();
     }
 };
 
@@ -263,6 +300,7 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     if (st != BQS_OK) return st;
     const hipStream_t s = ctx->stream;
     Timer tm{ctx, ctx->timing != 0};
+    tm.resolve(ctx->stats);  // drop events a failed call may have left
     bqs_stats stats{};
     stats.tile_keys = o->tile_keys;
     stats.small_cutoff = a.small_cut;
@@ -276,6 +314,9 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
 
     const int64_t level_cap = 4 * static_cast<int64_t>(a.depth_limit) + 64;
     const int64_t tile_grid_cap = ctx->grid > 0 ? ctx->grid : 256 * 16;
+    ctx->level_keys.clear();
+    ctx->level_ms.clear();
+    uint64_t part_before = 0;
     for (int L = 0;; ++L) {
         a.level = L;
         const uint32_t nseg = static_cast<uint32_t>(cur.segs);
@@ -283,27 +324,33 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
         const uint32_t nchunk = static_cast<uint32_t>(cur.fills >> 32);
         tm.start();
         o->plan(a, clamp_grid(std::max<uint64_t>(nseg, nchunk), 8192), s);
-        stats.plan_ms += tm.stop();
+        tm.stop(0, L);
         if (cur.smalls) {
             tm.start();
             o->small(a, clamp_grid(cur.smalls, 8192), s);
-            stats.small_ms += tm.stop();
+            tm.stop(1, L);
             stats.small_launches++;
         }
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
         if (nseg == 0) break;
         if (L >= level_cap) return BQS_EOVERFLOW;
+        ctx->level_keys.push_back(0);
+        ctx->level_ms.push_back(0.0);
         tm.start();
         o->tile(a, clamp_grid(ntile, tile_grid_cap), s);
-        stats.partition_ms += tm.stop();
+        tm.stop(2, L);
         stats.partition_launches++;
         stats.levels++;
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
         if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+        tm.resolve(stats);
         if (ctx->pinned->error) return BQS_EOVERFLOW;
+        ctx->level_keys[L] = static_cast<int64_t>(ctx->pinned->part_keys - part_before);
+        part_before = ctx->pinned->part_keys;
         cur = ctx->pinned->lc[(L + 1) & 1];
     }
     if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+    tm.resolve(stats);
     if (ctx->pinned->error) return BQS_EOVERFLOW;
     stats.partitioned_keys = static_cast<int64_t>(ctx->pinned->part_keys);
     stats.small_sorted_keys = static_cast<int64_t>(ctx->pinned->small_keys);
@@ -373,7 +420,11 @@ bqs_status bqs_ctx_create(bqs_ctx** out) {
 void bqs_ctx_destroy(bqs_ctx* ctx) {
     if (!ctx) return;
     if (ctx->pinned) hipHostFree(ctx->pinned);
-    for (hipEvent_t e : ctx->ev)
+    for (auto& p : ctx->pending) {
+        ctx->ev_pool.push_back(p.a);
+        ctx->ev_pool.push_back(p.b);
+    }
+    for (hipEvent_t e : ctx->ev_pool)
         if (e) hipEventDestroy(e);
     delete ctx;
 }
@@ -428,6 +479,13 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
 bqs_status bqs_ctx_get_stats(const bqs_ctx* ctx, bqs_stats* out) {
     if (!ctx || !out) return BQS_EINVAL;
     *out = ctx->stats;
+    return BQS_OK;
+}
+
+bqs_status bqs_ctx_get_level(const bqs_ctx* ctx, int level, int64_t* keys, double* partition_ms) {
+    if (!ctx || level < 0 || static_cast<size_t>(level) >= ctx->level_keys.size()) return BQS_EINVAL;
+    if (keys) *keys = ctx->level_keys[level];
+    if (partition_ms) *partition_ms = ctx->level_ms[level];
     return BQS_OK;
 }
 

@@ -141,17 +141,17 @@ def normal_f64(n: int, seed: int) -> np.ndarray:
 
 
 def sorted_swaps_f64(n: int, seed: int, fraction: float = 0.01) -> np.ndarray:
-    """Sorted uniform [0,1) with floor(fraction*n) swaps of independent
-    uniformly drawn index pairs (i, j)."""
+    """Sorted uniform [0,1) with floor(fraction*n) swaps of disjoint,
+    uniformly drawn index pairs (the first 2k entries of a random
+    permutation give the k pairs)."""
     g = rng(seed)
     u = g.integers(0, 2**64, size=n, dtype=np.uint64)
     a = np.sort((u >> np.uint64(11)).astype(np.float64) * (2.0 ** -53))
     k = int(fraction * n)
     if n >= 2 and k:
-        i = g.integers(0, n, size=k)
-        j = g.integers(0, n, size=k)
-        for x, y in zip(i, j):  # sequential swaps, as defined
-            a[x], a[y] = a[y], a[x]
+        perm = g.permutation(n)[: 2 * k]
+        i, j = perm[:k], perm[k:]
+        a[i], a[j] = a[j].copy(), a[i].copy()
     return a
 
 
