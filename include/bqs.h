@@ -71,7 +71,8 @@ typedef enum {
                                    and last key (median-of-three, Section 2)                    */
     BQS_PARAM_TIMING = 4,       /* 1: time every partition / small-sort launch with HIP events */
     BQS_PARAM_TILE_EPT = 5,     /* keys per thread in a partition tile (8, 16 or 32; 0 = auto)  */
-    BQS_PARAM_GRID = 6          /* workgroups per launch of the persistent kernels (0 = auto)  */
+    BQS_PARAM_GRID = 6,         /* workgroups per launch of the persistent kernels (0 = auto)  */
+    BQS_PARAM_PROFILE = 7       /* 1: count cycles and look-back rounds inside partition tiles */
 } bqs_param;
 
 typedef struct {
@@ -87,6 +88,13 @@ typedef struct {
     double plan_ms;             /* summed pivot/fill kernel time (BQS_PARAM_TIMING only)        */
     int64_t tile_keys;          /* compiled tile size used (keys per tile)                      */
     int64_t small_cutoff;       /* small-sort cutoff used                                       */
+    /* BQS_PARAM_PROFILE only (sums over all partition tiles; cycles of the shader clock): */
+    int64_t prof_tiles;
+    int64_t prof_lookback_rounds;   /* 64-tile windows read by look-backs                          */
+    int64_t prof_lookback_polls;    /* status reads including re-polls of unpublished tiles        */
+    double prof_lookback_cycles;    /* wave 0 time from its scan result to the claimed range       */
+    double prof_tile_cycles;        /* tile start to tile end                                      */
+    double prof_load_cycles;        /* tile start to all keys loaded and counted                   */
 } bqs_stats;
 
 typedef struct bqs_ctx bqs_ctx; /* opaque, host-side */

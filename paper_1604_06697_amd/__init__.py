@@ -41,6 +41,7 @@ PARAM_PIVOT_MODE = 3
 PARAM_TIMING = 4
 PARAM_TILE_EPT = 5
 PARAM_GRID = 6
+PARAM_PROFILE = 7
 
 _TORCH_DTYPES = {
     torch.int32: I32,
@@ -81,6 +82,12 @@ class Stats(ctypes.Structure):
         ("plan_ms", ctypes.c_double),
         ("tile_keys", ctypes.c_int64),
         ("small_cutoff", ctypes.c_int64),
+        ("prof_tiles", ctypes.c_int64),
+        ("prof_lookback_rounds", ctypes.c_int64),
+        ("prof_lookback_polls", ctypes.c_int64),
+        ("prof_lookback_cycles", ctypes.c_double),
+        ("prof_tile_cycles", ctypes.c_double),
+        ("prof_load_cycles", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -177,6 +184,7 @@ class Context:
         "timing": PARAM_TIMING,
         "tile_ept": PARAM_TILE_EPT,
         "grid": PARAM_GRID,
+        "profile": PARAM_PROFILE,
     }
 
     def set_param(self, name: str, value: int):

@@ -30,12 +30,13 @@ __global__ void k_init_single(Args a) {
     for (int s = 0; s < 2; ++s) {
         c->lc[s].segs = 0;
         c->lc[s].fills = 0;
-        c->lc[s].smalls = 0;
+        for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
         c->lc[s].tile_next = 0;
         c->lc[s].pad = 0;
     }
     c->error = 0;
     c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
+    for (int i = 0; i < 8; ++i) c->prof[i] = 0;
     const int64_t n = a.n;
     if (n > a.small_cut) {
         const int64_t T = a.tile_keys;
@@ -48,8 +49,9 @@ __global__ void k_init_single(Args a) {
         a.segs[0][0] = d;
         c->lc[0].segs = (static_cast<unsigned long long>(nt) << 32) | 1ull;
     } else if (n >= 2) {
-        a.smalls[0][0] = SmallItem{0, n};
-        c->lc[0].smalls = 1;
+        const int cls = small_class(n);
+        a.smalls[0][static_cast<size_t>(cls) * a.cap_small] = SmallItem{0, n};
+        c->lc[0].smalls[cls] = 1;
     }
 }
 
@@ -59,12 +61,13 @@ __global__ void k_zero_ctl(Args a) {
     for (int s = 0; s < 2; ++s) {
         c->lc[s].segs = 0;
         c->lc[s].fills = 0;
-        c->lc[s].smalls = 0;
+        for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
         c->lc[s].tile_next = 0;
         c->lc[s].pad = 0;
     }
     c->error = 0;
     c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
+    for (int i = 0; i < 8; ++i) c->prof[i] = 0;
 }
 
 // One thread per segment: validate the offsets, then route the segment to
@@ -99,13 +102,46 @@ __global__ void k_init_segments(Args a) {
         d.nt = nt;
         a.segs[0][idx] = d;
     } else if (m >= 2) {
-        const uint32_t idx = atomicAdd(&c->lc[0].smalls, 1u);
+        const int cls = small_class(m);
+        const uint32_t idx = atomicAdd(&c->lc[0].smalls[cls], 1u);
         if (idx >= a.cap_small) {
             atomicOr(&c->error, ERR_OVERFLOW);
             return;
         }
-        a.smalls[0][idx] = SmallItem{lo, hi};
+        a.smalls[0][static_cast<size_t>(cls) * a.cap_small + idx] = SmallItem{lo, hi};
     }
+}
+
+// Map kernel, level L: one thread per tile finds the tile's segment (the
+// segment list is ordered by first tile) and writes the tile descriptor;
+// it also clears the tile's look-back status word.
+__global__ __launch_bounds__(256) void k_map(Args a) {
+    Ctl* c = a.ctl;
+    const int p = a.level & 1;
+    const unsigned long long sc = c->lc[p].segs;
+    const uint32_t nseg = static_cast<uint32_t>(sc);
+    const uint32_t ntile = static_cast<uint32_t>(sc >> 32);
+    const SegDesc* segs = a.segs[p];
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntile; t += gridDim.x * blockDim.x) {
+        uint32_t lo_i = 0, hi_i = nseg;
+        while (hi_i - lo_i > 1) {
+            const uint32_t mid = (lo_i + hi_i) >> 1;
+            if (segs[mid].t0 <= t) lo_i = mid; else hi_i = mid;
+        }
+        const SegDesc& sd = segs[lo_i];
+        TileDesc d;
+        d.lo = sd.lo;
+        d.hi = sd.hi;
+        d.pivot = sd.pivot;
+        d.t0 = sd.t0;
+        d.si = lo_i;
+        a.tile_desc[t] = d;
+        a.status[t] = 0;
+    }
+}
+
+void launch_map(const Args& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_map, dim3(grid), dim3(256), 0, s, a);
 }
 
 void launch_init_single(const Args& a, hipStream_t s) {
@@ -121,7 +157,7 @@ void launch_init_segments(const Args& a, hipStream_t s) {
 // -------------------------------------------------------------- layout ----
 
 struct Layout {
-    size_t ctl, yk, yv, side, segs[2], smalls[2], fills[2], tile_seg, status, total;
+    size_t ctl, yk, yv, side, segs[2], smalls[2], fills[2], tile_desc, status, total;
     uint64_t cap_seg, cap_tile, cap_small, cap_fill;
 };
 
@@ -145,9 +181,9 @@ static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T,
     L.yv = take(vb ? un * vb : 0);
     L.side = take(vb ? un * vb : 0);
     for (int s = 0; s < 2; ++s) L.segs[s] = take(L.cap_seg * sizeof(SegDesc));
-    for (int s = 0; s < 2; ++s) L.smalls[s] = take(L.cap_small * sizeof(SmallItem));
+    for (int s = 0; s < 2; ++s) L.smalls[s] = take(kSmallClasses * L.cap_small * sizeof(SmallItem));
     for (int s = 0; s < 2; ++s) L.fills[s] = take(L.cap_fill * sizeof(FillItem));
-    L.tile_seg = take(L.cap_tile * sizeof(uint32_t));
+    L.tile_desc = take(L.cap_tile * sizeof(TileDesc));
     L.status = take(L.cap_tile * sizeof(unsigned long long));
     L.total = off;
     return L;
@@ -175,6 +211,7 @@ struct bqs_ctx {
     int64_t timing = 0;
     int64_t ept = 0;
     int64_t grid = 0;
+    int64_t profile = 0;
     bqs_stats stats{};
     bqs_status latched = BQS_OK;
     bqs::Ctl* pinned = nullptr;
@@ -313,7 +350,6 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     LevelCtr cur = ctx->pinned->lc[0];
 
     const int64_t level_cap = 4 * static_cast<int64_t>(a.depth_limit) + 64;
-    const int64_t tile_grid_cap = ctx->grid > 0 ? ctx->grid : 256 * 16;
     ctx->level_keys.clear();
     ctx->level_ms.clear();
     uint64_t part_before = 0;
@@ -323,11 +359,16 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
         const uint32_t ntile = static_cast<uint32_t>(cur.segs >> 32);
         const uint32_t nchunk = static_cast<uint32_t>(cur.fills >> 32);
         tm.start();
-        o->plan(a, clamp_grid(std::max<uint64_t>(nseg, nchunk), 8192), s);
+        o->plan(a, clamp_grid(std::max<uint64_t>(nseg, nchunk), 2048), s);
+        if (nseg) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
         tm.stop(0, L);
-        if (cur.smalls) {
+        for (int cls = 0; cls < kSmallClasses; ++cls) {
+            const uint32_t cnt = cur.smalls[cls];
+            if (!cnt) continue;
+            if (!o->small[cls]) return BQS_EOVERFLOW;  // cannot happen: classes follow small_cut
+            const uint32_t per = static_cast<uint32_t>(o->small_per_block[cls]);
             tm.start();
-            o->small(a, clamp_grid(cur.smalls, 8192), s);
+            o->small[cls](a, clamp_grid((cnt + per - 1) / per, 16384), s);
             tm.stop(1, L);
             stats.small_launches++;
         }
@@ -337,7 +378,9 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
         ctx->level_keys.push_back(0);
         ctx->level_ms.push_back(0.0);
         tm.start();
-        o->tile(a, clamp_grid(ntile, tile_grid_cap), s);
+        // one workgroup per tile (tiles are still claimed in order through the
+        // level's ticket counter, which the look-back relies on)
+        o->tile(a, static_cast<int>(ntile), s);
         tm.stop(2, L);
         stats.partition_launches++;
         stats.levels++;
@@ -356,6 +399,12 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     stats.small_sorted_keys = static_cast<int64_t>(ctx->pinned->small_keys);
     stats.filled_keys = static_cast<int64_t>(ctx->pinned->fill_keys);
     stats.tiles = static_cast<int64_t>(ctx->pinned->tiles);
+    stats.prof_tiles = static_cast<int64_t>(ctx->pinned->prof[0]);
+    stats.prof_lookback_rounds = static_cast<int64_t>(ctx->pinned->prof[1]);
+    stats.prof_lookback_polls = static_cast<int64_t>(ctx->pinned->prof[2]);
+    stats.prof_lookback_cycles = static_cast<double>(ctx->pinned->prof[3]);
+    stats.prof_tile_cycles = static_cast<double>(ctx->pinned->prof[4]);
+    stats.prof_load_cycles = static_cast<double>(ctx->pinned->prof[5]);
     ctx->stats = stats;
     return BQS_OK;
 }
@@ -385,7 +434,7 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
         a.smalls[s] = reinterpret_cast<SmallItem*>(w + L.smalls[s]);
         a.fills[s] = reinterpret_cast<FillItem*>(w + L.fills[s]);
     }
-    a.tile_seg = reinterpret_cast<uint32_t*>(w + L.tile_seg);
+    a.tile_desc = reinterpret_cast<TileDesc*>(w + L.tile_desc);
     a.status = reinterpret_cast<unsigned long long*>(w + L.status);
     a.cap_seg = static_cast<uint32_t>(L.cap_seg);
     a.cap_tile = static_cast<uint32_t>(L.cap_tile);
@@ -399,6 +448,7 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.pivot_mode = static_cast<int>(ctx->pivot_mode);
     a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
     a.tile_keys = o->tile_keys;
+    a.prof = static_cast<int>(ctx->profile);
     return BQS_OK;
 }
 
@@ -458,6 +508,7 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             ctx->ept = value;
             break;
         case BQS_PARAM_GRID: ctx->grid = value; break;
+        case BQS_PARAM_PROFILE: ctx->profile = value ? 1 : 0; break;
         default: return BQS_EINVAL;
     }
     return BQS_OK;
@@ -472,6 +523,7 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_TIMING: return ctx->timing;
         case BQS_PARAM_TILE_EPT: return ctx->ept;
         case BQS_PARAM_GRID: return ctx->grid;
+        case BQS_PARAM_PROFILE: return ctx->profile;
         default: return -1;
     }
 }

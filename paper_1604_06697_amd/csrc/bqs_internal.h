@@ -22,6 +22,15 @@
 namespace bqs {
 
 constexpr int kFillChunk = 4096;  // keys per fill work unit
+constexpr int kSmallClasses = 8;  // small-sort size classes: padded size 64 << c
+
+// Size class of a small segment of m >= 1 keys: the smallest c with
+// m <= 64 << c.
+__host__ __device__ inline int small_class(int64_t m) {
+    int c = 0;
+    while ((int64_t(64) << c) < m) ++c;
+    return c;
+}
 constexpr int kMaxSample = 255;   // largest pivot sample
 
 struct SegDesc {
@@ -30,6 +39,15 @@ struct SegDesc {
     uint64_t pivot_raw;  // pivot as stored bits
     uint32_t t0, nt;     // tiles [t0, t0 + nt) of this level belong to the segment
     uint32_t depth, pad;
+};
+
+// Per-tile copy of what a partition tile needs, written by the map kernel so
+// that a tile reaches its segment with one load.
+struct TileDesc {
+    int64_t lo, hi;      // the tile's segment
+    uint64_t pivot;      // the segment's pivot as an order key
+    uint32_t t0;         // first tile of the segment
+    uint32_t si;         // segment index in the level's list
 };
 
 struct SmallItem {
@@ -49,9 +67,9 @@ struct FillItem {
 struct LevelCtr {
     unsigned long long segs;   // low 32 bits: segments, high 32 bits: tiles
     unsigned long long fills;  // low 32 bits: items, high 32 bits: work units
-    unsigned int smalls;
+    unsigned int smalls[kSmallClasses];  // small segments per size class
     unsigned int tile_next;    // tile claim counter of the level that consumes this slot
-    unsigned long long pad;
+    unsigned int pad;
 };
 
 enum : unsigned { ERR_OVERFLOW = 1u, ERR_OFFSETS = 2u };
@@ -64,6 +82,9 @@ struct Ctl {
     unsigned long long small_keys;
     unsigned long long fill_keys;
     unsigned long long tiles;
+    // profile counters (only with Args::prof): tiles, look-back rounds,
+    // look-back polls, look-back cycles, tile cycles, load+count cycles
+    unsigned long long prof[8];
 };
 
 struct Args {
@@ -74,9 +95,9 @@ struct Args {
     void* y_vals;
     void* side;
     SegDesc* segs[2];
-    SmallItem* smalls[2];
+    SmallItem* smalls[2];      // per slot: kSmallClasses regions of cap_small items
     FillItem* fills[2];
-    uint32_t* tile_seg;
+    TileDesc* tile_desc;
     unsigned long long* status;
     uint32_t cap_seg, cap_tile, cap_small, cap_fill;
     int64_t n;
@@ -88,13 +109,16 @@ struct Args {
     int pivot_mode;
     int depth_limit;
     int tile_keys;
+    int prof;
 };
 
 struct Ops {
     int tile_keys;  // keys per partition tile
     int small_max;  // capacity of the in-LDS small sort
     void (*plan)(const Args&, int grid, hipStream_t);
-    void (*small)(const Args&, int grid, hipStream_t);
+    void (*map)(const Args&, int grid, hipStream_t);
+    void (*small[kSmallClasses])(const Args&, int grid, hipStream_t);  // nullptr beyond small_max
+    int small_per_block[kSmallClasses];  // segments one workgroup sorts at once
     void (*tile)(const Args&, int grid, hipStream_t);
 };
 
@@ -106,5 +130,6 @@ const Ops* ops_pairs64(int dtype);
 // Dtype-independent set-up kernels (bqs_api.hip).
 void launch_init_single(const Args& a, hipStream_t s);
 void launch_init_segments(const Args& a, hipStream_t s);
+void launch_map(const Args& a, int grid, hipStream_t s);
 
 }  // namespace bqs

@@ -116,13 +116,22 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d) {
     return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
 }
 
-__device__ __forceinline__ uint64_t wave_inclusive_sum(uint64_t v) {
-    const int lane = lane_id();
+// `lane` is passed in so that callers inside loops can hand over an opaque
+// copy: otherwise the six lane >= d masks are hoisted out of the loop and
+// held in scalar registers across it.
+__device__ __forceinline__ uint64_t wave_inclusive_sum(uint64_t v, int lane) {
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const uint64_t t = shfl_up64(v, d);
         if (lane >= d) v += t;
     }
+    return v;
+}
+
+// Value the compiler cannot see through: keeps cheap per-lane compares
+// inside the loop instead of hoisting their masks into scalar registers.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
     return v;
 }
 
@@ -197,12 +206,13 @@ __device__ inline void push_segment(const Args& a, int slot, int64_t lo, int64_t
         a.segs[slot][idx] = d;
     } else {
         if (m == 1 && slot == 0) return;
-        const uint32_t idx = atomicAdd(&c->lc[slot].smalls, 1u);
+        const int cls = small_class(m);
+        const uint32_t idx = atomicAdd(&c->lc[slot].smalls[cls], 1u);
         if (idx >= a.cap_small) {
             atomicOr(&c->error, ERR_OVERFLOW);
             return;
         }
-        a.smalls[slot][idx] = SmallItem{lo, hi};
+        a.smalls[slot][static_cast<size_t>(cls) * a.cap_small + idx] = SmallItem{lo, hi};
     }
 }
 
@@ -236,8 +246,7 @@ __device__ inline void push_fill(const Args& a, int slot, int64_t dst, int64_t l
 //      the segment (Section 2: median of three, or of a larger sample).  The
 //      sample is stratified -- one key from each of k equal strata, at a
 //      hashed position inside the stratum -- so sorted, reversed and
-//      periodic inputs still yield central pivots.  The kernel then maps the
-//      segment's tiles and clears their status words.
+//      periodic inputs still yield central pivots.
 //  (2) Writes the equal-key runs recorded by level L-1 into X (keys: the
 //      pivot bits; pairs: the payloads parked in the side buffer).
 //  Block 0 also clears the counters of slot (L+1)&1, which the partition
@@ -258,11 +267,12 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
     if (blockIdx.x == 0 && tid == 0) {
         c->lc[q].segs = 0;
         c->lc[q].fills = 0;
-        c->lc[q].smalls = 0;
+        for (int k = 0; k < kSmallClasses; ++k) c->lc[q].smalls[k] = 0;
         c->lc[q].tile_next = 0;
     }
     const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
+    unsigned long long my_keys = 0, my_tiles = 0;  // statistics, one atomic per block
 
     for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
         SegDesc* sd = &a.segs[p][si];
@@ -312,15 +322,14 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
         if (tid == 0) {
             sd->pivot = static_cast<uint64_t>(K::ord(piv));
             sd->pivot_raw = static_cast<uint64_t>(piv);
-            atomicAdd(&c->part_keys, static_cast<unsigned long long>(m));
-            atomicAdd(&c->tiles, static_cast<unsigned long long>(sd->nt));
-        }
-        const uint32_t t0 = sd->t0, nt = sd->nt;
-        for (uint32_t t = tid; t < nt; t += NT) {
-            a.tile_seg[t0 + t] = si;
-            a.status[t0 + t] = 0;
+            my_keys += static_cast<unsigned long long>(m);
+            my_tiles += sd->nt;
         }
         __syncthreads();
+    }
+    if (tid == 0 && my_keys) {
+        atomicAdd(&c->part_keys, my_keys);
+        atomicAdd(&c->tiles, my_tiles);
     }
 
     // equal-key runs of the previous level
@@ -351,13 +360,18 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
 // ---------------------------------------------------------------------------
 // Partition kernel, level L: one tile of T = NT*EPT keys per iteration.
 // Tiles are claimed in order through an atomic counter, so every tile that
-// a look-back waits for is held by a running workgroup.
+// a look-back waits for is held by a running workgroup.  The next tile is
+// claimed, and its descriptor fetched, while the current one is processed.
 
-template <int DT, class V, int NT, int EPT>
+__device__ __forceinline__ uint64_t cycles() { return static_cast<uint64_t>(clock64()); }
+
+template <int DT, class V, int NT, int EPT, bool PERSIST>
 __global__ __launch_bounds__(NT) void k_partition(Args a) {
     using K = KeyT<DT>;
     using R = typename K::raw;
+    using O = decltype(K::ord(R()));
     using VS = typename ValStore<V>::type;
+    using Cls = typename std::conditional<(EPT <= 16), uint32_t, uint64_t>::type;
     constexpr bool HV = !std::is_same<V, NoVal>::value;
     constexpr int T = NT * EPT;
     constexpr int NW = NT / 64;
@@ -366,14 +380,22 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     static_assert(T < (1 << 21), "tile counts are packed in 21 bits");
     static_assert(EPT <= 32, "class codes are packed in 64 bits");
 
-    __shared__ R s_k[T];
-    __shared__ VS s_v[HV ? T : 1];
-    __shared__ uint64_t s_cnt[NE];
-    __shared__ uint64_t s_tot;
-    __shared__ uint32_t s_tile;
+    // per-(item, wave) counts: less | greater (| equal for pairs) packed in
+    // FW-bit fields; prefix sums stay below 2^FW
+    using Cnt = typename std::conditional<HV, uint64_t, uint32_t>::type;
+    constexpr int FW = HV ? 21 : 16;
+    constexpr Cnt FM = (Cnt(1) << FW) - 1;
+    static_assert(T < (1 << FW), "tile counts must fit their packed fields");
+
+    __shared__ R s_k[T + 64];
+    __shared__ VS s_v[HV ? T + 64 : 1];
+    __shared__ Cnt s_cnt[NE];
+    __shared__ Cnt s_tot;
+    __shared__ TileDesc s_desc[2];
+    __shared__ uint32_t s_next;
     __shared__ int64_t s_ex[2];
 
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid0 = threadIdx.x;
     Ctl* c = a.ctl;
     const int p = a.level & 1, q = p ^ 1;
     const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
@@ -382,63 +404,106 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     const VS* vsrc = static_cast<const VS*>(p ? a.y_vals : a.x_vals);
     VS* vdst = static_cast<VS*>(p ? a.x_vals : a.y_vals);
     VS* side = static_cast<VS*>(a.side);
-    const SegDesc* segs = a.segs[p];
+    // profile counters live in LDS so that they hold no registers across tiles:
+    // tiles, look-back rounds, polls, look-back cycles, tile cycles, load cycles
+    const bool prof = a.prof != 0;
+    __shared__ unsigned long long s_prof[6];
+    if (prof && tid0 < 6) s_prof[tid0] = 0;
 
-    for (;;) {
-        if (tid == 0) s_tile = atomicAdd(&c->lc[p].tile_next, 1u);
-        __syncthreads();
-        const uint32_t tile = s_tile;
-        if (tile >= ntiles) return;
-        const SegDesc sd = segs[a.tile_seg[tile]];
-        const uint32_t j = tile - sd.t0;
+    // the prefetching lane: lane 0 of the last wave
+    const bool pf = tid0 == NT - 64;
+    if (pf) {
+        const uint32_t t = atomicAdd(&c->lc[p].tile_next, 1u);
+        s_next = t;
+        if (t < ntiles) s_desc[0] = a.tile_desc[t];
+    }
+    __syncthreads();
+    uint32_t tile = s_next;
+    int buf = 0;
+
+    while (tile < ntiles) {
+        const uint64_t t_begin = prof ? cycles() : 0;
+        // opaque per-iteration copies: everything derived from the thread
+        // index is recomputed per tile instead of held in registers
+        const int tid = opaque(tid0);
+        const int lane = tid & 63;
+        const int wv = tid >> 6;
+        const TileDesc td = s_desc[buf];
+        uint32_t nxt = ntiles;
+        if constexpr (PERSIST) {
+            if (pf) nxt = atomicAdd(&c->lc[p].tile_next, 1u);
+        }
+        const uint32_t j = tile - td.t0;
         // tiles sit on multiples of T in the array, so full tiles are aligned
-        const int64_t tbase = (sd.lo / T + j) * static_cast<int64_t>(T);
-        const int64_t s = sd.lo > tbase ? sd.lo : tbase;
-        const int64_t e = sd.hi < tbase + T ? sd.hi : tbase + T;
-        const auto piv = static_cast<decltype(K::ord(R()))>(sd.pivot);
+        const int64_t tbase = (td.lo / T + j) * static_cast<int64_t>(T);
+        const int sl = td.lo > tbase ? static_cast<int>(td.lo - tbase) : 0;
+        const int el = td.hi < tbase + T ? static_cast<int>(td.hi - tbase) : T;
+        const bool full = sl == 0 && el == T;
+        const O piv = static_cast<O>(td.pivot);
+        const R* tsrc = src + tbase;
 
-        // scanning phase: coalesced loads, item i of thread tid is key tbase + i*NT + tid
+        // scanning phase: coalesced loads, item i of thread tid is key i*NT + tid
         R key[EPT];
         VS val[EPT];
+        if (full) {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int64_t pos = tbase + i * NT + tid;
-            const bool ok = pos >= s && pos < e;
-            key[i] = ok ? src[pos] : R(0);
-            if constexpr (HV) val[i] = ok ? vsrc[pos] : VS(0);
+            for (int i = 0; i < EPT; ++i) {
+                key[i] = tsrc[i * NT + tid];
+                if constexpr (HV) val[i] = vsrc[tbase + i * NT + tid];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) {
+                const int off = i * NT + tid;
+                const bool ok = off >= sl && off < el;
+                key[i] = ok ? tsrc[off] : R(0);
+                if constexpr (HV) val[i] = ok ? vsrc[tbase + off] : VS(0);
+            }
         }
-        uint64_t cls = 0;  // 2 bits per item: 0 none, 1 less, 2 greater, 3 equal
+        // class codes (2 bits per item: 0 none, 1 less, 2 greater, 3 equal)
+        // and the per-(item, wave) counts; lane i collects item i's counts so
+        // that one store per lane publishes them
+        Cls cls = 0;
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
-            const int64_t pos = tbase + i * NT + tid;
-            const bool ok = pos >= s && pos < e;
-            const auto o = K::ord(key[i]);
+            const bool ok = full || ((i * NT + tid) >= sl && (i * NT + tid) < el);
+            const O o = K::ord(key[i]);
             const bool lt = ok & (o < piv);
             const bool gt = ok & (o > piv);
-            const bool eq = ok & !lt & !gt;
             const uint64_t mlt = __ballot(lt), mgt = __ballot(gt);
-            const uint64_t meq = HV ? __ballot(eq) : 0ull;
-            if (lane == 0)
-                s_cnt[i * NW + wv] = static_cast<uint64_t>(__popcll(mlt)) |
-                                     (static_cast<uint64_t>(__popcll(mgt)) << 21) |
-                                     (static_cast<uint64_t>(__popcll(meq)) << 42);
-            const uint64_t code = lt ? 1ull : (gt ? 2ull : (eq ? 3ull : 0ull));
+            Cnt packed = static_cast<Cnt>(__popcll(mlt)) | (static_cast<Cnt>(__popcll(mgt)) << FW);
+            if constexpr (HV) {
+                const bool eq = ok & !lt & !gt;
+                packed |= static_cast<Cnt>(__popcll(__ballot(eq))) << (2 * FW);
+            }
+            if (lane == 0) s_cnt[i * NW + wv] = packed;
+            // 1 less, 2 greater, 3 equal, 0 outside the segment
+            const Cls code = static_cast<Cls>(static_cast<uint32_t>(ok) * 3u -
+                                              2u * static_cast<uint32_t>(lt) -
+                                              static_cast<uint32_t>(gt));
             cls |= code << (2 * i);
+            // keep one item's lane masks live at a time (they live in SGPRs)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        TileDesc nd;
+        if constexpr (PERSIST) {
+            if (pf && nxt < ntiles) nd = a.tile_desc[nxt];
         }
         __syncthreads();
+        const uint64_t t_loaded = prof ? cycles() : 0;
 
         // offsets: exclusive prefix over (item, wave) counts, by wave 0
         if (wv == 0) {
-            uint64_t loc[C];
-            uint64_t sum = 0;
+            Cnt loc[C];
+            Cnt sum = 0;
 #pragma unroll
             for (int cc = 0; cc < C; ++cc) {
                 const int idx = lane * C + cc;
-                loc[cc] = idx < NE ? s_cnt[idx] : 0ull;
+                loc[cc] = idx < NE ? s_cnt[idx] : Cnt(0);
                 sum += loc[cc];
             }
-            const uint64_t inc = wave_inclusive_sum(sum);
-            uint64_t run = inc - sum;
+            const Cnt inc = static_cast<Cnt>(wave_inclusive_sum(static_cast<uint64_t>(sum), lane));
+            Cnt run = inc - sum;
 #pragma unroll
             for (int cc = 0; cc < C; ++cc) {
                 const int idx = lane * C + cc;
@@ -448,29 +513,32 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
             if (lane == 63) s_tot = inc;
         }
         __syncthreads();
-        const uint64_t tot = s_tot;
-        const uint32_t nlt = static_cast<uint32_t>(tot & kM21);
-        const uint32_t ngt = static_cast<uint32_t>((tot >> 21) & kM21);
-        const uint32_t neq = static_cast<uint32_t>((tot >> 42) & kM21);
+        const Cnt tot = s_tot;
+        const uint32_t nlt = static_cast<uint32_t>(tot & FM);
+        const uint32_t ngt = static_cast<uint32_t>((tot >> FW) & FM);
+        const uint32_t neq = HV ? static_cast<uint32_t>((static_cast<uint64_t>(tot) >> (2 * FW)) & FM) : 0u;
 
         // wave 0 claims the output ranges (look-back) while the other waves
         // already stage their keys in LDS
         if (wv == 0) {
+            const uint64_t t_lb = prof ? cycles() : 0;
             uint64_t Lx = 0, Gx = 0;
             if (j == 0) {
                 if (lane == 0) st_status(&a.status[tile], st_pack(kStInc, nlt, ngt));
             } else {
                 if (lane == 0) st_status(&a.status[tile], st_pack(kStAgg, nlt, ngt));
                 int64_t pos = static_cast<int64_t>(tile) - 1;
-                const int64_t first = sd.t0;
+                const int64_t first = td.t0;
                 for (;;) {
                     const int64_t qq = pos - lane;
                     uint64_t st;
                     for (;;) {
                         st = qq >= first ? ld_status(&a.status[qq]) : st_pack(kStInc, 0, 0);
+                        if (prof && lane == 0) s_prof[2] += 1;
                         if (__ballot((st >> 62) == 0) == 0ull) break;
                         __builtin_amdgcn_s_sleep(1);
                     }
+                    if (prof && lane == 0) s_prof[1] += 1;
                     const uint64_t incm = __ballot((st >> 62) == kStInc);
                     const int lim = incm ? (__ffsll(static_cast<unsigned long long>(incm)) - 1) : 63;
                     const uint64_t l = lane <= lim ? ((st >> 31) & kM31) : 0ull;
@@ -486,157 +554,392 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
                 s_ex[0] = static_cast<int64_t>(Lx);
                 s_ex[1] = static_cast<int64_t>(Gx);
             }
+            if (prof && lane == 0) s_prof[3] += cycles() - t_lb;
         }
 
         // rearrangement, part 1: every key to its rank in LDS
-        // [less run | greater run | equal run (pairs only)]
+        // [less run | greater run | equal run (pairs only)]; keys that stay
+        // behind go to a per-lane spare slot, so the store needs no branch
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
-            const uint32_t cl = static_cast<uint32_t>((cls >> (2 * i)) & 3ull);
+            const uint32_t cl = static_cast<uint32_t>((cls >> (2 * i)) & Cls(3));
             const uint64_t mlt = __ballot(cl == 1), mgt = __ballot(cl == 2);
-            const uint64_t meq = HV ? __ballot(cl == 3) : 0ull;
-            const uint64_t base = s_cnt[i * NW + wv];
-            int d = -1;
-            if (cl == 1) d = static_cast<int>((base & kM21) + mbcnt(mlt));
-            else if (cl == 2) d = static_cast<int>(nlt + ((base >> 21) & kM21) + mbcnt(mgt));
-            else if (HV && cl == 3) d = static_cast<int>(nlt + ngt + ((base >> 42) & kM21) + mbcnt(meq));
-            if (d >= 0) {
-                s_k[d] = key[i];
-                if constexpr (HV) s_v[d] = val[i];
+            const Cnt base = s_cnt[i * NW + wv];
+            const int dl = static_cast<int>((base & FM) + mbcnt(mlt));
+            const int dg = static_cast<int>(nlt + ((base >> FW) & FM) + mbcnt(mgt));
+            int d = cl == 1 ? dl : (cl == 2 ? dg : T + lane);
+            if constexpr (HV) {
+                const uint64_t meq = __ballot(cl == 3);
+                const int de = static_cast<int>(nlt + ngt + ((static_cast<uint64_t>(base) >> (2 * FW)) & FM) +
+                                                mbcnt(meq));
+                d = cl == 3 ? de : d;
+                s_v[d] = val[i];
+            }
+            s_k[d] = key[i];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (PERSIST) {
+            if (pf) {
+                s_next = nxt;
+                if (nxt < ntiles) s_desc[buf ^ 1] = nd;
             }
         }
         __syncthreads();
 
         // rearrangement, part 2: coalesced copy of the runs to the other buffer
         const int64_t Lx = s_ex[0], Gx = s_ex[1];
-        if (Lx + nlt + Gx + ngt > sd.hi - sd.lo) {
+        if (Lx + nlt + Gx + ngt > td.hi - td.lo) {
             // inconsistent look-back result: report it and write nothing
             if (tid == 0) atomicOr(&c->error, ERR_OVERFLOW);
-            __syncthreads();
-            continue;
+        } else {
+            R* dl = dst + (td.lo + Lx);
+            R* dr = dst + (td.hi - Gx - ngt);
+            for (int t = tid; t < static_cast<int>(nlt); t += NT) dl[t] = s_k[t];
+            for (int t = tid; t < static_cast<int>(ngt); t += NT) dr[t] = s_k[nlt + t];
+            if constexpr (HV) {
+                VS* vl = vdst + (td.lo + Lx);
+                VS* vr = vdst + (td.hi - Gx - ngt);
+                for (int t = tid; t < static_cast<int>(nlt); t += NT) vl[t] = s_v[t];
+                for (int t = tid; t < static_cast<int>(ngt); t += NT) vr[t] = s_v[nlt + t];
+                const int64_t Ex = (tbase + sl - td.lo) - Lx - Gx;
+                VS* ve = side + (td.lo + Ex);
+                for (int t = tid; t < static_cast<int>(neq); t += NT) ve[t] = s_v[nlt + ngt + t];
+            }
+            // segment completion: the segment's last tile knows the totals
+            if (tbase + el == td.hi && tid == 0) {
+                const SegDesc& sd = a.segs[p][td.si];
+                const int64_t Lt = Lx + nlt, Gt = Gx + ngt;
+                const int64_t Et = (td.hi - td.lo) - Lt - Gt;
+                push_fill(a, q, td.lo + Lt, Et, td.lo, sd.pivot_raw);
+                push_segment(a, q, td.lo, td.lo + Lt, sd.depth + 1);
+                push_segment(a, q, td.hi - Gt, td.hi, sd.depth + 1);
+            }
         }
-        const int64_t left0 = sd.lo + Lx;
-        const int64_t right0 = sd.hi - Gx - ngt;
-        const int nmove = static_cast<int>(nlt + ngt);
-        for (int t = tid; t < nmove; t += NT) {
-            const int64_t d = t < static_cast<int>(nlt) ? left0 + t : right0 + (t - static_cast<int>(nlt));
-            dst[d] = s_k[t];
-            if constexpr (HV) vdst[d] = s_v[t];
+        if (prof && tid == 0) {
+            s_prof[0] += 1;
+            s_prof[5] += t_loaded - t_begin;
+            s_prof[4] += cycles() - t_begin;
         }
-        if constexpr (HV) {
-            const int64_t Ex = (s - sd.lo) - Lx - Gx;
-            for (int t = tid; t < static_cast<int>(neq); t += NT) side[sd.lo + Ex + t] = s_v[nmove + t];
-        }
-
-        // segment completion: the segment's last tile knows the totals
-        if (j + 1 == sd.nt && tid == 0) {
-            const int64_t Lt = Lx + nlt, Gt = Gx + ngt;
-            const int64_t Et = (sd.hi - sd.lo) - Lt - Gt;
-            push_fill(a, q, sd.lo + Lt, Et, sd.lo, sd.pivot_raw);
-            push_segment(a, q, sd.lo, sd.lo + Lt, sd.depth + 1);
-            push_segment(a, q, sd.hi - Gt, sd.hi, sd.depth + 1);
-        }
+        if constexpr (!PERSIST) break;
         __syncthreads();
+        tile = s_next;
+        buf ^= 1;
     }
+    if (prof && tid0 < 6) atomicAdd(&c->prof[tid0], s_prof[tid0]);
 }
 
 // ---------------------------------------------------------------------------
-// Small-segment sort (the paper's Insertionsort stage, Section 2): one
-// workgroup loads a whole segment of at most SMAX keys into LDS as order
-// keys, sorts it with a bitonic network, and writes it to X.  Pairs carry
-// the key's index in the segment as a tie-break (so the network is stable
-// and padding never displaces a real payload) and gather payloads from LDS.
+// Small-segment sort (the paper's Insertionsort stage, Section 2).
+//
+// A group of NTH threads (one wave, or a 256-thread workgroup) sorts one
+// segment of at most E*NTH keys with Batcher's bitonic network held in
+// registers: thread t keeps items t*E .. t*E+E-1.  A compare-exchange whose
+// two items differ in a register bit runs inside the thread, one that
+// differs in a lane bit exchanges through a lane shuffle, one that differs
+// in a wave bit exchanges through LDS.  Every merge of two sorted halves
+// starts with the mirror step (item x against x ^ (2^k - 1)), after which
+// all compare-exchanges put the smaller item at the lower index, so no
+// direction bit is needed.  Padding items are larger than any key; pairs
+// carry the key's index in the segment as a tie-break, which makes the
+// network stable and keeps padding behind real keys.
 
-template <int DT, class V, int NT, int SMAX>
-__global__ __launch_bounds__(NT) void k_small(Args a) {
+template <class O, bool HV>
+struct SItem;
+template <class O>
+struct SItem<O, false> {
+    O k;
+};
+template <class O>
+struct SItem<O, true> {
+    O k;
+    uint32_t i;
+};
+
+__device__ __forceinline__ uint32_t shfl_x(uint32_t v, int m) {
+    return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), m, 64));
+}
+__device__ __forceinline__ uint64_t shfl_x(uint64_t v, int m) { return shfl_xor64(v, m); }
+
+template <class O>
+__device__ __forceinline__ SItem<O, false> shfl_item(SItem<O, false> a, int m) {
+    a.k = shfl_x(a.k, m);
+    return a;
+}
+template <class O>
+__device__ __forceinline__ SItem<O, true> shfl_item(SItem<O, true> a, int m) {
+    a.k = shfl_x(a.k, m);
+    a.i = shfl_x(a.i, m);
+    return a;
+}
+
+template <class O>
+__device__ __forceinline__ bool item_less(const SItem<O, false>& a, const SItem<O, false>& b) {
+    return a.k < b.k;
+}
+template <class O>
+__device__ __forceinline__ bool item_less(const SItem<O, true>& a, const SItem<O, true>& b) {
+    return (a.k < b.k) | ((a.k == b.k) & (a.i < b.i));
+}
+
+// a <- smaller, b <- larger
+template <class It>
+__device__ __forceinline__ void cx(It& a, It& b) {
+    const bool s = item_less(b, a);
+    const It lo = s ? b : a;
+    const It hi = s ? a : b;
+    a = lo;
+    b = hi;
+}
+
+// v <- min(v, o) for the lower item of a pair, max(v, o) for the upper one
+template <class It>
+__device__ __forceinline__ void keep(It& v, const It& o, bool lower) {
+    const bool s = item_less(o, v);
+    v = (s == lower) ? o : v;
+}
+
+template <int E>
+struct Log2 {
+    static constexpr int value = 1 + Log2<E / 2>::value;
+};
+template <>
+struct Log2<1> {
+    static constexpr int value = 0;
+};
+
+// LDS slot of item x: one pad word per 32 (4-byte keys) or 16 (8-byte keys)
+// items keeps the blocked-layout accesses free of bank conflicts.
+template <class O>
+__device__ __forceinline__ int lds_slot(int x) {
+    return sizeof(O) == 4 ? x + (x >> 5) : x + (x >> 4);
+}
+
+// In-thread stages: register bit j (xor) and the mirror step of merge k.
+template <class It, int E>
+__device__ __forceinline__ void reg_xor(It (&v)[E], int j) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int pr = r ^ (1 << j);
+        if (pr > r && pr < E) cx(v[r], v[pr]);
+    }
+}
+template <class It, int E>
+__device__ __forceinline__ void reg_mirror(It (&v)[E], int k) {
+    const int m = (1 << k) - 1;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int pr = r ^ m;
+        if (pr > r && pr < E) cx(v[r], v[pr]);
+    }
+}
+
+// Exchange with the item whose index is x ^ pmask through LDS (pmask has its
+// highest bit at `hb`); all NTH threads of the group take part.
+template <class It, class O, int E, int NTH>
+__device__ __forceinline__ void lds_stage(It (&v)[E], int t, O* sk, uint32_t* si, int pmask, int hb) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = t * E + r;
+        sk[lds_slot<O>(x)] = v[r].k;
+        if constexpr (sizeof(It) > sizeof(O)) si[lds_slot<O>(x)] = v[r].i;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = t * E + r;
+        const int y = x ^ pmask;
+        It o;
+        o.k = sk[lds_slot<O>(y)];
+        if constexpr (sizeof(It) > sizeof(O)) o.i = si[lds_slot<O>(y)];
+        keep(v[r], o, ((x >> hb) & 1) == 0);
+    }
+}
+
+template <class It, class O, int E, int NTH>
+__device__ void bitonic_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
+    constexpr int LE = Log2<E>::value;
+    constexpr int LP = LE + Log2<NTH>::value;
+    const int lane = t & 63;
+#pragma unroll 1
+    for (int k = 1; k <= LP; ++k) {
+        const int b = k - 1;
+        // mirror step of the merge of blocks of 2^k items
+        if (b < LE) {
+            switch (k) {
+                case 1: if constexpr (LE >= 1) reg_mirror(v, 1); break;
+                case 2: if constexpr (LE >= 2) reg_mirror(v, 2); break;
+                case 3: if constexpr (LE >= 3) reg_mirror(v, 3); break;
+                case 4: if constexpr (LE >= 4) reg_mirror(v, 4); break;
+                case 5: if constexpr (LE >= 5) reg_mirror(v, 5); break;
+                default: break;
+            }
+        } else if (b < LE + 6) {
+            const int m = (1 << (k - LE)) - 1;
+            const bool lower = ((lane >> (b - LE)) & 1) == 0;
+            It o[E];
+#pragma unroll
+            for (int r = 0; r < E; ++r) o[r] = shfl_item(v[E - 1 - r], m);
+#pragma unroll
+            for (int r = 0; r < E; ++r) keep(v[r], o[r], lower);
+        } else {
+            lds_stage<It, O, E, NTH>(v, t, sk, si, (1 << k) - 1, b);
+        }
+        // half-cleaners
+#pragma unroll 1
+        for (int j = k - 2; j >= 0; --j) {
+            if (j < LE) {
+                switch (j) {
+                    case 0: reg_xor(v, 0); break;
+                    case 1: if constexpr (LE >= 2) reg_xor(v, 1); break;
+                    case 2: if constexpr (LE >= 3) reg_xor(v, 2); break;
+                    case 3: if constexpr (LE >= 4) reg_xor(v, 3); break;
+                    case 4: if constexpr (LE >= 5) reg_xor(v, 4); break;
+                    default: break;
+                }
+            } else if (j < LE + 6) {
+                const int m = 1 << (j - LE);
+                const bool lower = (lane & m) == 0;
+#pragma unroll
+                for (int r = 0; r < E; ++r) keep(v[r], shfl_item(v[r], m), lower);
+            } else {
+                lds_stage<It, O, E, NTH>(v, t, sk, si, 1 << j, j);
+            }
+        }
+    }
+}
+
+// One launch sorts the segments of one size class: a workgroup of 256
+// threads holds 256/NTH groups, each group sorts one segment of at most
+// E*NTH keys.
+template <int DT, class V, int E, int NTH>
+__global__ __launch_bounds__(256) void k_small(Args a, int cls) {
     using K = KeyT<DT>;
     using R = typename K::raw;
+    using O = decltype(K::ord(R()));
     using VS = typename ValStore<V>::type;
     constexpr bool HV = !std::is_same<V, NoVal>::value;
-    __shared__ R s_o[SMAX];
-    __shared__ uint32_t s_i[HV ? SMAX : 1];
-    __shared__ VS s_v[HV ? SMAX : 1];
+    using It = SItem<O, HV>;
+    constexpr int G = 256 / NTH;     // groups per workgroup
+    constexpr int P = E * NTH;       // items per group
+    constexpr int PS = P + P / 16;   // padded LDS items per group (covers both pad rules)
+    __shared__ O s_k[G * PS];
+    __shared__ uint32_t s_i[HV ? G * PS : 1];
+    __shared__ VS s_v[HV ? G * P : 1];
 
     Ctl* c = a.ctl;
     const int p = a.level & 1;
     const int tid = threadIdx.x;
-    const uint32_t nsm = c->lc[p].smalls;
+    const int grp = tid / NTH;
+    const int t = tid % NTH;
+    const uint32_t nsm = c->lc[p].smalls[cls];
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
     R* xk = static_cast<R*>(a.x_keys);
     const VS* vsrc = static_cast<const VS*>(p ? a.y_vals : a.x_vals);
     VS* xv = static_cast<VS*>(a.x_vals);
+    const SmallItem* items = a.smalls[p] + static_cast<size_t>(cls) * a.cap_small;
+    O* sk = s_k + grp * PS;
+    uint32_t* si = HV ? s_i + grp * PS : s_i;
+    VS* sv = HV ? s_v + grp * P : s_v;
 
-    for (uint32_t it = blockIdx.x; it < nsm; it += gridDim.x) {
-        const SmallItem si = a.smalls[p][it];
-        const int m = static_cast<int>(si.hi - si.lo);
-        int P = 1;
-        while (P < m) P <<= 1;
-        for (int t = tid; t < P; t += NT) {
-            if (t < m) {
-                s_o[t] = K::ord(src[si.lo + t]);
-                if constexpr (HV) s_v[t] = vsrc[si.lo + t];
-            } else {
-                s_o[t] = static_cast<R>(~R(0));
+    for (uint32_t base = blockIdx.x * G; base < nsm; base += gridDim.x * G) {
+        const uint32_t it = base + grp;
+        const bool have = it < nsm;
+        int64_t lo = 0;
+        int m = 0;
+        if (have) {
+            const SmallItem s = items[it];
+            lo = s.lo;
+            m = static_cast<int>(s.hi - s.lo);
+        }
+        // striped (coalesced) load into LDS, padding with the largest key
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = r * NTH + t;
+            O key = static_cast<O>(~O(0));
+            if (x < m) {
+                key = K::ord(src[lo + x]);
+                if constexpr (HV) sv[x] = vsrc[lo + x];
             }
-            if constexpr (HV) s_i[t] = static_cast<uint32_t>(t);
+            sk[lds_slot<O>(x)] = key;
+            if constexpr (HV) si[lds_slot<O>(x)] = static_cast<uint32_t>(x);
         }
         __syncthreads();
-        for (int kk = 2; kk <= P; kk <<= 1) {
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int t = tid; t < (P >> 1); t += NT) {
-                    const int i = 2 * t - (t & (jj - 1));
-                    const int l = i + jj;
-                    const bool up = (i & kk) == 0;
-                    const R oa = s_o[i], ob = s_o[l];
-                    bool gt;
-                    if constexpr (HV) {
-                        const uint32_t ia = s_i[i], ib = s_i[l];
-                        gt = (oa > ob) | ((oa == ob) & (ia > ib));
-                        if (gt == up) {
-                            s_o[i] = ob;
-                            s_o[l] = oa;
-                            s_i[i] = ib;
-                            s_i[l] = ia;
-                        }
-                    } else {
-                        gt = oa > ob;
-                        if (gt == up) {
-                            s_o[i] = ob;
-                            s_o[l] = oa;
-                        }
-                    }
-                }
-                __syncthreads();
+        It v[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = t * E + r;
+            v[r].k = sk[lds_slot<O>(x)];
+            if constexpr (HV) v[r].i = si[lds_slot<O>(x)];
+        }
+        bitonic_sort<It, O, E, NTH>(v, t, sk, si);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = t * E + r;
+            sk[lds_slot<O>(x)] = v[r].k;
+            if constexpr (HV) si[lds_slot<O>(x)] = v[r].i;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = r * NTH + t;
+            if (x < m) {
+                xk[lo + x] = K::inv(sk[lds_slot<O>(x)]);
+                if constexpr (HV) xv[lo + x] = sv[si[lds_slot<O>(x)]];
             }
         }
-        for (int t = tid; t < m; t += NT) {
-            xk[si.lo + t] = K::inv(s_o[t]);
-            if constexpr (HV) xv[si.lo + t] = s_v[s_i[t]];
-        }
-        if (tid == 0) atomicAdd(&c->small_keys, static_cast<unsigned long long>(m));
+        if (t == 0 && have) atomicAdd(&c->small_keys, static_cast<unsigned long long>(m));
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Host-side launchers for one (dtype, payload, tile shape).
+// Host-side launchers for one (dtype, payload, tile shape).  SMAX is the
+// largest small segment (a power of two between 64 and 8192).
+
+template <int DT, class V, int E, int NTH>
+struct SmallLaunch {
+    static void run(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_small<DT, V, E, NTH>), dim3(grid), dim3(256), 0, s, a,
+                           small_class(static_cast<int64_t>(E) * NTH));
+    }
+};
+
+// function pointer of a small-sort class, or nullptr without instantiating it
+template <int DT, class V, int E, int NTH, bool ON>
+struct SmallFn {
+    static constexpr void (*get())(const Args&, int, hipStream_t) { return &SmallLaunch<DT, V, E, NTH>::run; }
+};
+template <int DT, class V, int E, int NTH>
+struct SmallFn<DT, V, E, NTH, false> {
+    static constexpr void (*get())(const Args&, int, hipStream_t) { return nullptr; }
+};
 
 template <int DT, class V, int NT, int EPT, int SMAX>
 struct Launch {
     static constexpr int kPlanThreads = 256;
-    static constexpr int kSmallThreads = 256;
     static void plan(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_plan<DT, V, kPlanThreads>), dim3(grid), dim3(kPlanThreads), 0, s, a);
     }
-    static void small(const Args& a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_small<DT, V, kSmallThreads, SMAX>), dim3(grid), dim3(kSmallThreads), 0,
-                           s, a);
-    }
     static void tile(const Args& a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_partition<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_partition<DT, V, NT, EPT, false>), dim3(grid), dim3(NT), 0, s, a);
     }
+    static void map(const Args& a, int grid, hipStream_t s) { launch_map(a, grid, s); }
     static const Ops* ops() {
-        static const Ops o{NT * EPT, SMAX, &plan, &small, &tile};
+        static const Ops o{
+            NT * EPT,
+            SMAX,
+            &plan,
+            &map,
+            {&SmallLaunch<DT, V, 1, 64>::run, &SmallLaunch<DT, V, 2, 64>::run,
+             &SmallLaunch<DT, V, 4, 64>::run, &SmallLaunch<DT, V, 8, 64>::run,
+             SmallFn<DT, V, 16, 64, (SMAX >= 1024)>::get(),
+             SmallFn<DT, V, 8, 256, (SMAX >= 2048)>::get(),
+             SmallFn<DT, V, 16, 256, (SMAX >= 4096)>::get(),
+             SmallFn<DT, V, 32, 256, (SMAX >= 8192)>::get()},
+            {4, 4, 4, 4, 4, 1, 1, 1},
+            &tile};
         return &o;
     }
 };

@@ -13,8 +13,8 @@ template <int DT>
 const Ops* four_byte(int ept) {
     switch (ept) {
         case 8: return Keys4<DT, 8>::ops();
-        case 32: return Keys4<DT, 32>::ops();
-        default: return Keys4<DT, 16>::ops();
+        case 16: return Keys4<DT, 16>::ops();
+        default: return Keys4<DT, 32>::ops();
     }
 }
 }  // namespace
@@ -22,8 +22,8 @@ const Ops* four_byte(int ept) {
 const Ops* ops_keys(int dtype, int ept) {
     switch (dtype) {
         case BQS_I32: return four_byte<BQS_I32>(ept);
-        case BQS_U32: return Keys4<BQS_U32, 16>::ops();
-        case BQS_F32: return Keys4<BQS_F32, 16>::ops();
+        case BQS_U32: return Keys4<BQS_U32, 32>::ops();
+        case BQS_F32: return Keys4<BQS_F32, 32>::ops();
         case BQS_I64: return Keys8<BQS_I64>::ops();
         case BQS_U64: return Keys8<BQS_U64>::ops();
         case BQS_F64: return Keys8<BQS_F64>::ops();
