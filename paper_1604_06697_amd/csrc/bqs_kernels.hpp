@@ -655,10 +655,25 @@ struct SItem<O, true> {
     uint32_t i;
 };
 
+// Value of lane (lane ^ m).  Masks with a DPP form stay in the vector ALU
+// (quad permutes for 1, 2, 3; row half-mirror for 7; row mirror for 15);
+// the others go through the LDS crossbar (ds_bpermute).
 __device__ __forceinline__ uint32_t shfl_x(uint32_t v, int m) {
-    return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), m, 64));
+    const int x = static_cast<int>(v);
+    switch (m) {
+        case 1: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true));
+        case 2: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true));
+        case 3: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, true));
+        case 7: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true));
+        case 15: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true));
+        default: return static_cast<uint32_t>(__shfl_xor(x, m, 64));
+    }
 }
-__device__ __forceinline__ uint64_t shfl_x(uint64_t v, int m) { return shfl_xor64(v, m); }
+__device__ __forceinline__ uint64_t shfl_x(uint64_t v, int m) {
+    const uint32_t lo = shfl_x(static_cast<uint32_t>(v), m);
+    const uint32_t hi = shfl_x(static_cast<uint32_t>(v >> 32), m);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
 
 template <class O>
 __device__ __forceinline__ SItem<O, false> shfl_item(SItem<O, false> a, int m) {
@@ -777,11 +792,17 @@ __device__ void bitonic_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
         } else if (b < LE + 6) {
             const int m = (1 << (k - LE)) - 1;
             const bool lower = ((lane >> (b - LE)) & 1) == 0;
-            It o[E];
+            // registers r and E-1-r trade with each other's partner: fetch
+            // both before either changes
 #pragma unroll
-            for (int r = 0; r < E; ++r) o[r] = shfl_item(v[E - 1 - r], m);
-#pragma unroll
-            for (int r = 0; r < E; ++r) keep(v[r], o[r], lower);
+            for (int r = 0; r < (E + 1) / 2; ++r) {
+                const It o1 = shfl_item(v[E - 1 - r], m);
+                if (E - 1 - r != r) {
+                    const It o2 = shfl_item(v[r], m);
+                    keep(v[E - 1 - r], o2, lower);
+                }
+                keep(v[r], o1, lower);
+            }
         } else {
             lds_stage<It, O, E, NTH>(v, t, sk, si, (1 << k) - 1, b);
         }
