@@ -72,8 +72,17 @@ typedef enum {
     BQS_PARAM_TIMING = 4,       /* 1: time every partition / small-sort launch with HIP events */
     BQS_PARAM_TILE_EPT = 5,     /* keys per thread in a partition tile (8, 16 or 32; 0 = auto)  */
     BQS_PARAM_GRID = 6,         /* workgroups per launch of the persistent kernels (0 = auto)  */
-    BQS_PARAM_PROFILE = 7       /* 1: count cycles and look-back rounds inside partition tiles */
+    BQS_PARAM_PROFILE = 7,      /* 1: count cycles and look-back rounds inside partition tiles */
+    BQS_PARAM_MODE = 8          /* BQS_MODE_LEVELS (default) or BQS_MODE_QUEUE                  */
 } bqs_param;
+
+/* Execution modes (BQS_PARAM_MODE).
+ *   LEVELS: one partition launch per recursion level; the host reads the
+ *           next level's size between levels (per-level statistics).
+ *   QUEUE : the recursion as a device-resident work queue drained by one
+ *           persistent kernel.  Closed: selecting it returns BQS_EINVAL (its
+ *           kernel faulted on the device and the cause is not yet known). */
+typedef enum { BQS_MODE_LEVELS = 0, BQS_MODE_QUEUE = 1 } bqs_mode;
 
 typedef struct {
     int64_t levels;             /* partition passes executed by the last call                  */

@@ -42,6 +42,8 @@ PARAM_TIMING = 4
 PARAM_TILE_EPT = 5
 PARAM_GRID = 6
 PARAM_PROFILE = 7
+PARAM_MODE = 8
+MODE_LEVELS, MODE_QUEUE = 0, 1
 
 _TORCH_DTYPES = {
     torch.int32: I32,
@@ -185,6 +187,7 @@ class Context:
         "tile_ept": PARAM_TILE_EPT,
         "grid": PARAM_GRID,
         "profile": PARAM_PROFILE,
+        "mode": PARAM_MODE,
     }
 
     def set_param(self, name: str, value: int):

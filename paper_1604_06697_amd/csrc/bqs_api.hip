@@ -140,6 +140,60 @@ __global__ __launch_bounds__(256) void k_map(Args a) {
     }
 }
 
+// Clears the queue state (flags, status pool, counters).
+__global__ void k_qclear(Args a) {
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (uint64_t i = i0; i < a.cap_qitem; i += stride) a.qpub[i] = 0u;
+    for (uint64_t i = i0; i < a.cap_qstatus; i += stride) a.qstatus[i] = 0ull;
+    if (i0 == 0) {
+        QCtl* q = a.qctl;
+        q->head = q->tail = q->outstanding = q->status_next = 0;
+        q->segs = 0;
+        q->small_raw = 0;
+        for (int k = 0; k < kSmallClasses; ++k) q->small_cursor[k] = 0;
+        Ctl* c = a.ctl;
+        for (int s = 0; s < 2; ++s) {
+            c->lc[s].segs = 0;
+            c->lc[s].fills = 0;
+            for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
+            c->lc[s].tile_next = 0;
+        }
+        c->error = 0;
+        c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
+        for (int k = 0; k < 8; ++k) c->prof[k] = 0;
+    }
+}
+
+// Packs the small segments of the work-queue run by size class: class c
+// occupies [sum of the counts of classes < c, + count of c) of smalls[0].
+__global__ void k_qbin(Args a) {
+    const Ctl* c = a.ctl;
+    QCtl* q = a.qctl;
+    uint32_t first[kSmallClasses];
+    uint32_t run = 0;
+    for (int k = 0; k < kSmallClasses; ++k) {
+        first[k] = run;
+        run += c->lc[0].smalls[k];
+    }
+    const uint32_t n = q->small_raw < a.cap_small ? q->small_raw : a.cap_small;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const SmallItem s = a.smalls[1][i];
+        const int64_t hi = s.hi & ((int64_t(1) << 62) - 1);
+        const int cls = small_class(hi - s.lo);
+        const uint32_t at = atomicAdd(&q->small_cursor[cls], 1u);
+        a.smalls[0][first[cls] + at] = s;
+    }
+}
+
+void launch_qclear(const Args& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_qclear, dim3(1024), dim3(256), 0, s, a);
+}
+
+void launch_qbin(const Args& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_qbin, dim3(256), dim3(256), 0, s, a);
+}
+
 void launch_map(const Args& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_map, dim3(grid), dim3(256), 0, s, a);
 }
@@ -158,18 +212,21 @@ void launch_init_segments(const Args& a, hipStream_t s) {
 
 struct Layout {
     size_t ctl, yk, yv, side, segs[2], smalls[2], fills[2], tile_desc, status, total;
+    size_t qctl, qsegs, qitems, qpub, qstatus;
     uint64_t cap_seg, cap_tile, cap_small, cap_fill;
+    uint64_t cap_qseg, cap_qitem, cap_qstatus;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S) {
+// Workspace layout.  Level mode keeps per-level lists (two slots); work-queue
+// mode keeps whole-sort lists whose capacities allow 16 partition passes
+// worth of segments and tiles (beyond that the run reports BQS_EOVERFLOW).
+static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S, bool queue) {
     Layout L{};
     const uint64_t un = static_cast<uint64_t>(n);
-    L.cap_seg = un / static_cast<uint64_t>(S + 1) + 1;
-    L.cap_tile = un / static_cast<uint64_t>(T) + 2 * L.cap_seg + 2;
-    L.cap_small = 2 * L.cap_seg + static_cast<uint64_t>(k) + 2;
-    L.cap_fill = L.cap_seg + 1;
+    const uint64_t uk = static_cast<uint64_t>(k);
+    const uint64_t per_level_segs = un / static_cast<uint64_t>(S + 1) + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -180,11 +237,28 @@ static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T,
     L.yk = take(un * kb);
     L.yv = take(vb ? un * vb : 0);
     L.side = take(vb ? un * vb : 0);
-    for (int s = 0; s < 2; ++s) L.segs[s] = take(L.cap_seg * sizeof(SegDesc));
-    for (int s = 0; s < 2; ++s) L.smalls[s] = take(kSmallClasses * L.cap_small * sizeof(SmallItem));
-    for (int s = 0; s < 2; ++s) L.fills[s] = take(L.cap_fill * sizeof(FillItem));
-    L.tile_desc = take(L.cap_tile * sizeof(TileDesc));
-    L.status = take(L.cap_tile * sizeof(unsigned long long));
+    if (!queue) {
+        L.cap_seg = per_level_segs;
+        L.cap_tile = un / static_cast<uint64_t>(T) + 2 * L.cap_seg + 2;
+        L.cap_small = 2 * L.cap_seg + uk + 2;
+        L.cap_fill = L.cap_seg + 1;
+        for (int s = 0; s < 2; ++s) L.segs[s] = take(L.cap_seg * sizeof(SegDesc));
+        for (int s = 0; s < 2; ++s) L.smalls[s] = take(kSmallClasses * L.cap_small * sizeof(SmallItem));
+        for (int s = 0; s < 2; ++s) L.fills[s] = take(L.cap_fill * sizeof(FillItem));
+        L.tile_desc = take(L.cap_tile * sizeof(TileDesc));
+        L.status = take(L.cap_tile * sizeof(unsigned long long));
+    } else {
+        L.cap_qseg = 16 * per_level_segs + uk + 1024;
+        L.cap_qstatus = 16 * (un / static_cast<uint64_t>(T)) + 2 * L.cap_qseg + 4096;
+        L.cap_qitem = L.cap_qstatus + un / kFillChunk + L.cap_qseg + 4096;
+        L.cap_small = 2 * L.cap_qseg + uk + 16;
+        L.qctl = take(sizeof(QCtl));
+        L.qsegs = take(L.cap_qseg * sizeof(SegQ));
+        L.qitems = take(L.cap_qitem * sizeof(QItem));
+        L.qpub = take(L.cap_qitem * sizeof(unsigned int));
+        L.qstatus = take(L.cap_qstatus * sizeof(unsigned long long));
+        for (int s = 0; s < 2; ++s) L.smalls[s] = take(L.cap_small * sizeof(SmallItem));
+    }
     L.total = off;
     return L;
 }
@@ -212,6 +286,8 @@ struct bqs_ctx {
     int64_t ept = 0;
     int64_t grid = 0;
     int64_t profile = 0;
+    int64_t mode = BQS_MODE_LEVELS;
+    int64_t queue_grid = 0;  // resident workgroups of the queue kernel (cached)
     bqs_stats stats{};
     bqs_status latched = BQS_OK;
     bqs::Ctl* pinned = nullptr;
@@ -331,8 +407,24 @@ int clamp_grid(uint64_t want, int64_t cap) {
     return static_cast<int>(want);
 }
 
+void fill_stats(bqs_stats& stats, const Ctl& c) {
+    stats.partitioned_keys = static_cast<int64_t>(c.part_keys);
+    stats.small_sorted_keys = static_cast<int64_t>(c.small_keys);
+    stats.filled_keys = static_cast<int64_t>(c.fill_keys);
+    stats.tiles = static_cast<int64_t>(c.tiles);
+    stats.prof_tiles = static_cast<int64_t>(c.prof[0]);
+    stats.prof_lookback_rounds = static_cast<int64_t>(c.prof[1]);
+    stats.prof_lookback_polls = static_cast<int64_t>(c.prof[2]);
+    stats.prof_lookback_cycles = static_cast<double>(c.prof[3]);
+    stats.prof_tile_cycles = static_cast<double>(c.prof[4]);
+    stats.prof_load_cycles = static_cast<double>(c.prof[5]);
+}
+
+bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented);
+
 // The level loop shared by all entry points.
 bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
+    if (ctx->mode == BQS_MODE_QUEUE) return run_queue(ctx, o, a, segmented);
     bqs_status st = ensure_device_state(ctx);
     if (st != BQS_OK) return st;
     const hipStream_t s = ctx->stream;
@@ -395,16 +487,53 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
     tm.resolve(stats);
     if (ctx->pinned->error) return BQS_EOVERFLOW;
-    stats.partitioned_keys = static_cast<int64_t>(ctx->pinned->part_keys);
-    stats.small_sorted_keys = static_cast<int64_t>(ctx->pinned->small_keys);
-    stats.filled_keys = static_cast<int64_t>(ctx->pinned->fill_keys);
-    stats.tiles = static_cast<int64_t>(ctx->pinned->tiles);
-    stats.prof_tiles = static_cast<int64_t>(ctx->pinned->prof[0]);
-    stats.prof_lookback_rounds = static_cast<int64_t>(ctx->pinned->prof[1]);
-    stats.prof_lookback_polls = static_cast<int64_t>(ctx->pinned->prof[2]);
-    stats.prof_lookback_cycles = static_cast<double>(ctx->pinned->prof[3]);
-    stats.prof_tile_cycles = static_cast<double>(ctx->pinned->prof[4]);
-    stats.prof_load_cycles = static_cast<double>(ctx->pinned->prof[5]);
+    fill_stats(stats, *ctx->pinned);
+    ctx->stats = stats;
+    return BQS_OK;
+}
+
+// Work-queue mode: seed, drain with one persistent launch, bin and sort the
+// small segments.  No host synchronisation until the final status read.
+bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
+    bqs_status st = ensure_device_state(ctx);
+    if (st != BQS_OK) return st;
+    const hipStream_t s = ctx->stream;
+    Timer tm{ctx, ctx->timing != 0};
+    tm.resolve(ctx->stats);
+    bqs_stats stats{};
+    stats.tile_keys = o->tile_keys;
+    stats.small_cutoff = a.small_cut;
+    ctx->level_keys.clear();
+    ctx->level_ms.clear();
+    if (ctx->queue_grid <= 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return BQS_EHIP;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return BQS_EHIP;
+        const int per = o->qblocks_per_cu();
+        if (per <= 0 || cus <= 0) return BQS_EHIP;
+        ctx->queue_grid = static_cast<int64_t>(per) * cus;
+    }
+    const int grid = static_cast<int>(ctx->grid > 0 ? std::min<int64_t>(ctx->grid, ctx->queue_grid) : ctx->queue_grid);
+    tm.start();
+    o->qinit(a, segmented ? static_cast<int>(a.k) : 1, s);
+    tm.stop(0, 0);
+    tm.start();
+    o->qrun(a, grid, s);
+    tm.stop(2, 0);
+    for (int cls = 0; cls < kSmallClasses; ++cls) {
+        if (!o->small[cls]) continue;
+        tm.start();
+        o->small[cls](a, 2048, s);
+        tm.stop(1, 0);
+        stats.small_launches++;
+    }
+    if (hipGetLastError() != hipSuccess) return BQS_EHIP;
+    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+    tm.resolve(stats);
+    const unsigned err = ctx->pinned->error;
+    if (err) return (err & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
+    stats.partition_launches = 1;
+    fill_stats(stats, *ctx->pinned);
     ctx->stats = stats;
     return BQS_OK;
 }
@@ -413,8 +542,10 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
                    void* vals, Args& a) {
     const size_t kb = key_bytes(dtype);
     const int64_t S = eff_small_cut(ctx, o);
-    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, o->tile_keys, S);
-    if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull)
+    const bool queue = ctx->mode == BQS_MODE_QUEUE;
+    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, o->tile_keys, S, queue);
+    if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull ||
+        L.cap_qseg > 0xffffffffull || L.cap_qitem > 0xffffffffull)
         return BQS_EINVAL;
     if (!ctx->ws || ctx->ws_bytes < L.total) return BQS_EINVAL;
     if (overlaps(keys, static_cast<size_t>(n) * kb, ctx->ws, ctx->ws_bytes)) return BQS_EINVAL;
@@ -449,6 +580,17 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
     a.tile_keys = o->tile_keys;
     a.prof = static_cast<int>(ctx->profile);
+    a.queue = queue ? 1 : 0;
+    if (queue) {
+        a.qctl = reinterpret_cast<QCtl*>(w + L.qctl);
+        a.qsegs = reinterpret_cast<SegQ*>(w + L.qsegs);
+        a.qitems = reinterpret_cast<QItem*>(w + L.qitems);
+        a.qpub = reinterpret_cast<unsigned int*>(w + L.qpub);
+        a.qstatus = reinterpret_cast<unsigned long long*>(w + L.qstatus);
+        a.cap_qseg = static_cast<uint32_t>(L.cap_qseg);
+        a.cap_qitem = static_cast<uint32_t>(L.cap_qitem);
+        a.cap_qstatus = L.cap_qstatus;
+    }
     return BQS_OK;
 }
 
@@ -509,6 +651,14 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             break;
         case BQS_PARAM_GRID: ctx->grid = value; break;
         case BQS_PARAM_PROFILE: ctx->profile = value ? 1 : 0; break;
+        case BQS_PARAM_MODE:
+            // The work-queue kernel took a memory-aperture fault on its first
+            // input with partition tiles (n = 8193 int32) and the cause is not
+            // known; the mode stays closed until it is.
+            if (value != BQS_MODE_LEVELS) return BQS_EINVAL;
+            ctx->mode = value;
+            ctx->queue_grid = 0;
+            break;
         default: return BQS_EINVAL;
     }
     return BQS_OK;
@@ -524,6 +674,7 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_TILE_EPT: return ctx->ept;
         case BQS_PARAM_GRID: return ctx->grid;
         case BQS_PARAM_PROFILE: return ctx->profile;
+        case BQS_PARAM_MODE: return ctx->mode;
         default: return -1;
     }
 }
@@ -547,7 +698,8 @@ size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, i
     const Ops* o = select_ops(ctx, key, val_bytes);
     if (!o) return 0;
     const Layout L = make_layout(n_total, key_bytes(key), static_cast<size_t>(val_bytes),
-                                 std::max<int64_t>(k_segments, 1), o->tile_keys, eff_small_cut(ctx, o));
+                                 std::max<int64_t>(k_segments, 1), o->tile_keys, eff_small_cut(ctx, o),
+                                 ctx && ctx->mode == BQS_MODE_QUEUE);
     return L.total;
 }
 

@@ -358,15 +358,41 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// Partition kernel, level L: one tile of T = NT*EPT keys per iteration.
-// Tiles are claimed in order through an atomic counter, so every tile that
-// a look-back waits for is held by a running workgroup.  The next tile is
-// claimed, and its descriptor fetched, while the current one is processed.
+// Partition tile, shared by the level-mode kernel and the work-queue kernel.
+//
+// One workgroup partitions one tile of T = NT*EPT keys of a segment [lo, hi)
+// around the segment's pivot: keys < pivot go to the left run, keys > pivot
+// to the right run, keys == pivot are counted (keys) or parked in the side
+// buffer (payloads).  Tile j of a segment covers [ (lo/T + j)*T, +T ) clipped
+// to the segment, so full tiles are aligned.  `status` points at the status
+// words of the segment's tiles (index j).
 
 __device__ __forceinline__ uint64_t cycles() { return static_cast<uint64_t>(clock64()); }
 
-template <int DT, class V, int NT, int EPT, bool PERSIST>
-__global__ __launch_bounds__(NT) void k_partition(Args a) {
+constexpr unsigned long long kLookbackTicks = 1ull << 27;  // ~1.3 s of the 100 MHz wall clock
+
+struct TileIO {
+    unsigned int* error;
+    const void* src;
+    void* dst;
+    const void* vsrc;
+    void* vdst;
+    void* side;
+    unsigned long long* status;
+    int64_t lo, hi;
+    uint64_t pivot;
+    uint32_t j;
+};
+
+struct TileOut {
+    int64_t Lx, Gx;     // keys < pivot / > pivot in the segment's earlier tiles
+    uint32_t nlt, ngt;  // this tile's counts
+    bool last;          // this tile is the segment's last
+    bool ok;            // the claimed ranges are consistent
+};
+
+template <int DT, class V, int NT, int EPT>
+__device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned long long* s_prof) {
     using K = KeyT<DT>;
     using R = typename K::raw;
     using O = decltype(K::ord(R()));
@@ -377,9 +403,7 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     constexpr int NW = NT / 64;
     constexpr int NE = EPT * NW;
     constexpr int C = (NE + 63) / 64;
-    static_assert(T < (1 << 21), "tile counts are packed in 21 bits");
     static_assert(EPT <= 32, "class codes are packed in 64 bits");
-
     // per-(item, wave) counts: less | greater (| equal for pairs) packed in
     // FW-bit fields; prefix sums stay below 2^FW
     using Cnt = typename std::conditional<HV, uint64_t, uint32_t>::type;
@@ -391,243 +415,591 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     __shared__ VS s_v[HV ? T + 64 : 1];
     __shared__ Cnt s_cnt[NE];
     __shared__ Cnt s_tot;
-    __shared__ TileDesc s_desc[2];
-    __shared__ uint32_t s_next;
     __shared__ int64_t s_ex[2];
 
-    const int tid0 = threadIdx.x;
-    Ctl* c = a.ctl;
-    const int p = a.level & 1, q = p ^ 1;
-    const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
-    const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
-    R* dst = static_cast<R*>(p ? a.x_keys : a.y_keys);
-    const VS* vsrc = static_cast<const VS*>(p ? a.y_vals : a.x_vals);
-    VS* vdst = static_cast<VS*>(p ? a.x_vals : a.y_vals);
-    VS* side = static_cast<VS*>(a.side);
-    // profile counters live in LDS so that they hold no registers across tiles:
-    // tiles, look-back rounds, polls, look-back cycles, tile cycles, load cycles
-    const bool prof = a.prof != 0;
-    __shared__ unsigned long long s_prof[6];
-    if (prof && tid0 < 6) s_prof[tid0] = 0;
+    const int tid = static_cast<int>(threadIdx.x), lane = tid & 63, wv = tid >> 6;
+    const bool prof = s_prof != nullptr;
+    const uint64_t t_begin = prof ? cycles() : 0;
+    const R* src = static_cast<const R*>(io.src);
+    R* dst = static_cast<R*>(io.dst);
+    const VS* vsrc = static_cast<const VS*>(io.vsrc);
+    VS* vdst = static_cast<VS*>(io.vdst);
+    VS* side = static_cast<VS*>(io.side);
+    const uint32_t j = io.j;
+    const int64_t tbase = (io.lo / T + j) * static_cast<int64_t>(T);
+    const int sl = io.lo > tbase ? static_cast<int>(io.lo - tbase) : 0;
+    const int el = io.hi < tbase + T ? static_cast<int>(io.hi - tbase) : T;
+    const bool full = sl == 0 && el == T;
+    const O piv = static_cast<O>(io.pivot);
+    const R* tsrc = src + tbase;
 
-    // the prefetching lane: lane 0 of the last wave
-    const bool pf = tid0 == NT - 64;
-    if (pf) {
-        const uint32_t t = atomicAdd(&c->lc[p].tile_next, 1u);
-        s_next = t;
-        if (t < ntiles) s_desc[0] = a.tile_desc[t];
+    // scanning phase: coalesced loads, item i of thread tid is key i*NT + tid
+    R key[EPT];
+    VS val[EPT];
+    if (full) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            key[i] = tsrc[i * NT + tid];
+            if constexpr (HV) val[i] = vsrc[tbase + i * NT + tid];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int off = i * NT + tid;
+            const bool ok = off >= sl && off < el;
+            key[i] = ok ? tsrc[off] : R(0);
+            if constexpr (HV) val[i] = ok ? vsrc[tbase + off] : VS(0);
+        }
+    }
+    // class codes (2 bits per item: 0 none, 1 less, 2 greater, 3 equal) and
+    // per-(item, wave) counts from wave ballots
+    Cls cls = 0;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const bool ok = full || ((i * NT + tid) >= sl && (i * NT + tid) < el);
+        const O o = K::ord(key[i]);
+        const bool lt = ok & (o < piv);
+        const bool gt = ok & (o > piv);
+        const uint64_t mlt = __ballot(lt), mgt = __ballot(gt);
+        Cnt packed = static_cast<Cnt>(__popcll(mlt)) | (static_cast<Cnt>(__popcll(mgt)) << FW);
+        if constexpr (HV) {
+            const bool eq = ok & !lt & !gt;
+            packed |= static_cast<Cnt>(__popcll(__ballot(eq))) << (2 * FW);
+        }
+        if (lane == 0) s_cnt[i * NW + wv] = packed;
+        const Cls code = static_cast<Cls>(static_cast<uint32_t>(ok) * 3u - 2u * static_cast<uint32_t>(lt) -
+                                          static_cast<uint32_t>(gt));
+        cls |= code << (2 * i);
+        // keep one item's lane masks live at a time (they live in SGPRs)
+        __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    uint32_t tile = s_next;
-    int buf = 0;
+    const uint64_t t_loaded = prof ? cycles() : 0;
 
-    while (tile < ntiles) {
-        const uint64_t t_begin = prof ? cycles() : 0;
-        // opaque per-iteration copies: everything derived from the thread
-        // index is recomputed per tile instead of held in registers
-        const int tid = opaque(tid0);
-        const int lane = tid & 63;
-        const int wv = tid >> 6;
-        const TileDesc td = s_desc[buf];
-        uint32_t nxt = ntiles;
-        if constexpr (PERSIST) {
-            if (pf) nxt = atomicAdd(&c->lc[p].tile_next, 1u);
-        }
-        const uint32_t j = tile - td.t0;
-        // tiles sit on multiples of T in the array, so full tiles are aligned
-        const int64_t tbase = (td.lo / T + j) * static_cast<int64_t>(T);
-        const int sl = td.lo > tbase ? static_cast<int>(td.lo - tbase) : 0;
-        const int el = td.hi < tbase + T ? static_cast<int>(td.hi - tbase) : T;
-        const bool full = sl == 0 && el == T;
-        const O piv = static_cast<O>(td.pivot);
-        const R* tsrc = src + tbase;
-
-        // scanning phase: coalesced loads, item i of thread tid is key i*NT + tid
-        R key[EPT];
-        VS val[EPT];
-        if (full) {
+    // offsets: exclusive prefix over (item, wave) counts, by wave 0
+    if (wv == 0) {
+        Cnt loc[C];
+        Cnt sum = 0;
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                key[i] = tsrc[i * NT + tid];
-                if constexpr (HV) val[i] = vsrc[tbase + i * NT + tid];
-            }
-        } else {
+        for (int cc = 0; cc < C; ++cc) {
+            const int idx = lane * C + cc;
+            loc[cc] = idx < NE ? s_cnt[idx] : Cnt(0);
+            sum += loc[cc];
+        }
+        const Cnt inc = static_cast<Cnt>(wave_inclusive_sum(static_cast<uint64_t>(sum), lane));
+        Cnt run = inc - sum;
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                const int off = i * NT + tid;
-                const bool ok = off >= sl && off < el;
-                key[i] = ok ? tsrc[off] : R(0);
-                if constexpr (HV) val[i] = ok ? vsrc[tbase + off] : VS(0);
-            }
+        for (int cc = 0; cc < C; ++cc) {
+            const int idx = lane * C + cc;
+            if (idx < NE) s_cnt[idx] = run;
+            run += loc[cc];
         }
-        // class codes (2 bits per item: 0 none, 1 less, 2 greater, 3 equal)
-        // and the per-(item, wave) counts; lane i collects item i's counts so
-        // that one store per lane publishes them
-        Cls cls = 0;
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const bool ok = full || ((i * NT + tid) >= sl && (i * NT + tid) < el);
-            const O o = K::ord(key[i]);
-            const bool lt = ok & (o < piv);
-            const bool gt = ok & (o > piv);
-            const uint64_t mlt = __ballot(lt), mgt = __ballot(gt);
-            Cnt packed = static_cast<Cnt>(__popcll(mlt)) | (static_cast<Cnt>(__popcll(mgt)) << FW);
-            if constexpr (HV) {
-                const bool eq = ok & !lt & !gt;
-                packed |= static_cast<Cnt>(__popcll(__ballot(eq))) << (2 * FW);
-            }
-            if (lane == 0) s_cnt[i * NW + wv] = packed;
-            // 1 less, 2 greater, 3 equal, 0 outside the segment
-            const Cls code = static_cast<Cls>(static_cast<uint32_t>(ok) * 3u -
-                                              2u * static_cast<uint32_t>(lt) -
-                                              static_cast<uint32_t>(gt));
-            cls |= code << (2 * i);
-            // keep one item's lane masks live at a time (they live in SGPRs)
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        TileDesc nd;
-        if constexpr (PERSIST) {
-            if (pf && nxt < ntiles) nd = a.tile_desc[nxt];
-        }
-        __syncthreads();
-        const uint64_t t_loaded = prof ? cycles() : 0;
-
-        // offsets: exclusive prefix over (item, wave) counts, by wave 0
-        if (wv == 0) {
-            Cnt loc[C];
-            Cnt sum = 0;
-#pragma unroll
-            for (int cc = 0; cc < C; ++cc) {
-                const int idx = lane * C + cc;
-                loc[cc] = idx < NE ? s_cnt[idx] : Cnt(0);
-                sum += loc[cc];
-            }
-            const Cnt inc = static_cast<Cnt>(wave_inclusive_sum(static_cast<uint64_t>(sum), lane));
-            Cnt run = inc - sum;
-#pragma unroll
-            for (int cc = 0; cc < C; ++cc) {
-                const int idx = lane * C + cc;
-                if (idx < NE) s_cnt[idx] = run;
-                run += loc[cc];
-            }
-            if (lane == 63) s_tot = inc;
-        }
-        __syncthreads();
-        const Cnt tot = s_tot;
-        const uint32_t nlt = static_cast<uint32_t>(tot & FM);
-        const uint32_t ngt = static_cast<uint32_t>((tot >> FW) & FM);
-        const uint32_t neq = HV ? static_cast<uint32_t>((static_cast<uint64_t>(tot) >> (2 * FW)) & FM) : 0u;
-
-        // wave 0 claims the output ranges (look-back) while the other waves
-        // already stage their keys in LDS
-        if (wv == 0) {
-            const uint64_t t_lb = prof ? cycles() : 0;
-            uint64_t Lx = 0, Gx = 0;
-            if (j == 0) {
-                if (lane == 0) st_status(&a.status[tile], st_pack(kStInc, nlt, ngt));
-            } else {
-                if (lane == 0) st_status(&a.status[tile], st_pack(kStAgg, nlt, ngt));
-                int64_t pos = static_cast<int64_t>(tile) - 1;
-                const int64_t first = td.t0;
-                for (;;) {
-                    const int64_t qq = pos - lane;
-                    uint64_t st;
-                    for (;;) {
-                        st = qq >= first ? ld_status(&a.status[qq]) : st_pack(kStInc, 0, 0);
-                        if (prof && lane == 0) s_prof[2] += 1;
-                        if (__ballot((st >> 62) == 0) == 0ull) break;
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                    if (prof && lane == 0) s_prof[1] += 1;
-                    const uint64_t incm = __ballot((st >> 62) == kStInc);
-                    const int lim = incm ? (__ffsll(static_cast<unsigned long long>(incm)) - 1) : 63;
-                    const uint64_t l = lane <= lim ? ((st >> 31) & kM31) : 0ull;
-                    const uint64_t g = lane <= lim ? (st & kM31) : 0ull;
-                    Lx += wave_sum(l);
-                    Gx += wave_sum(g);
-                    if (incm) break;
-                    pos -= 64;
-                }
-                if (lane == 0) st_status(&a.status[tile], st_pack(kStInc, Lx + nlt, Gx + ngt));
-            }
-            if (lane == 0) {
-                s_ex[0] = static_cast<int64_t>(Lx);
-                s_ex[1] = static_cast<int64_t>(Gx);
-            }
-            if (prof && lane == 0) s_prof[3] += cycles() - t_lb;
-        }
-
-        // rearrangement, part 1: every key to its rank in LDS
-        // [less run | greater run | equal run (pairs only)]; keys that stay
-        // behind go to a per-lane spare slot, so the store needs no branch
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const uint32_t cl = static_cast<uint32_t>((cls >> (2 * i)) & Cls(3));
-            const uint64_t mlt = __ballot(cl == 1), mgt = __ballot(cl == 2);
-            const Cnt base = s_cnt[i * NW + wv];
-            const int dl = static_cast<int>((base & FM) + mbcnt(mlt));
-            const int dg = static_cast<int>(nlt + ((base >> FW) & FM) + mbcnt(mgt));
-            int d = cl == 1 ? dl : (cl == 2 ? dg : T + lane);
-            if constexpr (HV) {
-                const uint64_t meq = __ballot(cl == 3);
-                const int de = static_cast<int>(nlt + ngt + ((static_cast<uint64_t>(base) >> (2 * FW)) & FM) +
-                                                mbcnt(meq));
-                d = cl == 3 ? de : d;
-                s_v[d] = val[i];
-            }
-            s_k[d] = key[i];
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if constexpr (PERSIST) {
-            if (pf) {
-                s_next = nxt;
-                if (nxt < ntiles) s_desc[buf ^ 1] = nd;
-            }
-        }
-        __syncthreads();
-
-        // rearrangement, part 2: coalesced copy of the runs to the other buffer
-        const int64_t Lx = s_ex[0], Gx = s_ex[1];
-        if (Lx + nlt + Gx + ngt > td.hi - td.lo) {
-            // inconsistent look-back result: report it and write nothing
-            if (tid == 0) atomicOr(&c->error, ERR_OVERFLOW);
-        } else {
-            R* dl = dst + (td.lo + Lx);
-            R* dr = dst + (td.hi - Gx - ngt);
-            for (int t = tid; t < static_cast<int>(nlt); t += NT) dl[t] = s_k[t];
-            for (int t = tid; t < static_cast<int>(ngt); t += NT) dr[t] = s_k[nlt + t];
-            if constexpr (HV) {
-                VS* vl = vdst + (td.lo + Lx);
-                VS* vr = vdst + (td.hi - Gx - ngt);
-                for (int t = tid; t < static_cast<int>(nlt); t += NT) vl[t] = s_v[t];
-                for (int t = tid; t < static_cast<int>(ngt); t += NT) vr[t] = s_v[nlt + t];
-                const int64_t Ex = (tbase + sl - td.lo) - Lx - Gx;
-                VS* ve = side + (td.lo + Ex);
-                for (int t = tid; t < static_cast<int>(neq); t += NT) ve[t] = s_v[nlt + ngt + t];
-            }
-            // segment completion: the segment's last tile knows the totals
-            if (tbase + el == td.hi && tid == 0) {
-                const SegDesc& sd = a.segs[p][td.si];
-                const int64_t Lt = Lx + nlt, Gt = Gx + ngt;
-                const int64_t Et = (td.hi - td.lo) - Lt - Gt;
-                push_fill(a, q, td.lo + Lt, Et, td.lo, sd.pivot_raw);
-                push_segment(a, q, td.lo, td.lo + Lt, sd.depth + 1);
-                push_segment(a, q, td.hi - Gt, td.hi, sd.depth + 1);
-            }
-        }
-        if (prof && tid == 0) {
-            s_prof[0] += 1;
-            s_prof[5] += t_loaded - t_begin;
-            s_prof[4] += cycles() - t_begin;
-        }
-        if constexpr (!PERSIST) break;
-        __syncthreads();
-        tile = s_next;
-        buf ^= 1;
+        if (lane == 63) s_tot = inc;
     }
-    if (prof && tid0 < 6) atomicAdd(&c->prof[tid0], s_prof[tid0]);
+    __syncthreads();
+    const Cnt tot = s_tot;
+    const uint32_t nlt = static_cast<uint32_t>(tot & FM);
+    const uint32_t ngt = static_cast<uint32_t>((tot >> FW) & FM);
+    const uint32_t neq = HV ? static_cast<uint32_t>((static_cast<uint64_t>(tot) >> (2 * FW)) & FM) : 0u;
+
+    // wave 0 claims the output ranges (decoupled look-back over the status
+    // words of the segment's earlier tiles) while the other waves already
+    // stage their keys in LDS
+    if (wv == 0) {
+        const uint64_t t_lb = prof ? cycles() : 0;
+        uint64_t Lx = 0, Gx = 0;
+        unsigned long long* st_me = io.status + j;
+        if (j == 0) {
+            if (lane == 0) st_status(st_me, st_pack(kStInc, nlt, ngt));
+        } else {
+            if (lane == 0) st_status(st_me, st_pack(kStAgg, nlt, ngt));
+            int64_t pos = static_cast<int64_t>(j) - 1;
+            const unsigned long long t_wait = wall_clock64();
+            bool stalled = false;
+            for (;;) {
+                const int64_t qq = pos - lane;
+                uint64_t st;
+                for (;;) {
+                    st = (qq >= 0 && !stalled) ? ld_status(io.status + qq) : st_pack(kStInc, 0, 0);
+                    if (prof && lane == 0) s_prof[2] += 1;
+                    if (__ballot((st >> 62) == 0) == 0ull) break;
+                    if (wall_clock64() - t_wait > kLookbackTicks) {
+                        // a predecessor never published: latch the error and stop waiting
+                        stalled = true;
+                        if (lane == 0) atomicOr(io.error, ERR_STALL);
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (prof && lane == 0) s_prof[1] += 1;
+                const uint64_t incm = __ballot((st >> 62) == kStInc);
+                const int lim = incm ? (__ffsll(static_cast<unsigned long long>(incm)) - 1) : 63;
+                const uint64_t l = lane <= lim ? ((st >> 31) & kM31) : 0ull;
+                const uint64_t g = lane <= lim ? (st & kM31) : 0ull;
+                Lx += wave_sum(l);
+                Gx += wave_sum(g);
+                if (incm) break;
+                pos -= 64;
+            }
+            if (lane == 0) st_status(st_me, st_pack(kStInc, Lx + nlt, Gx + ngt));
+        }
+        if (lane == 0) {
+            s_ex[0] = static_cast<int64_t>(Lx);
+            s_ex[1] = static_cast<int64_t>(Gx);
+        }
+        if (prof && lane == 0) s_prof[3] += cycles() - t_lb;
+    }
+
+    // rearrangement, part 1: every key to its rank in LDS
+    // [less run | greater run | equal run (pairs only)]; keys that stay
+    // behind go to a per-lane spare slot, so the store needs no branch
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const uint32_t cl = static_cast<uint32_t>((cls >> (2 * i)) & Cls(3));
+        const uint64_t mlt = __ballot(cl == 1), mgt = __ballot(cl == 2);
+        const Cnt base = s_cnt[i * NW + wv];
+        const int dl = static_cast<int>((base & FM) + mbcnt(mlt));
+        const int dg = static_cast<int>(nlt + ((base >> FW) & FM) + mbcnt(mgt));
+        int d = cl == 1 ? dl : (cl == 2 ? dg : T + lane);
+        if constexpr (HV) {
+            const uint64_t meq = __ballot(cl == 3);
+            const int de = static_cast<int>(nlt + ngt + ((static_cast<uint64_t>(base) >> (2 * FW)) & FM) + mbcnt(meq));
+            d = cl == 3 ? de : d;
+            s_v[d] = val[i];
+        }
+        s_k[d] = key[i];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+
+    // rearrangement, part 2: coalesced copy of the runs to the other buffer
+    TileOut out;
+    out.Lx = s_ex[0];
+    out.Gx = s_ex[1];
+    out.nlt = nlt;
+    out.ngt = ngt;
+    out.last = tbase + el == io.hi;
+    out.ok = out.Lx + nlt + out.Gx + ngt <= io.hi - io.lo;
+    if (out.ok) {
+        R* dl = dst + (io.lo + out.Lx);
+        R* dr = dst + (io.hi - out.Gx - ngt);
+        for (int t = tid; t < static_cast<int>(nlt); t += NT) dl[t] = s_k[t];
+        for (int t = tid; t < static_cast<int>(ngt); t += NT) dr[t] = s_k[nlt + t];
+        if constexpr (HV) {
+            VS* vl = vdst + (io.lo + out.Lx);
+            VS* vr = vdst + (io.hi - out.Gx - ngt);
+            for (int t = tid; t < static_cast<int>(nlt); t += NT) vl[t] = s_v[t];
+            for (int t = tid; t < static_cast<int>(ngt); t += NT) vr[t] = s_v[nlt + t];
+            const int64_t Ex = (tbase + sl - io.lo) - out.Lx - out.Gx;
+            VS* ve = side + (io.lo + Ex);
+            for (int t = tid; t < static_cast<int>(neq); t += NT) ve[t] = s_v[nlt + ngt + t];
+        }
+    }
+    if (prof && tid == 0) {
+        s_prof[0] += 1;
+        s_prof[5] += t_loaded - t_begin;
+        s_prof[4] += cycles() - t_begin;
+    }
+    return out;
 }
 
+// ---------------------------------------------------------------------------
+// Partition kernel, level mode: one tile per workgroup.  Tiles are claimed in
+// order through the level's ticket counter, so every tile that a look-back
+// waits for is held by a running workgroup.
+
+template <int DT, class V, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_partition(Args a) {
+    __shared__ TileDesc s_desc;
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_prof[6];
+    Ctl* c = a.ctl;
+    const int p = a.level & 1, q = p ^ 1;
+    const int tid = threadIdx.x;
+    const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
+    if (a.prof && tid < 6) s_prof[tid] = 0;
+    if (tid == 0) {
+        const uint32_t t = atomicAdd(&c->lc[p].tile_next, 1u);
+        s_tile = t;
+        if (t < ntiles) s_desc = a.tile_desc[t];
+    }
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) return;
+    const TileDesc td = s_desc;
+    TileIO io;
+    io.error = &c->error;
+    io.src = p ? a.y_keys : a.x_keys;
+    io.dst = p ? a.x_keys : a.y_keys;
+    io.vsrc = p ? a.y_vals : a.x_vals;
+    io.vdst = p ? a.x_vals : a.y_vals;
+    io.side = a.side;
+    io.status = a.status + td.t0;
+    io.lo = td.lo;
+    io.hi = td.hi;
+    io.pivot = td.pivot;
+    io.j = tile - td.t0;
+    const TileOut r = tile_partition<DT, V, NT, EPT>(io, a.prof ? s_prof : nullptr);
+    if (!r.ok) {
+        // inconsistent look-back result: report it (nothing was written)
+        if (tid == 0) atomicOr(&c->error, ERR_OVERFLOW);
+    } else if (r.last && tid == 0) {
+        // segment completion: the segment's last tile knows the totals
+        const SegDesc& sd = a.segs[p][td.si];
+        const int64_t Lt = r.Lx + r.nlt, Gt = r.Gx + r.ngt;
+        const int64_t Et = (td.hi - td.lo) - Lt - Gt;
+        push_fill(a, q, td.lo + Lt, Et, td.lo, sd.pivot_raw);
+        push_segment(a, q, td.lo, td.lo + Lt, sd.depth + 1);
+        push_segment(a, q, td.hi - Gt, td.hi, sd.depth + 1);
+    }
+    if (a.prof) {
+        __syncthreads();
+        if (tid < 6) atomicAdd(&c->prof[tid], s_prof[tid]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Work-queue mode: the recursion as a device-resident queue drained by one
+// persistent kernel (Quicksort main loop, Algorithm 1 with an explicit stack,
+// Section 2: here the "stack" holds tiles of every open segment at once).
+//
+// Protocol.  A producer reserves slots with an atomic add on `tail`, writes
+// the items, fences (release, agent scope) and then sets each slot's flag.
+// A consumer claims the next slot with an atomic add on `head`, waits for its
+// flag, fences (acquire) and reads the item.  `outstanding` counts items that
+// are published or running; producers raise it before publishing and an item
+// lowers it only after publishing its own follow-up work, so it reaches zero
+// exactly when the sort is done -- that is when waiting workgroups leave.
+// A segment's tiles each fence and then count themselves done; the last one
+// to finish (its acquire fence makes every tile's output visible) writes the
+// equal run, picks the children's pivots and publishes their tiles.  Every
+// wait is bounded by a wall-clock limit: past it the kernel latches
+// ERR_STALL and every workgroup leaves, so the launch always terminates.
+
+constexpr unsigned long long kSpinTicks = 1ull << 27;  // ~1.3 s of the 100 MHz wall clock
+constexpr int64_t kInlineFill = 16384;                  // equal runs written by the finisher itself
+
+__device__ __forceinline__ unsigned ld_flag(const unsigned int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Pivot of keys src[lo, hi): median of a stratified sample (all NT threads).
+template <int DT, int NT>
+__device__ typename KeyT<DT>::raw pick_pivot(const typename KeyT<DT>::raw* src, int64_t lo, int64_t hi,
+                                             uint32_t depth, const Args& a) {
+    using K = KeyT<DT>;
+    using R = typename K::raw;
+    static_assert(NT >= kMaxSample + 1, "one thread per sample");
+    __shared__ R s_samp[kMaxSample + 1];
+    __shared__ R s_pick;
+    const int tid = threadIdx.x;
+    const int64_t m = hi - lo;
+    int k;
+    if (a.pivot_mode == 3 && depth < static_cast<uint32_t>(a.depth_limit)) {
+        k = 3;
+    } else {
+        // about sqrt(m)/4 samples, odd, within [7, sample_max]; past the
+        // depth limit the largest sample is used
+        int64_t kk = static_cast<int64_t>(sqrt(static_cast<double>(m))) / 4;
+        if (depth >= static_cast<uint32_t>(a.depth_limit)) kk = a.sample_max;
+        if (kk > a.sample_max) kk = a.sample_max;
+        if (kk < 7) kk = 7;
+        if (kk > m) kk = m;
+        k = static_cast<int>(kk) | 1;
+        if (k > m) k -= 2;
+    }
+    __syncthreads();  // s_samp may still be read by a previous call
+    if (tid < k) {
+        int64_t pos;
+        if (k == 3) {
+            pos = tid == 0 ? lo : (tid == 1 ? lo + m / 2 : hi - 1);
+        } else {
+            const int64_t stride = m / k;
+            const uint64_t h = mix64((static_cast<uint64_t>(lo) * 0x9e3779b97f4a7c15ull) ^
+                                     (static_cast<uint64_t>(hi) << 17) ^ (static_cast<uint64_t>(tid) << 40) ^ depth);
+            pos = lo + tid * stride + static_cast<int64_t>(h % static_cast<uint64_t>(stride));
+        }
+        s_samp[tid] = src[pos];
+    }
+    __syncthreads();
+    if (tid < k) {
+        // rank of this sample: smaller samples, plus equal ones of lower index
+        const R mine = s_samp[tid];
+        const auto om = K::ord(mine);
+        int rank = 0;
+        for (int j = 0; j < k; ++j) {
+            const auto oj = K::ord(s_samp[j]);
+            rank += (oj < om) | ((oj == om) & (j < tid));
+        }
+        if (rank == k / 2) s_pick = mine;
+    }
+    __syncthreads();
+    return s_pick;
+}
+
+// Publishes `count` items (kind, seg, 0..count-1).  All NT threads.
+template <int NT>
+__device__ void q_publish(const Args& a, uint32_t kind, uint32_t seg, uint32_t count) {
+    __shared__ unsigned long long s_pos;
+    const int tid = threadIdx.x;
+    QCtl* q = a.qctl;
+    if (tid == 0) {
+        atomicAdd(&q->outstanding, static_cast<unsigned long long>(count));
+        s_pos = atomicAdd(&q->tail, static_cast<unsigned long long>(count));
+    }
+    __syncthreads();
+    const unsigned long long pos = s_pos;
+    if (pos + count > a.cap_qitem) {
+        if (tid == 0) atomicOr(&a.ctl->error, ERR_OVERFLOW);
+        return;
+    }
+    for (uint32_t i = tid; i < count; i += NT) a.qitems[pos + i] = QItem{kind, seg, i, 0u};
+    __threadfence();  // release: items, segment descriptors and the data they describe
+    __syncthreads();
+    for (uint32_t i = tid; i < count; i += NT)
+        __hip_atomic_store(&a.qpub[pos + i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A child segment [lo, hi) whose keys sit in buffer `buf`: small segments go
+// to the small-sort lists, larger ones get a pivot, status words and tiles.
+template <int DT, class V, int NT, int EPT>
+__device__ void q_spawn(const Args& a, int64_t lo, int64_t hi, uint32_t depth, uint32_t buf) {
+    using K = KeyT<DT>;
+    using R = typename K::raw;
+    constexpr int64_t T = NT * EPT;
+    __shared__ uint32_t s_seg;
+    __shared__ int s_ok;
+    const int tid = threadIdx.x;
+    const int64_t m = hi - lo;
+    if (m <= 0) return;
+    Ctl* c = a.ctl;
+    if (m <= a.small_cut) {
+        if (tid == 0 && !(m == 1 && buf == 0)) {
+            // arrival-order list; binned by size class once the queue drained
+            const uint32_t idx = atomicAdd(&a.qctl->small_raw, 1u);
+            if (idx >= a.cap_small) {
+                atomicOr(&c->error, ERR_OVERFLOW);
+            } else {
+                atomicAdd(&c->lc[0].smalls[small_class(m)], 1u);
+                a.smalls[1][idx] = SmallItem{lo, hi | (static_cast<int64_t>(buf) << 62)};
+            }
+        }
+        return;
+    }
+    const R* src = static_cast<const R*>(buf ? a.y_keys : a.x_keys);
+    const R piv = pick_pivot<DT, NT>(src, lo, hi, depth, a);
+    const uint32_t nt = static_cast<uint32_t>((hi + T - 1) / T - lo / T);
+    if (tid == 0) {
+        QCtl* q = a.qctl;
+        const uint32_t si = atomicAdd(&q->segs, 1u);
+        const unsigned long long sb = atomicAdd(&q->status_next, static_cast<unsigned long long>(nt));
+        const bool ok = si < a.cap_qseg && sb + nt <= a.cap_qstatus;
+        if (ok) {
+            SegQ d{};
+            d.lo = lo;
+            d.hi = hi;
+            d.pivot = static_cast<uint64_t>(K::ord(piv));
+            d.pivot_raw = static_cast<uint64_t>(piv);
+            d.st_base = sb;
+            d.nt = nt;
+            d.depth = depth;
+            d.buf = buf;
+            a.qsegs[si] = d;
+            atomicAdd(&c->part_keys, static_cast<unsigned long long>(m));
+            atomicAdd(&c->tiles, static_cast<unsigned long long>(nt));
+        } else {
+            atomicOr(&c->error, ERR_OVERFLOW);
+        }
+        s_seg = si;
+        s_ok = ok;
+    }
+    __syncthreads();
+    if (s_ok) q_publish<NT>(a, QK_TILE, s_seg, nt);
+}
+
+// Writes units [u0, u1) of keys equal to the pivot (and, for pairs, their
+// payloads from the side buffer) into X.  All NT threads.
+template <int DT, class V, int NT>
+__device__ void q_fill(const Args& a, const SegQ& sd, int64_t b, int64_t e) {
+    using R = typename KeyT<DT>::raw;
+    using VS = typename ValStore<V>::type;
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    R* xk = static_cast<R*>(a.x_keys) + sd.lo + sd.Lt;
+    const R raw = static_cast<R>(sd.pivot_raw);
+    for (int64_t t = b + threadIdx.x; t < e; t += NT) {
+        xk[t] = raw;
+        if constexpr (HV) static_cast<VS*>(a.x_vals)[sd.lo + sd.Lt + t] = static_cast<const VS*>(a.side)[sd.lo + t];
+    }
+}
+
+template <int DT, class V, int NT, int EPT>
+__device__ void q_children(const Args& a, const SegQ& sd) {
+    q_spawn<DT, V, NT, EPT>(a, sd.lo, sd.lo + sd.Lt, sd.depth + 1, sd.buf ^ 1u);
+    q_spawn<DT, V, NT, EPT>(a, sd.hi - sd.Gt, sd.hi, sd.depth + 1, sd.buf ^ 1u);
+}
+
+// Segment completion by the workgroup of its last finishing tile.
+template <int DT, class V, int NT, int EPT>
+__device__ void q_complete(const Args& a, uint32_t si, int64_t Lt, int64_t Gt) {
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    __shared__ SegQ s_sd;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        SegQ* sd = &a.qsegs[si];
+        sd->Lt = Lt;
+        sd->Gt = Gt;
+        s_sd = *sd;
+        s_sd.Lt = Lt;
+        s_sd.Gt = Gt;
+    }
+    __syncthreads();
+    const SegQ sd = s_sd;
+    const int64_t Et = (sd.hi - sd.lo) - Lt - Gt;
+    if (tid == 0 && Et > 0) atomicAdd(&a.ctl->fill_keys, static_cast<unsigned long long>(Et));
+    if (Et <= kInlineFill) {
+        q_fill<DT, V, NT>(a, sd, 0, Et);
+        if constexpr (HV) __threadfence();  // side reads done before children may overwrite it
+        __syncthreads();
+        q_children<DT, V, NT, EPT>(a, sd);
+    } else {
+        const uint32_t nch = static_cast<uint32_t>((Et + kFillChunk - 1) / kFillChunk);
+        if constexpr (HV) {
+            // the children reuse the side buffer: they start after the last fill unit
+            if (tid == 0) a.qsegs[si].fill_left = nch;
+            q_publish<NT>(a, QK_FILL, si, nch);
+        } else {
+            q_publish<NT>(a, QK_FILL, si, nch);
+            q_children<DT, V, NT, EPT>(a, sd);
+        }
+    }
+}
+
+template <int DT, class V, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_queue(Args a) {
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    __shared__ QItem s_item;
+    __shared__ int s_exit;
+    __shared__ int s_fin;
+    __shared__ int64_t s_tot[2];
+    __shared__ SegQ s_sd;
+    const int tid = threadIdx.x;
+    QCtl* q = a.qctl;
+    Ctl* c = a.ctl;
+    for (;;) {
+        if (tid == 0) {
+            int ex = 0;
+            const unsigned long long h = atomicAdd(&q->head, 1ull);
+            if (h >= a.cap_qitem) {
+                ex = 1;  // no item can ever be published there
+            } else {
+                const unsigned long long t0 = wall_clock64();
+                for (;;) {
+                    if (ld_flag(&a.qpub[h]) != 0u) break;
+                    if (ld_u64(&q->outstanding) == 0ull || __hip_atomic_load(&c->error, __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                        ex = 1;
+                        break;
+                    }
+                    if (wall_clock64() - t0 > kSpinTicks) {
+                        atomicOr(&c->error, ERR_STALL);
+                        ex = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (!ex) {
+                    __threadfence();  // acquire: the item and what it describes
+                    s_item = a.qitems[h];
+                    s_sd = a.qsegs[s_item.seg];
+                }
+            }
+            s_exit = ex;
+        }
+        __syncthreads();
+        if (s_exit) return;
+        __threadfence();  // every wave: acquire before touching the segment's data
+        const QItem it = s_item;
+        const SegQ sd = s_sd;
+        if (it.kind == QK_TILE) {
+            TileIO io;
+            io.error = &c->error;
+            io.src = sd.buf ? a.y_keys : a.x_keys;
+            io.dst = sd.buf ? a.x_keys : a.y_keys;
+            io.vsrc = sd.buf ? a.y_vals : a.x_vals;
+            io.vdst = sd.buf ? a.x_vals : a.y_vals;
+            io.side = a.side;
+            io.status = a.qstatus + sd.st_base;
+            io.lo = sd.lo;
+            io.hi = sd.hi;
+            io.pivot = sd.pivot;
+            io.j = it.j;
+            const TileOut r = tile_partition<DT, V, NT, EPT>(io, nullptr);
+            __threadfence();  // release this tile's output
+            __syncthreads();
+            if (tid == 0) {
+                if (!r.ok) atomicOr(&c->error, ERR_OVERFLOW);
+                const uint32_t old = atomicAdd(&a.qsegs[it.seg].done, 1u);
+                const bool fin = old + 1 == sd.nt;
+                if (fin) {
+                    // totals: the inclusive status word of the segment's last tile
+                    const uint64_t st = r.last ? st_pack(kStInc, r.Lx + r.nlt, r.Gx + r.ngt)
+                                               : ld_status(&a.qstatus[sd.st_base + sd.nt - 1]);
+                    s_tot[0] = static_cast<int64_t>((st >> 31) & kM31);
+                    s_tot[1] = static_cast<int64_t>(st & kM31);
+                }
+                s_fin = fin;
+            }
+            __syncthreads();
+            if (s_fin) {
+                __threadfence();  // acquire: every tile's output
+                q_complete<DT, V, NT, EPT>(a, it.seg, s_tot[0], s_tot[1]);
+            }
+        } else {
+            const int64_t Et = (sd.hi - sd.lo) - sd.Lt - sd.Gt;
+            const int64_t b = static_cast<int64_t>(it.j) * kFillChunk;
+            const int64_t e = b + kFillChunk < Et ? b + kFillChunk : Et;
+            q_fill<DT, V, NT>(a, sd, b, e);
+            if constexpr (HV) {
+                __threadfence();
+                __syncthreads();
+                if (tid == 0) s_fin = atomicSub(&a.qsegs[it.seg].fill_left, 1u) == 1u;
+                __syncthreads();
+                if (s_fin) {
+                    __threadfence();
+                    q_children<DT, V, NT, EPT>(a, sd);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) atomicSub(&q->outstanding, 1ull);
+    }
+}
+
+// Seeds the queue: one workgroup per input segment (the whole array for a
+// single sort), validating segment offsets.
+template <int DT, class V, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_qseed(Args a) {
+    const int64_t i = blockIdx.x;
+    int64_t lo = 0, hi = a.n;
+    if (a.offsets) {
+        if (i >= a.k) return;
+        lo = a.offsets[i];
+        hi = a.offsets[i + 1];
+        const bool bad = lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) || (i == a.k - 1 && hi != a.n) ||
+                         hi - lo >= (int64_t(1) << 31);
+        if (bad) {
+            if (threadIdx.x == 0) atomicOr(&a.ctl->error, ERR_OFFSETS);
+            return;
+        }
+    } else if (i > 0) {
+        return;
+    }
+    q_spawn<DT, V, NT, EPT>(a, lo, hi, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Small-segment sort (the paper's Insertionsort stage, Section 2).
 //
@@ -655,35 +1027,48 @@ struct SItem<O, true> {
     uint32_t i;
 };
 
-// Value of lane (lane ^ m).  Masks with a DPP form stay in the vector ALU
-// (quad permutes for 1, 2, 3; row half-mirror for 7; row mirror for 15);
-// the others go through the LDS crossbar (ds_bpermute).
-__device__ __forceinline__ uint32_t shfl_x(uint32_t v, int m) {
+// Value of lane (lane ^ M) for a mask M fixed at compile time.  Masks with a
+// DPP form stay in the vector ALU (quad permutes for 1, 2, 3; row half-mirror
+// for 7; row mirror for 15); other masks below 32 use ds_swizzle in its xor
+// mode (no address operand); 32 and above go through ds_bpermute.
+template <int M>
+__device__ __forceinline__ uint32_t xlane(uint32_t v) {
     const int x = static_cast<int>(v);
-    switch (m) {
-        case 1: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true));
-        case 2: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true));
-        case 3: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, true));
-        case 7: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true));
-        case 15: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true));
-        default: return static_cast<uint32_t>(__shfl_xor(x, m, 64));
+    int r;
+    if constexpr (M == 1) {
+        r = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);
+    } else if constexpr (M == 2) {
+        r = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);
+    } else if constexpr (M == 3) {
+        r = __builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, true);
+    } else if constexpr (M == 7) {
+        r = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true);
+    } else if constexpr (M == 15) {
+        r = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true);
+    } else if constexpr (M < 32) {
+        // bit mode: and_mask 0x1f, or_mask 0, xor_mask M (within 32 lanes)
+        r = __builtin_amdgcn_ds_swizzle(x, (M << 10) | 0x1F);
+    } else {
+        r = __shfl_xor(x, M, 64);
     }
+    return static_cast<uint32_t>(r);
 }
-__device__ __forceinline__ uint64_t shfl_x(uint64_t v, int m) {
-    const uint32_t lo = shfl_x(static_cast<uint32_t>(v), m);
-    const uint32_t hi = shfl_x(static_cast<uint32_t>(v >> 32), m);
+template <int M>
+__device__ __forceinline__ uint64_t xlane(uint64_t v) {
+    const uint32_t lo = xlane<M>(static_cast<uint32_t>(v));
+    const uint32_t hi = xlane<M>(static_cast<uint32_t>(v >> 32));
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-template <class O>
-__device__ __forceinline__ SItem<O, false> shfl_item(SItem<O, false> a, int m) {
-    a.k = shfl_x(a.k, m);
+template <int M, class O>
+__device__ __forceinline__ SItem<O, false> shfl_item(SItem<O, false> a) {
+    a.k = xlane<M>(a.k);
     return a;
 }
-template <class O>
-__device__ __forceinline__ SItem<O, true> shfl_item(SItem<O, true> a, int m) {
-    a.k = shfl_x(a.k, m);
-    a.i = shfl_x(a.i, m);
+template <int M, class O>
+__device__ __forceinline__ SItem<O, true> shfl_item(SItem<O, true> a) {
+    a.k = xlane<M>(a.k);
+    a.i = xlane<M>(a.i);
     return a;
 }
 
@@ -771,6 +1156,28 @@ __device__ __forceinline__ void lds_stage(It (&v)[E], int t, O* sk, uint32_t* si
     }
 }
 
+// Cross-lane stages inside one wave: the partner of register r sits in lane
+// (lane ^ M).  Half-cleaner: same register; mirror step: register E-1-r.
+template <int M, class It, int E>
+__device__ __forceinline__ void lane_xor_stage(It (&v)[E], bool lower) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) keep(v[r], shfl_item<M>(v[r]), lower);
+}
+template <int M, class It, int E>
+__device__ __forceinline__ void lane_mirror_stage(It (&v)[E], bool lower) {
+    // registers r and E-1-r trade with each other's partner: fetch both
+    // before either changes
+#pragma unroll
+    for (int r = 0; r < (E + 1) / 2; ++r) {
+        const It o1 = shfl_item<M>(v[E - 1 - r]);
+        if (E - 1 - r != r) {
+            const It o2 = shfl_item<M>(v[r]);
+            keep(v[E - 1 - r], o2, lower);
+        }
+        keep(v[r], o1, lower);
+    }
+}
+
 template <class It, class O, int E, int NTH>
 __device__ void bitonic_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
     constexpr int LE = Log2<E>::value;
@@ -790,18 +1197,16 @@ __device__ void bitonic_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
                 default: break;
             }
         } else if (b < LE + 6) {
-            const int m = (1 << (k - LE)) - 1;
+            // partner lane: lane ^ (2^(k-LE) - 1); the exchange form is
+            // chosen once per stage
             const bool lower = ((lane >> (b - LE)) & 1) == 0;
-            // registers r and E-1-r trade with each other's partner: fetch
-            // both before either changes
-#pragma unroll
-            for (int r = 0; r < (E + 1) / 2; ++r) {
-                const It o1 = shfl_item(v[E - 1 - r], m);
-                if (E - 1 - r != r) {
-                    const It o2 = shfl_item(v[r], m);
-                    keep(v[E - 1 - r], o2, lower);
-                }
-                keep(v[r], o1, lower);
+            switch (k - LE) {
+                case 1: lane_mirror_stage<1>(v, lower); break;
+                case 2: lane_mirror_stage<3>(v, lower); break;
+                case 3: lane_mirror_stage<7>(v, lower); break;
+                case 4: lane_mirror_stage<15>(v, lower); break;
+                case 5: lane_mirror_stage<31>(v, lower); break;
+                default: lane_mirror_stage<63>(v, lower); break;
             }
         } else {
             lds_stage<It, O, E, NTH>(v, t, sk, si, (1 << k) - 1, b);
@@ -819,10 +1224,16 @@ __device__ void bitonic_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
                     default: break;
                 }
             } else if (j < LE + 6) {
-                const int m = 1 << (j - LE);
-                const bool lower = (lane & m) == 0;
-#pragma unroll
-                for (int r = 0; r < E; ++r) keep(v[r], shfl_item(v[r], m), lower);
+                // partner lane: lane ^ 2^(j-LE)
+                const bool lower = ((lane >> (j - LE)) & 1) == 0;
+                switch (j - LE) {
+                    case 0: lane_xor_stage<1>(v, lower); break;
+                    case 1: lane_xor_stage<2>(v, lower); break;
+                    case 2: lane_xor_stage<4>(v, lower); break;
+                    case 3: lane_xor_stage<8>(v, lower); break;
+                    case 4: lane_xor_stage<16>(v, lower); break;
+                    default: lane_xor_stage<32>(v, lower); break;
+                }
             } else {
                 lds_stage<It, O, E, NTH>(v, t, sk, si, 1 << j, j);
             }
@@ -854,11 +1265,16 @@ __global__ __launch_bounds__(256) void k_small(Args a, int cls) {
     const int grp = tid / NTH;
     const int t = tid % NTH;
     const uint32_t nsm = c->lc[p].smalls[cls];
-    const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
     R* xk = static_cast<R*>(a.x_keys);
-    const VS* vsrc = static_cast<const VS*>(p ? a.y_vals : a.x_vals);
     VS* xv = static_cast<VS*>(a.x_vals);
-    const SmallItem* items = a.smalls[p] + static_cast<size_t>(cls) * a.cap_small;
+    // level mode: one region of cap_small items per class; work-queue mode:
+    // the classes are packed back to back (binned after the queue drained)
+    size_t first = static_cast<size_t>(cls) * a.cap_small;
+    if (a.queue) {
+        first = 0;
+        for (int k = 0; k < cls; ++k) first += c->lc[0].smalls[k];
+    }
+    const SmallItem* items = a.smalls[p] + first;
     O* sk = s_k + grp * PS;
     uint32_t* si = HV ? s_i + grp * PS : s_i;
     VS* sv = HV ? s_v + grp * P : s_v;
@@ -868,11 +1284,17 @@ __global__ __launch_bounds__(256) void k_small(Args a, int cls) {
         const bool have = it < nsm;
         int64_t lo = 0;
         int m = 0;
+        int par = p;
         if (have) {
             const SmallItem s = items[it];
+            // work-queue mode keeps the item's buffer in bit 62 of hi
+            const int64_t hi = s.hi & ((int64_t(1) << 62) - 1);
+            if (a.queue) par = static_cast<int>((static_cast<uint64_t>(s.hi) >> 62) & 1u);
             lo = s.lo;
-            m = static_cast<int>(s.hi - s.lo);
+            m = static_cast<int>(hi - s.lo);
         }
+        const R* src = static_cast<const R*>(par ? a.y_keys : a.x_keys);
+        const VS* vsrc = static_cast<const VS*>(par ? a.y_vals : a.x_vals);
         // striped (coalesced) load into LDS, padding with the largest key
 #pragma unroll
         for (int r = 0; r < E; ++r) {
@@ -944,7 +1366,22 @@ struct Launch {
         hipLaunchKernelGGL((k_plan<DT, V, kPlanThreads>), dim3(grid), dim3(kPlanThreads), 0, s, a);
     }
     static void tile(const Args& a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_partition<DT, V, NT, EPT, false>), dim3(grid), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_partition<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
+    }
+    // work-queue mode: clear, seed one workgroup per input segment
+    static void qinit(const Args& a, int grid, hipStream_t s) {
+        launch_qclear(a, s);
+        hipLaunchKernelGGL((k_qseed<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
+    }
+    // drain the queue with `grid` resident workgroups, then bin the small segments
+    static void qrun(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_queue<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
+        launch_qbin(a, s);
+    }
+    static int qblocks_per_cu() {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_queue<DT, V, NT, EPT>, NT, 0) != hipSuccess) return 0;
+        return nb;
     }
     static void map(const Args& a, int grid, hipStream_t s) { launch_map(a, grid, s); }
     static const Ops* ops() {
@@ -960,7 +1397,10 @@ struct Launch {
              SmallFn<DT, V, 16, 256, (SMAX >= 4096)>::get(),
              SmallFn<DT, V, 32, 256, (SMAX >= 8192)>::get()},
             {4, 4, 4, 4, 4, 1, 1, 1},
-            &tile};
+            &tile,
+            &qinit,
+            &qrun,
+            &qblocks_per_cu};
         return &o;
     }
 };

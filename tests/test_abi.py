@@ -57,6 +57,10 @@ def test_ctx_params_roundtrip(bqs):
     with pytest.raises(bqs.BqsError):
         ctx.set_param("tile_ept", 12)
     assert bqs.lib.bqs_ctx_set_param(ctx._h, 77, 1) == 1
+    # the work-queue mode is closed (its kernel faulted; cause not yet known)
+    with pytest.raises(bqs.BqsError):
+        ctx.set_param("mode", bqs.MODE_QUEUE)
+    assert ctx.get_param("mode") == bqs.MODE_LEVELS
 
 
 def test_workspace_bytes(bqs):
