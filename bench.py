@@ -38,8 +38,9 @@ def parse():
     ap.add_argument("--n", type=int, default=N_HEADLINE, help="keys of the headline workload")
     ap.add_argument("--no-dists", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched segmented workload")
     ap.add_argument("--cpu-log2", type=int, default=26, help="CPU sample: arrays of 2^x keys")
-    ap.add_argument("--cpu-arrays", type=int, default=2)
+    ap.add_argument("--cpu-arrays", type=int, default=6)
     return ap.parse_args()
 
 
@@ -103,6 +104,14 @@ def run_workload(torch, bqs, ctx, kind, n, steps, warmup, seed=0):
         else:
             ctx.sort(data[i])
 
+    # reference of the last step's input, taken before it is sorted
+    last = data[-1][0] if pairs else data[-1]
+    sign = torch.tensor(-(2**63), dtype=torch.int64, device="cuda")
+    if pairs:
+        keys_in = last.clone()
+        ref = torch.sort(last ^ sign).values ^ sign  # unsigned order of the uint64 keys
+    else:
+        ref = torch.sort(last).values
     for i in range(warmup):
         one(i)
     torch.cuda.synchronize()
@@ -117,19 +126,106 @@ def run_workload(torch, bqs, ctx, kind, n, steps, warmup, seed=0):
     t1 = time.perf_counter()
     levels = ctx.levels()
     st = ctx.stats()
-    # correctness of the last step (cheap device-side checks)
-    last = data[-1][0] if pairs else data[-1]
+    # the last step against the reference: keys bit for bit; pairs also carry
+    # their payload (payload = original index)
+    ok = bool(torch.equal(last, ref))
     if pairs:
-        kk = last
-        # order of the uint64 keys: compare as signed after flipping the sign bit
-        flipped = kk ^ torch.tensor(-(2**63), dtype=torch.int64, device="cuda")
-        ok = bool((flipped[1:] >= flipped[:-1]).all())
-    else:
-        ok = bool((last[1:] >= last[:-1]).all())
+        vals = data[-1][1].to(torch.int64) & 0xFFFFFFFF
+        ok = ok and bool(torch.equal(keys_in[vals], last))
+    del ref
     del data
     torch.cuda.empty_cache()
     ms = (t1 - t0) * 1e3 / steps
     return ms, st, levels, part_ms / steps, part_keys / steps, ok
+
+
+def batched_segments(torch, bqs, steps, warmup, k=20000, seed=7, per_array=True):
+    """k int32 arrays, sizes log-uniform in [16, 2^20] (uniform keys),
+    concatenated with an int64 offsets array: one sort_segments call per
+    step, against one sort call per array on the same stream."""
+    import workloads as W
+
+    sizes = W.log_uniform_sizes(k, seed)
+    offsets = np.zeros(k + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    n = int(offsets[-1])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    pristine = torch.randint(-(2**31), 2**31, (n,), dtype=torch.int32, device="cuda", generator=g)
+    work = torch.empty_like(pristine)
+    off_d = torch.from_numpy(offsets).cuda()
+    # graph mode: the warm-up call captures the launches, timed calls replay
+    ctx = bqs.Context(graph=1)
+    times = []
+    for i in range(warmup + steps):
+        work.copy_(pristine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.sort_segments(work, off_d)
+        torch.cuda.synchronize()
+        if i >= warmup:
+            times.append(time.perf_counter() - t0)
+    st = ctx.stats()
+    ok = check_segments(torch, pristine, work, offsets)
+    ms = 1e3 * float(np.median(times))
+    out = {
+        "workload": f"{k} int32 arrays, sizes log-uniform in [16, 2^20], {n} keys, int64 offsets",
+        "k": k, "n": n, "seed": seed,
+        "batched": {"ms": round(ms, 3), "ms_min": round(1e3 * min(times), 3),
+                    "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3),
+                    "alg_GBps": round((8 * (st["partitioned_keys"] + st["small_sorted_keys"]) +
+                                       4 * st["filled_keys"]) / (ms * 1e-3) / 1e9, 1),
+                    "levels": st["levels"], "graph_replay": bool(st["graph_launches"]),
+                    # every array completes when the call does
+                    "array_done_p50_ms": round(ms, 3), "array_done_p99_ms": round(ms, 3)},
+        "correct": ok,
+    }
+    if per_array:
+        # baseline: one sort call per array, in order, on one stream
+        work.copy_(pristine)
+        torch.cuda.synchronize()
+        views = [work[int(offsets[i]):int(offsets[i + 1])] for i in range(k)]
+        ctx = bqs.Context()
+        done = np.empty(k)
+        t0 = time.perf_counter()
+        for i, v in enumerate(views):
+            if v.numel() > 1:
+                ctx.sort(v)
+            done[i] = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        ok_pa = check_segments(torch, pristine, work, offsets)
+        out["per_array"] = {"ms": round(1e3 * total, 1), "Gkeys/s": round(n / total / 1e9, 3),
+                            "array_done_p50_ms": round(1e3 * float(np.percentile(done, 50, method="nearest")), 1),
+                            "array_done_p99_ms": round(1e3 * float(np.percentile(done, 99, method="nearest")), 1),
+                            "correct": ok_pa}
+        out["speedup_vs_per_array"] = round(total * 1e3 / ms, 2)
+    del work, pristine
+    torch.cuda.empty_cache()
+    return out
+
+
+def check_segments(torch, pristine, work, offsets):
+    """Every segment ascending, and per segment the same multiset of keys
+    as the input (sum of a 64-bit mix of each key, per segment)."""
+    k = len(offsets) - 1
+    n = int(offsets[-1])
+    sizes = torch.from_numpy(np.diff(offsets)).cuda()
+    seg = torch.repeat_interleave(torch.arange(k, device="cuda"), sizes)
+    up = work[1:] >= work[:-1]
+    first = torch.zeros(n, dtype=torch.bool, device="cuda")
+    starts = torch.from_numpy(offsets[:-1][np.diff(offsets) > 0]).cuda()
+    first[starts] = True
+    ok = bool((up | first[1:]).all())
+
+    def mix(x):
+        z = x.to(torch.int64) * -7046029254386353131  # 0x9e3779b97f4a7c15 as int64
+        z = z ^ (z >> 29)
+        return z * -4658895280553007687  # 0xbf58476d1ce4e5b9 as int64
+
+    a = torch.zeros(k, dtype=torch.int64, device="cuda").index_add_(0, seg, mix(pristine))
+    b = torch.zeros(k, dtype=torch.int64, device="cuda").index_add_(0, seg, mix(work))
+    return ok and bool(torch.equal(a, b))
 
 
 def record_bytes(kind):
@@ -219,7 +315,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": None,
-            "kernel": "k_partition (int32 keys, 256 threads x 16 keys per tile)",
+            "kernel": f"k_partition (int32 keys, {st['tile_keys']}-key tiles of 256 threads)",
             "bytes_per_launch": round(2 * r * part_keys / max(launches, 1)),
             "avg_launch_ms": round(part_ms / max(launches, 1), 4),
         },
@@ -244,8 +340,10 @@ def main():
             dms, dst, _, dpart_ms, dpart_keys, dok = run_workload(
                 torch, bqs, ctx, kind, nn, max(2, args.steps // 2), 1, seed=1)
             rb = record_bytes(kind)
-            ab = 2 * rb * (dst["partitioned_keys"] + dst["small_sorted_keys"]) + \
-                (rb if kind != "pairs_u64_u32" else 8) * dst["filled_keys"]
+            # equal runs: keys are written once; pairs also park and restore
+            # their payloads (side write + side read + final write)
+            fill_b = rb if kind != "pairs_u64_u32" else 8 + 3 * 4
+            ab = 2 * rb * (dst["partitioned_keys"] + dst["small_sorted_keys"]) + fill_b * dst["filled_keys"]
             dists[kind] = {
                 "n": nn, "ms": round(dms, 3), "Gkeys/s": round(nn / (dms * 1e-3) / 1e9, 3),
                 "alg_GBps": round(ab / (dms * 1e-3) / 1e9, 1),
@@ -255,6 +353,9 @@ def main():
                 "levels": dst["levels"], "correct": dok,
             }
         out["distributions"] = dists
+
+    if not args.no_batched:
+        out["segmented"] = batched_segments(torch, bqs, max(2, args.steps // 3), 1)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2, args.cpu_arrays)

@@ -73,7 +73,10 @@ typedef enum {
     BQS_PARAM_TILE_EPT = 5,     /* keys per thread in a partition tile (8, 16 or 32; 0 = auto)  */
     BQS_PARAM_GRID = 6,         /* workgroups per launch of the persistent kernels (0 = auto)  */
     BQS_PARAM_PROFILE = 7,      /* 1: count cycles and look-back rounds inside partition tiles */
-    BQS_PARAM_MODE = 8          /* BQS_MODE_LEVELS (default) or BQS_MODE_QUEUE                  */
+    BQS_PARAM_MODE = 8,         /* BQS_MODE_LEVELS (default) or BQS_MODE_QUEUE                  */
+    BQS_PARAM_GRAPH = 9         /* 1: capture the launches of a call into a HIP graph and replay
+                                   it for later calls with the same buffers, sizes and parameters
+                                   (see "Graph mode" below)                                     */
 } bqs_param;
 
 /* Execution modes (BQS_PARAM_MODE).
@@ -83,6 +86,19 @@ typedef enum {
  *           persistent kernel.  Closed: selecting it returns BQS_EINVAL (its
  *           kernel faulted on the device and the cause is not yet known). */
 typedef enum { BQS_MODE_LEVELS = 0, BQS_MODE_QUEUE = 1 } bqs_mode;
+
+/* Graph mode (BQS_PARAM_GRAPH = 1).  The first call with a given set of
+ * buffers (keys, vals, offsets, workspace), sizes and parameters sorts with
+ * the host-driven level loop and then captures that call's launches (one
+ * level more than it needed) into a HIP graph held by the context.  Later
+ * calls with the same set replay the graph with one hipGraphLaunch and one
+ * status read; if an input needs more levels than the graph holds, the
+ * host-driven loop finishes it.  Results are identical to the default mode.
+ * The graph reads the buffers' contents at replay time, so callers refill
+ * the same buffers between calls.  Per-level statistics (bqs_ctx_get_level)
+ * and kernel timings are not kept for replayed levels.  Changing any
+ * parameter drops the graph.  The graph is recorded on a stream the context
+ * owns (default priority) and replayed on the context's stream. */
 
 typedef struct {
     int64_t levels;             /* partition passes executed by the last call                  */
@@ -104,6 +120,7 @@ typedef struct {
     double prof_lookback_cycles;    /* wave 0 time from its scan result to the claimed range       */
     double prof_tile_cycles;        /* tile start to tile end                                      */
     double prof_load_cycles;        /* tile start to all keys loaded and counted                   */
+    int64_t graph_launches;         /* 1 if the call replayed a captured graph                     */
 } bqs_stats;
 
 typedef struct bqs_ctx bqs_ctx; /* opaque, host-side */

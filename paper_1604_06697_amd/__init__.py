@@ -43,6 +43,7 @@ PARAM_TILE_EPT = 5
 PARAM_GRID = 6
 PARAM_PROFILE = 7
 PARAM_MODE = 8
+PARAM_GRAPH = 9
 MODE_LEVELS, MODE_QUEUE = 0, 1
 
 _TORCH_DTYPES = {
@@ -90,6 +91,7 @@ class Stats(ctypes.Structure):
         ("prof_lookback_cycles", ctypes.c_double),
         ("prof_tile_cycles", ctypes.c_double),
         ("prof_load_cycles", ctypes.c_double),
+        ("graph_launches", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -188,6 +190,7 @@ class Context:
         "grid": PARAM_GRID,
         "profile": PARAM_PROFILE,
         "mode": PARAM_MODE,
+        "graph": PARAM_GRAPH,
     }
 
     def set_param(self, name: str, value: int):

@@ -35,6 +35,7 @@ __global__ void k_init_single(Args a) {
         c->lc[s].pad = 0;
     }
     c->error = 0;
+    c->levels = 0;
     c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
     for (int i = 0; i < 8; ++i) c->prof[i] = 0;
     const int64_t n = a.n;
@@ -66,6 +67,7 @@ __global__ void k_zero_ctl(Args a) {
         c->lc[s].pad = 0;
     }
     c->error = 0;
+    c->levels = 0;
     c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
     for (int i = 0; i < 8; ++i) c->prof[i] = 0;
 }
@@ -117,6 +119,7 @@ __global__ void k_init_segments(Args a) {
 // it also clears the tile's look-back status word.
 __global__ __launch_bounds__(256) void k_map(Args a) {
     Ctl* c = a.ctl;
+    if (c->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
     const int p = a.level & 1;
     const unsigned long long sc = c->lc[p].segs;
     const uint32_t nseg = static_cast<uint32_t>(sc);
@@ -160,6 +163,7 @@ __global__ void k_qclear(Args a) {
             c->lc[s].tile_next = 0;
         }
         c->error = 0;
+        c->levels = 0;
         c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
         for (int k = 0; k < 8; ++k) c->prof[k] = 0;
     }
@@ -287,6 +291,13 @@ struct bqs_ctx {
     int64_t grid = 0;
     int64_t profile = 0;
     int64_t mode = BQS_MODE_LEVELS;
+    int64_t graph = 0;
+    // graph mode: the captured launch sequence and the call it belongs to
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph_obj = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uint64_t> gkey;
+    int glevels = 0;
     int64_t queue_grid = 0;  // resident workgroups of the queue kernel (cached)
     bqs_stats stats{};
     bqs_status latched = BQS_OK;
@@ -408,6 +419,7 @@ int clamp_grid(uint64_t want, int64_t cap) {
 }
 
 void fill_stats(bqs_stats& stats, const Ctl& c) {
+    stats.levels = static_cast<int64_t>(c.levels);
     stats.partitioned_keys = static_cast<int64_t>(c.part_keys);
     stats.small_sorted_keys = static_cast<int64_t>(c.small_keys);
     stats.filled_keys = static_cast<int64_t>(c.fill_keys);
@@ -421,31 +433,17 @@ void fill_stats(bqs_stats& stats, const Ctl& c) {
 }
 
 bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented);
+void drop_graph(bqs_ctx* ctx);
 
-// The level loop shared by all entry points.
-bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
-    if (ctx->mode == BQS_MODE_QUEUE) return run_queue(ctx, o, a, segmented);
-    bqs_status st = ensure_device_state(ctx);
-    if (st != BQS_OK) return st;
+// Levels L0, L0+1, ... driven from the host: each level's counts are read
+// back before its launches are sized.  `cur` holds the lists of level L0.
+bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur, Timer& tm,
+                      bqs_stats& stats) {
     const hipStream_t s = ctx->stream;
-    Timer tm{ctx, ctx->timing != 0};
-    tm.resolve(ctx->stats);  // drop events a failed call may have left
-    bqs_stats stats{};
-    stats.tile_keys = o->tile_keys;
-    stats.small_cutoff = a.small_cut;
-
-    if (segmented) launch_init_segments(a, s);
-    else launch_init_single(a, s);
-    if (hipGetLastError() != hipSuccess) return BQS_EHIP;
-    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
-    if (ctx->pinned->error) return (ctx->pinned->error & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
-    LevelCtr cur = ctx->pinned->lc[0];
-
+    bqs_status st = BQS_OK;
     const int64_t level_cap = 4 * static_cast<int64_t>(a.depth_limit) + 64;
-    ctx->level_keys.clear();
-    ctx->level_ms.clear();
-    uint64_t part_before = 0;
-    for (int L = 0;; ++L) {
+    uint64_t part_before = ctx->pinned->part_keys;
+    for (int L = L0;; ++L) {
         a.level = L;
         const uint32_t nseg = static_cast<uint32_t>(cur.segs);
         const uint32_t ntile = static_cast<uint32_t>(cur.segs >> 32);
@@ -467,15 +465,16 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
         if (nseg == 0) break;
         if (L >= level_cap) return BQS_EOVERFLOW;
-        ctx->level_keys.push_back(0);
-        ctx->level_ms.push_back(0.0);
+        if (ctx->level_keys.size() <= static_cast<size_t>(L)) {
+            ctx->level_keys.resize(L + 1, 0);
+            ctx->level_ms.resize(L + 1, 0.0);
+        }
         tm.start();
         // one workgroup per tile (tiles are still claimed in order through the
         // level's ticket counter, which the look-back relies on)
         o->tile(a, static_cast<int>(ntile), s);
         tm.stop(2, L);
         stats.partition_launches++;
-        stats.levels++;
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
         if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
         tm.resolve(stats);
@@ -484,12 +483,159 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
         part_before = ctx->pinned->part_keys;
         cur = ctx->pinned->lc[(L + 1) & 1];
     }
+    return BQS_OK;
+}
+
+// Host-driven sort: init, then the level loop.
+bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
+    bqs_status st = ensure_device_state(ctx);
+    if (st != BQS_OK) return st;
+    const hipStream_t s = ctx->stream;
+    Timer tm{ctx, ctx->timing != 0};
+    tm.resolve(ctx->stats);  // drop events a failed call may have left
+    bqs_stats stats{};
+    stats.tile_keys = o->tile_keys;
+    stats.small_cutoff = a.small_cut;
+
+    if (segmented) launch_init_segments(a, s);
+    else launch_init_single(a, s);
+    if (hipGetLastError() != hipSuccess) return BQS_EHIP;
+    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+    if (ctx->pinned->error) return (ctx->pinned->error & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
+    ctx->level_keys.clear();
+    ctx->level_ms.clear();
+    if ((st = level_loop(ctx, o, a, 0, ctx->pinned->lc[0], tm, stats)) != BQS_OK) return st;
     if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
     tm.resolve(stats);
     if (ctx->pinned->error) return BQS_EOVERFLOW;
     fill_stats(stats, *ctx->pinned);
     ctx->stats = stats;
     return BQS_OK;
+}
+
+// ------------------------------------------------------------ graph mode --
+// The launches of a whole sort, captured once into a HIP graph and replayed.
+// A graph cannot read counts back, so every launch has a grid fixed at
+// capture time that covers the most work its level can hold, and the kernels
+// take the actual counts from the device (surplus workgroups leave at once).
+// The graph holds as many levels as the first, host-driven call of the same
+// shape needed; if a later input needs more, the host-driven loop takes over
+// at the first level the graph does not hold.
+
+std::vector<uint64_t> graph_key(const Ops* o, const Args& a, bool segmented) {
+    auto u = [](const void* p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); };
+    return {u(o), u(a.ctl), u(a.x_keys), u(a.x_vals), u(a.y_keys), u(a.offsets), static_cast<uint64_t>(a.n),
+            static_cast<uint64_t>(a.k), static_cast<uint64_t>(a.small_cut), static_cast<uint64_t>(a.sample_max),
+            static_cast<uint64_t>(a.pivot_mode), static_cast<uint64_t>(a.depth_limit),
+            static_cast<uint64_t>(a.prof), segmented ? 1ull : 0ull};
+}
+
+void drop_graph(bqs_ctx* ctx) {
+    if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph_obj) hipGraphDestroy(ctx->graph_obj);
+    ctx->gexec = nullptr;
+    ctx->graph_obj = nullptr;
+    ctx->gkey.clear();
+    ctx->glevels = 0;
+}
+
+// Most tiles level L can hold: n/T plus two partial tiles per segment; a
+// level has at most min(k * 2^L, cap_seg) segments.
+uint64_t tile_bound(const Args& a, int L) {
+    const uint64_t T = static_cast<uint64_t>(a.tile_keys);
+    uint64_t segs = static_cast<uint64_t>(a.k);
+    for (int i = 0; i < L && segs < a.cap_seg; ++i) segs *= 2;
+    segs = std::min<uint64_t>(segs, a.cap_seg);
+    return std::min<uint64_t>(static_cast<uint64_t>(a.n) / T + 2 * segs + 2, a.cap_tile);
+}
+
+bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, Args a, bool segmented, int levels) {
+    drop_graph(ctx);
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return BQS_EHIP;
+    const hipStream_t cs = ctx->cap_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return BQS_EHIP;
+    if (segmented) launch_init_segments(a, cs);
+    else launch_init_single(a, cs);
+    for (int L = 0; L < levels; ++L) {
+        a.level = L;
+        o->plan(a, 2048, cs);
+        o->map(a, 4096, cs);
+        for (int cls = 0; cls < kSmallClasses; ++cls)
+            if (o->small[cls]) o->small[cls](a, 2048, cs);
+        const uint64_t tb = tile_bound(a, L);
+        if (tb > 0x7fffffffull) {
+            hipGraph_t g = nullptr;
+            hipStreamEndCapture(cs, &g);
+            if (g) hipGraphDestroy(g);
+            return BQS_EINVAL;
+        }
+        o->tile(a, static_cast<int>(std::max<uint64_t>(tb, 1)), cs);
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return BQS_EHIP;
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return BQS_EHIP;
+    }
+    ctx->graph_obj = g;
+    ctx->gexec = ex;
+    ctx->glevels = levels;
+    return BQS_OK;
+}
+
+bqs_status run_graph(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
+    const std::vector<uint64_t> key = graph_key(o, a, segmented);
+    if (!ctx->gexec || key != ctx->gkey) {
+        // first call of this shape: sort host-driven, then capture as many
+        // levels as it took (the last one has no segments left to partition)
+        bqs_status st = run_levels(ctx, o, a, segmented);
+        if (st != BQS_OK) return st;
+        const int levels = static_cast<int>(ctx->stats.levels) + 1;
+        if ((st = capture_graph(ctx, o, a, segmented, levels)) != BQS_OK) return st;
+        ctx->gkey = key;
+        return BQS_OK;
+    }
+    bqs_status st = ensure_device_state(ctx);
+    if (st != BQS_OK) return st;
+    Timer tm{ctx, ctx->timing != 0};
+    tm.resolve(ctx->stats);
+    bqs_stats stats{};
+    stats.tile_keys = o->tile_keys;
+    stats.small_cutoff = a.small_cut;
+    ctx->level_keys.clear();
+    ctx->level_ms.clear();
+    if (hipGraphLaunch(ctx->gexec, ctx->stream) != hipSuccess) return BQS_EHIP;
+    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+    tm.resolve(stats);
+    if (ctx->pinned->error) return (ctx->pinned->error & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
+    stats.graph_launches = 1;
+    // work the graph's levels did not reach: continue host-driven
+    const LevelCtr cur = ctx->pinned->lc[ctx->glevels & 1];
+    bool more = cur.segs != 0 || cur.fills != 0;
+    for (int c = 0; c < kSmallClasses; ++c) more = more || cur.smalls[c] != 0;
+    if (more) {
+        if ((st = level_loop(ctx, o, a, ctx->glevels, cur, tm, stats)) != BQS_OK) return st;
+        if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+        tm.resolve(stats);
+        if (ctx->pinned->error) return BQS_EOVERFLOW;
+    }
+    fill_stats(stats, *ctx->pinned);
+    ctx->stats = stats;
+    if (more) {
+        // hold the deeper recursion from now on
+        if ((st = capture_graph(ctx, o, a, segmented, static_cast<int>(stats.levels) + 1)) != BQS_OK) return st;
+        ctx->gkey = key;
+    }
+    return BQS_OK;
+}
+
+// The entry points' common driver.
+bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
+    if (ctx->mode == BQS_MODE_QUEUE) return run_queue(ctx, o, a, segmented);
+    if (ctx->graph) return run_graph(ctx, o, a, segmented);
+    return run_levels(ctx, o, a, segmented);
 }
 
 // Work-queue mode: seed, drain with one persistent launch, bin and sort the
@@ -611,6 +757,8 @@ bqs_status bqs_ctx_create(bqs_ctx** out) {
 
 void bqs_ctx_destroy(bqs_ctx* ctx) {
     if (!ctx) return;
+    drop_graph(ctx);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     if (ctx->pinned) hipHostFree(ctx->pinned);
     for (auto& p : ctx->pending) {
         ctx->ev_pool.push_back(p.a);
@@ -651,6 +799,10 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             break;
         case BQS_PARAM_GRID: ctx->grid = value; break;
         case BQS_PARAM_PROFILE: ctx->profile = value ? 1 : 0; break;
+        case BQS_PARAM_GRAPH:
+            ctx->graph = value ? 1 : 0;
+            drop_graph(ctx);
+            break;
         case BQS_PARAM_MODE:
             // The work-queue kernel took a memory-aperture fault on its first
             // input with partition tiles (n = 8193 int32) and the cause is not
@@ -675,6 +827,7 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_GRID: return ctx->grid;
         case BQS_PARAM_PROFILE: return ctx->profile;
         case BQS_PARAM_MODE: return ctx->mode;
+        case BQS_PARAM_GRAPH: return ctx->graph;
         default: return -1;
     }
 }

@@ -115,7 +115,7 @@ struct QCtl {
 struct Ctl {
     LevelCtr lc[2];
     unsigned int error;
-    unsigned int pad;
+    unsigned int levels;  // levels that partitioned at least one segment
     unsigned long long part_keys;
     unsigned long long small_keys;
     unsigned long long fill_keys;

@@ -262,15 +262,17 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
     __shared__ R s_pick;
 
     Ctl* c = a.ctl;
+    if (c->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
     const int p = a.level & 1, q = p ^ 1;
     const int tid = threadIdx.x;
+    const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
     if (blockIdx.x == 0 && tid == 0) {
         c->lc[q].segs = 0;
         c->lc[q].fills = 0;
         for (int k = 0; k < kSmallClasses; ++k) c->lc[q].smalls[k] = 0;
         c->lc[q].tile_next = 0;
+        if (nseg) c->levels += 1;
     }
-    const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
     unsigned long long my_keys = 0, my_tiles = 0;  // statistics, one atomic per block
 
@@ -616,6 +618,9 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     const int p = a.level & 1, q = p ^ 1;
     const int tid = threadIdx.x;
     const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
+    // a launch may cover more workgroups than the level has tiles (a grid
+    // fixed in advance); the surplus leaves before taking a ticket
+    if (blockIdx.x >= ntiles || (c->error & ERR_OFFSETS)) return;
     if (a.prof && tid < 6) s_prof[tid] = 0;
     if (tid == 0) {
         const uint32_t t = atomicAdd(&c->lc[p].tile_next, 1u);
@@ -1260,6 +1265,7 @@ __global__ __launch_bounds__(256) void k_small(Args a, int cls) {
     __shared__ VS s_v[HV ? G * P : 1];
 
     Ctl* c = a.ctl;
+    if (c->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
     const int p = a.level & 1;
     const int tid = threadIdx.x;
     const int grp = tid / NTH;

@@ -251,6 +251,83 @@ def test_segments_bad_offsets_reported(torch_mod, bqs):
     assert e.value.status == 1
 
 
+# ------------------------------------------------------------ graph mode --
+
+def test_graph_replays_match_oracle(torch_mod, bqs, oracle):
+    """Graph mode on one set of buffers: the first call runs host-driven and
+    captures; later calls replay the graph.  Eager work and synchronisations
+    run between the replays, and every replay is compared with the oracle.
+    A uniform input after a few-distinct one needs more levels than the
+    first graph holds: the host-driven loop finishes it and a deeper graph
+    is captured for the next calls."""
+    torch = torch_mod
+    keys0, offsets = W.segmented_i32(300, 11, 4.0, 16.0)
+    n = keys0.size
+    ctx = bqs.Context(graph=1)
+    buf = torch.empty(n, dtype=torch.int32, device="cuda")
+    off = torch.from_numpy(offsets).cuda()
+    seq = [("few_distinct", 3), ("uniform", 4), ("uniform", 5), ("few_distinct", 6),
+           ("reverse", 0), ("all_equal", 0), ("uniform", 7)]
+    for i, (fam, seed) in enumerate(seq):
+        a = W.I32_FAMILIES[fam](n, seed)
+        note(f"graph replay {i}: segments {fam} seed {seed} n={n}")
+        buf.copy_(torch.from_numpy(a))
+        junk = (buf.to(torch.float32) * 2.0).sum()  # eager work on the same stream
+        ctx.sort_segments(buf, off)
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        assert_same_bits(buf.cpu().numpy(), oracle.sort_segments(a, offsets))
+        s = ctx.stats()
+        assert s["graph_launches"] == (0 if i == 0 else 1)
+        assert s["small_sorted_keys"] + s["filled_keys"] <= n
+
+
+def test_graph_single_array_and_pairs(torch_mod, bqs, oracle):
+    torch = torch_mod
+    n = 1_000_003
+    ctx = bqs.Context(graph=1)
+    buf = torch.empty(n, dtype=torch.int32, device="cuda")
+    for r in range(3):
+        a = W.uniform_i32(n, 20 + r)
+        note(f"graph single array replay {r}")
+        buf.copy_(torch.from_numpy(a))
+        ctx.sort(buf)
+        torch.cuda.synchronize()
+        assert_same_bits(buf.cpu().numpy(), oracle.sort(a))
+        assert ctx.stats()["graph_launches"] == (0 if r == 0 else 1)
+    m = 300_000
+    kb = torch.empty(m, dtype=torch.int64, device="cuda")
+    vb = torch.empty(m, dtype=torch.int32, device="cuda")
+    for r in range(3):
+        k, v = W.uniform_u64_pairs(m, 30 + r)
+        note(f"graph pairs replay {r}")
+        kb.copy_(torch.from_numpy(k.view(np.int64)))
+        vb.copy_(torch.from_numpy(v.view(np.int32)))
+        ctx.sort_pairs(kb, vb, key_type="u64")
+        torch.cuda.synchronize()
+        ko = kb.cpu().numpy().view(np.uint64)
+        vo = vb.cpu().numpy().view(np.uint32)
+        assert_same_bits(ko, oracle.sort(k))
+        assert np.array_equal(k[vo.astype(np.int64)], ko)
+
+
+def test_graph_bad_offsets_on_replay(torch_mod, bqs):
+    torch = torch_mod
+    keys = W.uniform_i32(100_000, 0)
+    good = np.array([0, 40_000, 60_000, 100_000], dtype=np.int64)
+    ctx = bqs.Context(graph=1)
+    buf = to_dev(torch, keys)
+    off = torch.from_numpy(good).cuda()
+    note("graph capture for offsets check")
+    ctx.sort_segments(buf, off)
+    torch.cuda.synchronize()
+    off.copy_(torch.tensor([0, 60_000, 40_000, 100_000], dtype=torch.int64))
+    note("graph replay with malformed offsets")
+    with pytest.raises(bqs.BqsError) as e:
+        ctx.sort_segments(buf, off)
+    assert e.value.status == 1
+
+
 # ------------------------------------------------------------- contract --
 
 def test_workspace_too_small_is_rejected(torch_mod, bqs):
@@ -279,6 +356,7 @@ def test_stats_account_for_every_key(torch_mod, bqs):
         done = s["small_sorted_keys"] + s["filled_keys"]
         assert 0.99 * a.size <= done <= a.size
         assert s["levels"] == s["partition_launches"] >= 1
+        assert s["graph_launches"] == 0
         assert s["partition_ms"] > 0
 
 
