@@ -74,9 +74,16 @@ typedef enum {
     BQS_PARAM_GRID = 6,         /* workgroups per launch of the persistent kernels (0 = auto)  */
     BQS_PARAM_PROFILE = 7,      /* 1: count cycles and look-back rounds inside partition tiles */
     BQS_PARAM_MODE = 8,         /* BQS_MODE_LEVELS (default) or BQS_MODE_QUEUE                  */
-    BQS_PARAM_GRAPH = 9         /* 1: capture the launches of a call into a HIP graph and replay
+    BQS_PARAM_GRAPH = 9,        /* 1: capture the launches of a call into a HIP graph and replay
                                    it for later calls with the same buffers, sizes and parameters
                                    (see "Graph mode" below)                                     */
+    BQS_PARAM_LOOKBACK = 10     /* how a partition tile claims its output ranges.  0 (default):
+                                   keys-only sorts move the segment's two cursors with one atomic
+                                   add per tile (the paper's cursors l and r, Algorithm 3), so
+                                   runs land in claim order; pairs always use the decoupled
+                                   look-back.  1: every tile uses the look-back, runs land in
+                                   tile order and the intermediate layout is the same on every
+                                   run.  Sorted output is identical either way.                 */
 } bqs_param;
 
 /* Execution modes (BQS_PARAM_MODE).

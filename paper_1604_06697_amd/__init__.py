@@ -44,6 +44,7 @@ PARAM_GRID = 6
 PARAM_PROFILE = 7
 PARAM_MODE = 8
 PARAM_GRAPH = 9
+PARAM_LOOKBACK = 10
 MODE_LEVELS, MODE_QUEUE = 0, 1
 
 _TORCH_DTYPES = {
@@ -191,6 +192,7 @@ class Context:
         "profile": PARAM_PROFILE,
         "mode": PARAM_MODE,
         "graph": PARAM_GRAPH,
+        "lookback": PARAM_LOOKBACK,
     }
 
     def set_param(self, name: str, value: int):

@@ -292,6 +292,7 @@ struct bqs_ctx {
     int64_t profile = 0;
     int64_t mode = BQS_MODE_LEVELS;
     int64_t graph = 0;
+    int64_t lookback = 0;  // 1: keys-only tiles also claim by decoupled look-back
     // graph mode: the captured launch sequence and the call it belongs to
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph_obj = nullptr;
@@ -473,6 +474,7 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         // one workgroup per tile (tiles are still claimed in order through the
         // level's ticket counter, which the look-back relies on)
         o->tile(a, static_cast<int>(ntile), s);
+        if (o->complete && a.claim) o->complete(a, clamp_grid((nseg + 255) / 256, 4096), s);
         tm.stop(2, L);
         stats.partition_launches++;
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
@@ -527,7 +529,7 @@ std::vector<uint64_t> graph_key(const Ops* o, const Args& a, bool segmented) {
     return {u(o), u(a.ctl), u(a.x_keys), u(a.x_vals), u(a.y_keys), u(a.offsets), static_cast<uint64_t>(a.n),
             static_cast<uint64_t>(a.k), static_cast<uint64_t>(a.small_cut), static_cast<uint64_t>(a.sample_max),
             static_cast<uint64_t>(a.pivot_mode), static_cast<uint64_t>(a.depth_limit),
-            static_cast<uint64_t>(a.prof), segmented ? 1ull : 0ull};
+            static_cast<uint64_t>(a.prof), static_cast<uint64_t>(a.claim), segmented ? 1ull : 0ull};
 }
 
 void drop_graph(bqs_ctx* ctx) {
@@ -571,6 +573,7 @@ bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, Args a, bool segmented, int
             return BQS_EINVAL;
         }
         o->tile(a, static_cast<int>(std::max<uint64_t>(tb, 1)), cs);
+        if (o->complete && a.claim) o->complete(a, 1024, cs);
     }
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return BQS_EHIP;
@@ -726,6 +729,7 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
     a.tile_keys = o->tile_keys;
     a.prof = static_cast<int>(ctx->profile);
+    a.claim = ctx->lookback ? 0 : 1;
     a.queue = queue ? 1 : 0;
     if (queue) {
         a.qctl = reinterpret_cast<QCtl*>(w + L.qctl);
@@ -803,6 +807,7 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             ctx->graph = value ? 1 : 0;
             drop_graph(ctx);
             break;
+        case BQS_PARAM_LOOKBACK: ctx->lookback = value ? 1 : 0; break;
         case BQS_PARAM_MODE:
             // The work-queue kernel took a memory-aperture fault on its first
             // input with partition tiles (n = 8193 int32) and the cause is not
@@ -828,6 +833,7 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_PROFILE: return ctx->profile;
         case BQS_PARAM_MODE: return ctx->mode;
         case BQS_PARAM_GRAPH: return ctx->graph;
+        case BQS_PARAM_LOOKBACK: return ctx->lookback;
         default: return -1;
     }
 }

@@ -39,6 +39,9 @@ struct SegDesc {
     uint64_t pivot_raw;  // pivot as stored bits
     uint32_t t0, nt;     // tiles [t0, t0 + nt) of this level belong to the segment
     uint32_t depth, pad;
+    // cursor claims (keys only): low 32 bits keys already placed in the left
+    // run, high 32 bits in the right run (cleared by the plan kernel)
+    unsigned long long cursor;
 };
 
 // Per-tile copy of what a partition tile needs, written by the map kernel so
@@ -148,6 +151,7 @@ struct Args {
     int depth_limit;
     int tile_keys;
     int prof;
+    int claim;  // 1: keys-only tiles claim their ranges with the segment's cursor
     // work-queue mode
     int queue;
     QCtl* qctl;
@@ -167,6 +171,9 @@ struct Ops {
     void (*small[kSmallClasses])(const Args&, int grid, hipStream_t);  // nullptr beyond small_max
     int small_per_block[kSmallClasses];  // segments one workgroup sorts at once
     void (*tile)(const Args&, int grid, hipStream_t);
+    // segment completion after a partition launch whose tiles claimed with
+    // cursors (keys only; nullptr where tiles always use the look-back)
+    void (*complete)(const Args&, int grid, hipStream_t);
     // work-queue mode: clear + seed the queue, drain it with `grid` workgroups
     void (*qinit)(const Args&, int grid, hipStream_t);
     void (*qrun)(const Args&, int grid, hipStream_t);

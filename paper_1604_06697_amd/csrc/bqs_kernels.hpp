@@ -203,6 +203,7 @@ __device__ inline void push_segment(const Args& a, int slot, int64_t lo, int64_t
         d.nt = nt;
         d.depth = depth;
         d.pad = 0;
+        d.cursor = 0;
         a.segs[slot][idx] = d;
     } else {
         if (m == 1 && slot == 0) return;
@@ -324,6 +325,7 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
         if (tid == 0) {
             sd->pivot = static_cast<uint64_t>(K::ord(piv));
             sd->pivot_raw = static_cast<uint64_t>(piv);
+            sd->cursor = 0;
             my_keys += static_cast<unsigned long long>(m);
             my_tiles += sd->nt;
         }
@@ -381,6 +383,7 @@ struct TileIO {
     void* vdst;
     void* side;
     unsigned long long* status;
+    unsigned long long* cursor;  // non-null: claim ranges with this cursor instead of the look-back
     int64_t lo, hi;
     uint64_t pivot;
     uint32_t j;
@@ -504,14 +507,24 @@ __device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned lon
     const uint32_t ngt = static_cast<uint32_t>((tot >> FW) & FM);
     const uint32_t neq = HV ? static_cast<uint32_t>((static_cast<uint64_t>(tot) >> (2 * FW)) & FM) : 0u;
 
-    // wave 0 claims the output ranges (decoupled look-back over the status
-    // words of the segment's earlier tiles) while the other waves already
-    // stage their keys in LDS
+    // wave 0 claims the output ranges while the other waves already stage
+    // their keys in LDS: either with the segment's two cursors (one atomic
+    // add moves the left cursor by nlt and the right one by ngt, the paper's
+    // cursors l and r advancing a block at a time) or by a decoupled
+    // look-back over the status words of the segment's earlier tiles (runs
+    // laid out in tile order, so the layout is the same on every run)
     if (wv == 0) {
         const uint64_t t_lb = prof ? cycles() : 0;
         uint64_t Lx = 0, Gx = 0;
         unsigned long long* st_me = io.status + j;
-        if (j == 0) {
+        if (io.cursor) {
+            if (lane == 0) {
+                const unsigned long long got =
+                    atomicAdd(io.cursor, (static_cast<unsigned long long>(ngt) << 32) | nlt);
+                Lx = got & 0xffffffffull;
+                Gx = got >> 32;
+            }
+        } else if (j == 0) {
             if (lane == 0) st_status(st_me, st_pack(kStInc, nlt, ngt));
         } else {
             if (lane == 0) st_status(st_me, st_pack(kStAgg, nlt, ngt));
@@ -639,26 +652,55 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     io.vdst = p ? a.x_vals : a.y_vals;
     io.side = a.side;
     io.status = a.status + td.t0;
+    SegDesc* seg = &a.segs[p][td.si];
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    // payloads keep the look-back: their equal-key runs are parked by tile order
+    const bool use_cursor = !HV && a.claim != 0;
+    io.cursor = use_cursor ? &seg->cursor : nullptr;
     io.lo = td.lo;
     io.hi = td.hi;
     io.pivot = td.pivot;
     io.j = tile - td.t0;
     const TileOut r = tile_partition<DT, V, NT, EPT>(io, a.prof ? s_prof : nullptr);
-    if (!r.ok) {
-        // inconsistent look-back result: report it (nothing was written)
-        if (tid == 0) atomicOr(&c->error, ERR_OVERFLOW);
-    } else if (r.last && tid == 0) {
-        // segment completion: the segment's last tile knows the totals
-        const SegDesc& sd = a.segs[p][td.si];
+    if (!r.ok && tid == 0) atomicOr(&c->error, ERR_OVERFLOW);  // inconsistent claim: nothing was written
+    if (!use_cursor && tid == 0 && r.ok && r.last) {
+        // segment completion (look-back): the segment's last tile knows the
+        // totals.  With cursors the completion kernel does this after the
+        // launch, when every tile has claimed.
         const int64_t Lt = r.Lx + r.nlt, Gt = r.Gx + r.ngt;
         const int64_t Et = (td.hi - td.lo) - Lt - Gt;
-        push_fill(a, q, td.lo + Lt, Et, td.lo, sd.pivot_raw);
-        push_segment(a, q, td.lo, td.lo + Lt, sd.depth + 1);
-        push_segment(a, q, td.hi - Gt, td.hi, sd.depth + 1);
+        push_fill(a, q, td.lo + Lt, Et, td.lo, seg->pivot_raw);
+        push_segment(a, q, td.lo, td.lo + Lt, seg->depth + 1);
+        push_segment(a, q, td.hi - Gt, td.hi, seg->depth + 1);
     }
     if (a.prof) {
         __syncthreads();
         if (tid < 6) atomicAdd(&c->prof[tid], s_prof[tid]);
+    }
+}
+
+// Segment completion for cursor claims, level L: one thread per segment
+// reads the final cursor (keys < pivot, keys > pivot) and appends the equal
+// run and the two children to the level L+1 lists.  Runs as its own launch
+// after the partition launch, so every tile's claim is visible.
+template <class V>
+__global__ __launch_bounds__(256) void k_complete(Args a) {
+    Ctl* c = a.ctl;
+    if (c->error & ERR_OFFSETS) return;
+    const int p = a.level & 1, q = p ^ 1;
+    const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    for (uint32_t si = blockIdx.x * blockDim.x + threadIdx.x; si < nseg; si += gridDim.x * blockDim.x) {
+        const SegDesc sd = a.segs[p][si];
+        const int64_t Lt = static_cast<int64_t>(sd.cursor & 0xffffffffull);
+        const int64_t Gt = static_cast<int64_t>(sd.cursor >> 32);
+        const int64_t Et = (sd.hi - sd.lo) - Lt - Gt;
+        if (Et < 0) {
+            atomicOr(&c->error, ERR_OVERFLOW);
+            continue;
+        }
+        push_fill(a, q, sd.lo + Lt, Et, sd.lo, sd.pivot_raw);
+        push_segment(a, q, sd.lo, sd.lo + Lt, sd.depth + 1);
+        push_segment(a, q, sd.hi - Gt, sd.hi, sd.depth + 1);
     }
 }
 
@@ -936,6 +978,7 @@ __global__ __launch_bounds__(NT) void k_queue(Args a) {
             io.vdst = sd.buf ? a.x_vals : a.y_vals;
             io.side = a.side;
             io.status = a.qstatus + sd.st_base;
+            io.cursor = nullptr;
             io.lo = sd.lo;
             io.hi = sd.hi;
             io.pivot = sd.pivot;
@@ -1374,6 +1417,9 @@ struct Launch {
     static void tile(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_partition<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
     }
+    static void complete(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_complete<V>), dim3(grid), dim3(256), 0, s, a);
+    }
     // work-queue mode: clear, seed one workgroup per input segment
     static void qinit(const Args& a, int grid, hipStream_t s) {
         launch_qclear(a, s);
@@ -1404,6 +1450,7 @@ struct Launch {
              SmallFn<DT, V, 32, 256, (SMAX >= 8192)>::get()},
             {4, 4, 4, 4, 4, 1, 1, 1},
             &tile,
+            std::is_same<V, NoVal>::value ? &complete : nullptr,
             &qinit,
             &qrun,
             &qblocks_per_cu};

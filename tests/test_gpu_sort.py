@@ -251,6 +251,39 @@ def test_segments_bad_offsets_reported(torch_mod, bqs):
     assert e.value.status == 1
 
 
+# ---------------------------------------------------------- claim modes --
+
+@pytest.mark.parametrize("lookback", [0, 1])
+def test_claim_modes_match_oracle(torch_mod, bqs, oracle, lookback):
+    """Keys-only tiles claim their output ranges with the segment's cursors
+    (default) or by decoupled look-back; both must give the oracle's keys,
+    across tile-aligned and ragged sizes and duplicate-heavy inputs."""
+    ctx = bqs.Context(lookback=lookback, small_cutoff=1024)
+    for fam in ("uniform", "few_distinct", "sorted", "all_equal"):
+        for n in (8192 * 3, 8192 * 7 + 5, 1 << 20):
+            a = W.I32_FAMILIES[fam](n, 9)
+            note(f"claim lookback={lookback} {fam} n={n}")
+            assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+    keys, offsets = W.segmented_i32(500, 2, 4.0, 16.0)
+    note(f"claim lookback={lookback} segments n={keys.size}")
+    assert_same_bits(gpu_segments(torch_mod, bqs, keys, offsets, ctx), oracle.sort_segments(keys, offsets))
+
+
+def test_lookback_layout_is_deterministic(torch_mod, bqs):
+    """With the look-back every tile's runs land in tile order, so pivots and
+    the whole recursion repeat exactly: the per-level counts of two runs are
+    equal."""
+    a = W.uniform_i32(3_000_017, 4)
+    ctx = bqs.Context(lookback=1, timing=1)
+    runs = []
+    for r in range(2):
+        note(f"lookback determinism run {r}")
+        gpu_sort(torch_mod, bqs, a, ctx)
+        s = ctx.stats()
+        runs.append((s["levels"], s["partitioned_keys"], s["small_sorted_keys"], [k for k, _ in ctx.levels()]))
+    assert runs[0] == runs[1]
+
+
 # ------------------------------------------------------------ graph mode --
 
 def test_graph_replays_match_oracle(torch_mod, bqs, oracle):
