@@ -474,7 +474,7 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         // one workgroup per tile (tiles are still claimed in order through the
         // level's ticket counter, which the look-back relies on)
         o->tile(a, static_cast<int>(ntile), s);
-        if (o->complete && a.claim) o->complete(a, clamp_grid((nseg + 255) / 256, 4096), s);
+        o->complete(a, clamp_grid((nseg + 255) / 256, 4096), s);
         tm.stop(2, L);
         stats.partition_launches++;
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
@@ -573,7 +573,7 @@ bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, Args a, bool segmented, int
             return BQS_EINVAL;
         }
         o->tile(a, static_cast<int>(std::max<uint64_t>(tb, 1)), cs);
-        if (o->complete && a.claim) o->complete(a, 1024, cs);
+        o->complete(a, 1024, cs);
     }
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return BQS_EHIP;

@@ -171,8 +171,8 @@ struct Ops {
     void (*small[kSmallClasses])(const Args&, int grid, hipStream_t);  // nullptr beyond small_max
     int small_per_block[kSmallClasses];  // segments one workgroup sorts at once
     void (*tile)(const Args&, int grid, hipStream_t);
-    // segment completion after a partition launch whose tiles claimed with
-    // cursors (keys only; nullptr where tiles always use the look-back)
+    // segment completion after a partition launch: children and equal runs
+    // of every segment of the level
     void (*complete)(const Args&, int grid, hipStream_t);
     // work-queue mode: clear + seed the queue, drain it with `grid` workgroups
     void (*qinit)(const Args&, int grid, hipStream_t);

@@ -628,7 +628,7 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_prof[6];
     Ctl* c = a.ctl;
-    const int p = a.level & 1, q = p ^ 1;
+    const int p = a.level & 1;
     const int tid = threadIdx.x;
     const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
     // a launch may cover more workgroups than the level has tiles (a grid
@@ -663,45 +663,160 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     io.j = tile - td.t0;
     const TileOut r = tile_partition<DT, V, NT, EPT>(io, a.prof ? s_prof : nullptr);
     if (!r.ok && tid == 0) atomicOr(&c->error, ERR_OVERFLOW);  // inconsistent claim: nothing was written
-    if (!use_cursor && tid == 0 && r.ok && r.last) {
-        // segment completion (look-back): the segment's last tile knows the
-        // totals.  With cursors the completion kernel does this after the
-        // launch, when every tile has claimed.
-        const int64_t Lt = r.Lx + r.nlt, Gt = r.Gx + r.ngt;
-        const int64_t Et = (td.hi - td.lo) - Lt - Gt;
-        push_fill(a, q, td.lo + Lt, Et, td.lo, seg->pivot_raw);
-        push_segment(a, q, td.lo, td.lo + Lt, seg->depth + 1);
-        push_segment(a, q, td.hi - Gt, td.hi, seg->depth + 1);
-    }
     if (a.prof) {
         __syncthreads();
         if (tid < 6) atomicAdd(&c->prof[tid], s_prof[tid]);
     }
 }
 
-// Segment completion for cursor claims, level L: one thread per segment
-// reads the final cursor (keys < pivot, keys > pivot) and appends the equal
-// run and the two children to the level L+1 lists.  Runs as its own launch
-// after the partition launch, so every tile's claim is visible.
+// Segment completion, level L (Section 2: the pivot leaves the recursion, the
+// two sides recurse).  One thread per segment reads the segment's totals --
+// the final cursor pair (cursor claims) or the inclusive status word of its
+// last tile (look-back) -- and appends the equal run and the two children to
+// the level L+1 lists.  Runs as its own launch after the partition launch, so
+// every tile's claim and output is visible.  Appends are aggregated per wave:
+// a wave prefix sum of the lanes' requests, one atomic add per wave and list.
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
+    const int lo = __shfl(static_cast<int>(static_cast<uint32_t>(v)), src, 64);
+    const int hi = __shfl(static_cast<int>(static_cast<uint32_t>(v >> 32)), src, 64);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+// All 64 lanes: lane's first slot of a wave-wide append of `inc` to *ctr.
+__device__ __forceinline__ uint64_t wave_append(unsigned long long* ctr, uint64_t inc, int lane) {
+    const uint64_t incl = wave_inclusive_sum(inc, lane);
+    const uint64_t total = bcast64(incl, 63);
+    uint64_t base = 0;
+    if (lane == 63 && total) base = atomicAdd(ctr, static_cast<unsigned long long>(total));
+    return bcast64(base, 63) + incl - inc;
+}
+
 template <class V>
 __global__ __launch_bounds__(256) void k_complete(Args a) {
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
     Ctl* c = a.ctl;
     if (c->error & ERR_OFFSETS) return;
     const int p = a.level & 1, q = p ^ 1;
+    const int lane = lane_id();
+    const bool cursor = !HV && a.claim != 0;
     const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
-    for (uint32_t si = blockIdx.x * blockDim.x + threadIdx.x; si < nseg; si += gridDim.x * blockDim.x) {
-        const SegDesc sd = a.segs[p][si];
-        const int64_t Lt = static_cast<int64_t>(sd.cursor & 0xffffffffull);
-        const int64_t Gt = static_cast<int64_t>(sd.cursor >> 32);
-        const int64_t Et = (sd.hi - sd.lo) - Lt - Gt;
-        if (Et < 0) {
-            atomicOr(&c->error, ERR_OVERFLOW);
-            continue;
+    const int64_t T = a.tile_keys;
+    const int64_t S = a.small_cut;
+    unsigned long long fill_keys = 0;
+    // wave-uniform trip count: lanes past the list take part with nothing
+    for (uint32_t base = blockIdx.x * blockDim.x; base < nseg; base += gridDim.x * blockDim.x) {
+        const uint32_t si = base + threadIdx.x;
+        const bool valid = si < nseg;
+        int64_t lo = 0, hi = 0, Lt = 0, Gt = 0;
+        uint32_t depth = 0;
+        uint64_t raw = 0;
+        if (valid) {
+            const SegDesc sd = a.segs[p][si];
+            lo = sd.lo;
+            hi = sd.hi;
+            depth = sd.depth + 1;
+            raw = sd.pivot_raw;
+            if (cursor) {
+                Lt = static_cast<int64_t>(sd.cursor & 0xffffffffull);
+                Gt = static_cast<int64_t>(sd.cursor >> 32);
+            } else {
+                const uint64_t st = ld_status(&a.status[sd.t0 + sd.nt - 1]);
+                Lt = static_cast<int64_t>((st >> 31) & kM31);
+                Gt = static_cast<int64_t>(st & kM31);
+            }
+            if (Lt + Gt > hi - lo) {
+                atomicOr(&c->error, ERR_OVERFLOW);
+                Lt = Gt = 0;
+                hi = lo;  // nothing to append
+            }
         }
-        push_fill(a, q, sd.lo + Lt, Et, sd.lo, sd.pivot_raw);
-        push_segment(a, q, sd.lo, sd.lo + Lt, sd.depth + 1);
-        push_segment(a, q, sd.hi - Gt, sd.hi, sd.depth + 1);
+        const int64_t Et = (hi - lo) - Lt - Gt;
+        // children: [lo, lo+Lt) and [hi-Gt, hi).  kind 1: partitioned at
+        // L+1; kind 2: small sort; 0: nothing (empty, or one key already in
+        // the caller's buffer)
+        const int64_t clo[2] = {lo, hi - Gt};
+        const int64_t chi[2] = {lo + Lt, hi};
+        int kind[2], cls[2];
+        uint32_t nt[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t m = chi[h] - clo[h];
+            kind[h] = m <= 0 ? 0 : (m > S ? 1 : ((m == 1 && q == 0) ? 0 : 2));
+            nt[h] = kind[h] == 1 ? static_cast<uint32_t>((chi[h] + T - 1) / T - clo[h] / T) : 0u;
+            cls[h] = kind[h] == 2 ? small_class(m) : -1;
+        }
+        // segments of level L+1 (count | tiles << 32)
+        const uint64_t sinc = static_cast<uint64_t>((kind[0] == 1) + (kind[1] == 1)) |
+                              (static_cast<uint64_t>(nt[0] + nt[1]) << 32);
+        if (__ballot(sinc != 0)) {
+            const uint64_t at = wave_append(&c->lc[q].segs, sinc, lane);
+            uint32_t idx = static_cast<uint32_t>(at);
+            uint64_t t0 = at >> 32;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (kind[h] != 1) continue;
+                if (idx >= a.cap_seg || t0 + nt[h] > a.cap_tile) {
+                    atomicOr(&c->error, ERR_OVERFLOW);
+                } else {
+                    SegDesc d{};
+                    d.lo = clo[h];
+                    d.hi = chi[h];
+                    d.t0 = static_cast<uint32_t>(t0);
+                    d.nt = nt[h];
+                    d.depth = depth;
+                    a.segs[q][idx] = d;
+                }
+                ++idx;
+                t0 += nt[h];
+            }
+        }
+        // small segments, per size class
+        for (int k = 0; k < kSmallClasses; ++k) {
+            const bool h0 = cls[0] == k, h1 = cls[1] == k;
+            const uint64_t b0 = __ballot(h0), b1 = __ballot(h1);
+            if ((b0 | b1) == 0) continue;
+            const uint32_t total = static_cast<uint32_t>(__popcll(b0) + __popcll(b1));
+            uint32_t first = 0;
+            if (lane == 0) first = atomicAdd(&c->lc[q].smalls[k], total);
+            first = static_cast<uint32_t>(__shfl(static_cast<int>(first), 0, 64));
+            uint32_t idx = first + mbcnt(b0) + mbcnt(b1);
+            SmallItem* dst = a.smalls[q] + static_cast<size_t>(k) * a.cap_small;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (cls[h] != k) continue;
+                if (idx >= a.cap_small) atomicOr(&c->error, ERR_OVERFLOW);
+                else dst[idx] = SmallItem{clo[h], chi[h]};
+                ++idx;
+            }
+        }
+        // equal run: written at level L+1 (keys: the pivot; pairs: the
+        // payloads parked in the side buffer at [lo, lo + Et))
+        const uint32_t nch = Et > 0 ? static_cast<uint32_t>((Et + kFillChunk - 1) / kFillChunk) : 0u;
+        const uint64_t finc = Et > 0 ? (1ull | (static_cast<uint64_t>(nch) << 32)) : 0ull;
+        if (__ballot(finc != 0)) {
+            const uint64_t at = wave_append(&c->lc[q].fills, finc, lane);
+            const uint32_t idx = static_cast<uint32_t>(at);
+            if (Et > 0) {
+                if (idx >= a.cap_fill) {
+                    atomicOr(&c->error, ERR_OVERFLOW);
+                } else {
+                    FillItem f;
+                    f.dst = lo + Lt;
+                    f.len = Et;
+                    f.side = lo;
+                    f.raw = raw;
+                    f.chunk0 = static_cast<uint32_t>(at >> 32);
+                    f.pad0 = 0;
+                    f.pad1 = 0;
+                    a.fills[q][idx] = f;
+                }
+                fill_keys += static_cast<unsigned long long>(Et);
+            }
+        }
     }
+    fill_keys = wave_sum(fill_keys);
+    if (lane == 0 && fill_keys) atomicAdd(&c->fill_keys, fill_keys);
 }
 
 // ---------------------------------------------------------------------------
@@ -1129,21 +1244,39 @@ __device__ __forceinline__ bool item_less(const SItem<O, true>& a, const SItem<O
     return (a.k < b.k) | ((a.k == b.k) & (a.i < b.i));
 }
 
-// a <- smaller, b <- larger
-template <class It>
-__device__ __forceinline__ void cx(It& a, It& b) {
-    const bool s = item_less(b, a);
-    const It lo = s ? b : a;
-    const It hi = s ? a : b;
-    a = lo;
-    b = hi;
+// a <- smaller, b <- larger.  Fields are selected one by one: a select
+// between whole items would pick an address and keep the register arrays
+// in private memory.
+template <class O>
+__device__ __forceinline__ void cx(SItem<O, false>& a, SItem<O, false>& b) {
+    const O x = a.k, y = b.k;
+    const bool s = y < x;
+    a.k = s ? y : x;
+    b.k = s ? x : y;
+}
+template <class O>
+__device__ __forceinline__ void cx(SItem<O, true>& a, SItem<O, true>& b) {
+    const O xk = a.k, yk = b.k;
+    const uint32_t xi = a.i, yi = b.i;
+    const bool s = (yk < xk) | ((yk == xk) & (yi < xi));
+    a.k = s ? yk : xk;
+    b.k = s ? xk : yk;
+    a.i = s ? yi : xi;
+    b.i = s ? xi : yi;
 }
 
 // v <- min(v, o) for the lower item of a pair, max(v, o) for the upper one
-template <class It>
-__device__ __forceinline__ void keep(It& v, const It& o, bool lower) {
-    const bool s = item_less(o, v);
-    v = (s == lower) ? o : v;
+template <class O>
+__device__ __forceinline__ void keep(SItem<O, false>& v, const SItem<O, false>& o, bool lower) {
+    const bool s = o.k < v.k;
+    v.k = (s == lower) ? o.k : v.k;
+}
+template <class O>
+__device__ __forceinline__ void keep(SItem<O, true>& v, const SItem<O, true>& o, bool lower) {
+    const bool s = (o.k < v.k) | ((o.k == v.k) & (o.i < v.i));
+    const bool take = s == lower;
+    v.k = take ? o.k : v.k;
+    v.i = take ? o.i : v.i;
 }
 
 template <int E>
@@ -1327,6 +1460,8 @@ __global__ __launch_bounds__(256) void k_small(Args a, int cls) {
     O* sk = s_k + grp * PS;
     uint32_t* si = HV ? s_i + grp * PS : s_i;
     VS* sv = HV ? s_v + grp * P : s_v;
+    __shared__ unsigned long long s_done[G];  // keys sorted by each group (statistics)
+    unsigned long long my_keys = 0;
 
     for (uint32_t base = blockIdx.x * G; base < nsm; base += gridDim.x * G) {
         const uint32_t it = base + grp;
@@ -1381,8 +1516,16 @@ __global__ __launch_bounds__(256) void k_small(Args a, int cls) {
                 if constexpr (HV) xv[lo + x] = sv[si[lds_slot<O>(x)]];
             }
         }
-        if (t == 0 && have) atomicAdd(&c->small_keys, static_cast<unsigned long long>(m));
+        my_keys += static_cast<unsigned long long>(m);
         __syncthreads();
+    }
+    // one statistics atomic per workgroup
+    if (t == 0) s_done[grp] = my_keys;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long sum = 0;
+        for (int g = 0; g < G; ++g) sum += s_done[g];
+        if (sum) atomicAdd(&c->small_keys, sum);
     }
 }
 
@@ -1450,7 +1593,7 @@ struct Launch {
              SmallFn<DT, V, 32, 256, (SMAX >= 8192)>::get()},
             {4, 4, 4, 4, 4, 1, 1, 1},
             &tile,
-            std::is_same<V, NoVal>::value ? &complete : nullptr,
+            &complete,
             &qinit,
             &qrun,
             &qblocks_per_cu};
