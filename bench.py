@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-dists", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched segmented workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=100_000)
     ap.add_argument("--cpu-log2", type=int, default=26, help="CPU sample: arrays of 2^x keys")
     ap.add_argument("--cpu-arrays", type=int, default=6)
     return ap.parse_args()
@@ -285,6 +287,60 @@ def measured_traffic():
         return None
 
 
+def serving(torch, requests, seed=11, budget=64 << 30, workers=3):
+    """Serving loop: Poisson arrivals of mixed requests (sizes log-uniform in
+    [2^10, 2^24]; 50 % int32, 30 % float64, 20 % uint64+uint32 pairs), admitted
+    under an HBM budget and batched continuously.  The arrival rate is 0.7 x
+    the service's saturated capacity, measured first on a burst of requests
+    that all arrive at once.  The same trace is then replayed with one plain
+    sort call per request, in arrival order on one stream."""
+    from paper_1604_06697_amd import serve
+
+    def fresh(tr):
+        return [serve.Request(r.rid, r.kind, r.n, r.arrival) for r in tr]
+
+    burst = serve.make_trace(max(200, requests // 50), qps=0.0, seed=seed + 1)
+    _, mk, _ = serve.run_service(burst, budget, workers=workers, seed_base=1 << 40)
+    cap = serve.latency_summary(burst, mk)
+    qps = 0.7 * len(burst) / mk
+    trace = serve.make_trace(requests, qps=qps, seed=seed)
+    sample = [r.rid for r in trace if r.rid % 100 == 0]
+    trace, mk, svc = serve.run_service(trace, budget, workers=workers, seed_base=0, keep_inputs=sample)
+    ok = check_requests(torch, [trace[i] for i in sample])
+    out = {
+        "workload": f"{requests} requests, Poisson arrivals at {qps:.0f}/s (0.7 x saturated capacity), "
+                    "sizes log-uniform [2^10, 2^24], 50% int32 / 30% float64 / 20% uint64+uint32 pairs, "
+                    f"{budget >> 30} GiB HBM budget, {workers} batch workers",
+        "qps": round(qps, 1),
+        "saturated": {"requests": cap["requests"], "Gkeys/s": cap["Gkeys/s"]},
+        "service": dict(serve.latency_summary(trace, mk), batches=svc.batches,
+                        peak_budget_GiB=round(svc.budget.peak / 2**30, 2)),
+        "correct_sample": ok,
+    }
+    base = fresh(trace)
+    base, mk_b = serve.run_one_per_launch(base, seed_base=0, keep_inputs=sample)
+    out["one_per_launch"] = dict(serve.latency_summary(base, mk_b),
+                                 correct_sample=check_requests(torch, [base[i] for i in sample]))
+    return out
+
+
+def check_requests(torch, reqs):
+    """Each sampled request's output against torch.sort of its input (for
+    pairs: the unsigned order of the keys, and payload = index into the
+    input)."""
+    sign = torch.tensor(-(2**63), dtype=torch.int64, device="cuda")
+    for r in reqs:
+        if r.kind == "pairs":
+            ref = torch.sort(r.input_keys ^ sign).values ^ sign
+            if not (torch.equal(r.out_keys, ref) and
+                    torch.equal(r.input_keys[r.out_vals.long()], r.out_keys)):
+                return False
+        elif not torch.equal(r.out_keys, torch.sort(r.input_keys).values):
+            return False
+        r.input_keys = r.input_vals = None
+    return True
+
+
 def record_bytes(kind):
     if kind.startswith("i32"):
         return 4
@@ -414,6 +470,9 @@ def main():
 
     if not args.no_batched:
         out["segmented"] = batched_segments(torch, bqs, max(2, args.steps // 3), 1)
+
+    if not args.no_serve:
+        out["serving"] = serving(torch, args.serve_requests)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_log2, args.cpu_arrays)

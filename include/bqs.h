@@ -190,6 +190,12 @@ bqs_status bqs_sort_pairs(void* keys, void* vals, int64_t n, bqs_dtype key, int3
 bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int64_t n_total,
                              bqs_dtype dtype, bqs_ctx* ctx);
 
+/* Segmented form of bqs_sort_pairs: each segment's (key, payload) records
+ * are sorted by key, payloads moving with their keys; offsets, n_total and
+ * error behaviour as for bqs_sort_segments, vals as for bqs_sort_pairs. */
+bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offsets, int64_t k,
+                                   int64_t n_total, bqs_dtype key, int32_t val_bytes, bqs_ctx* ctx);
+
 /* Synchronises the context's stream and returns the latched device status. */
 bqs_status bqs_ctx_sync_status(bqs_ctx* ctx);
 

@@ -61,7 +61,7 @@ EXPORTED = [
     "bqs_ctx_create", "bqs_ctx_destroy", "bqs_ctx_set_stream", "bqs_ctx_set_workspace",
     "bqs_ctx_set_param", "bqs_ctx_get_param", "bqs_ctx_get_stats", "bqs_ctx_get_level",
     "bqs_workspace_bytes",
-    "bqs_sort", "bqs_sort_pairs", "bqs_sort_segments", "bqs_ctx_sync_status",
+    "bqs_sort", "bqs_sort_pairs", "bqs_sort_segments", "bqs_sort_segments_pairs", "bqs_ctx_sync_status",
     "bqs_status_str", "bqs_version",
 ]
 
@@ -121,6 +121,7 @@ def _load(path: str = LIBRARY) -> ctypes.CDLL:
         "bqs_sort": ([vp, i64, ctypes.c_int, vp], st),
         "bqs_sort_pairs": ([vp, vp, i64, ctypes.c_int, i32, vp], st),
         "bqs_sort_segments": ([vp, vp, i64, i64, ctypes.c_int, vp], st),
+        "bqs_sort_segments_pairs": ([vp, vp, vp, i64, i64, ctypes.c_int, i32, vp], st),
         "bqs_ctx_sync_status": ([vp], st),
         "bqs_status_str": ([st], ctypes.c_char_p),
         "bqs_version": ([], ctypes.c_int),
@@ -275,6 +276,30 @@ class Context:
                    "bqs_sort_segments")
         return keys
 
+    def sort_segments_pairs(self, keys: torch.Tensor, vals: torch.Tensor, offsets: torch.Tensor,
+                            key_type=None):
+        self._check_tensor(keys, "keys")
+        self._check_tensor(vals, "vals")
+        self._check_tensor(offsets, "offsets")
+        if keys.numel() != vals.numel() or keys.device != vals.device:
+            raise BqsError(1, "keys and vals differ in length or device")
+        if offsets.dtype != torch.int64 or offsets.device != keys.device:
+            raise BqsError(1, "offsets must be int64 on the keys' device")
+        k = offsets.numel() - 1
+        if k < 0:
+            raise BqsError(1, "offsets must hold k+1 >= 1 entries")
+        vb = vals.element_size()
+        code = _key_code(keys, key_type)
+        n = keys.numel()
+        with self._lock, torch.cuda.device(keys.device):
+            self._prepare(keys.device, self.workspace_bytes(n, code, vb, max(k, 1)))
+            _check(lib.bqs_sort_segments_pairs(ctypes.c_void_p(keys.data_ptr()),
+                                               ctypes.c_void_p(vals.data_ptr()),
+                                               ctypes.c_void_p(offsets.data_ptr()), k, n, code, vb,
+                                               self._h),
+                   "bqs_sort_segments_pairs")
+        return keys, vals
+
 
 _default: Context | None = None
 
@@ -297,3 +322,8 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, ctx: Context | None = Non
 def sort_segments(keys: torch.Tensor, offsets: torch.Tensor, ctx: Context | None = None,
                   key_type=None):
     return (ctx or default_context()).sort_segments(keys, offsets, key_type)
+
+
+def sort_segments_pairs(keys: torch.Tensor, vals: torch.Tensor, offsets: torch.Tensor,
+                        ctx: Context | None = None, key_type=None):
+    return (ctx or default_context()).sort_segments_pairs(keys, vals, offsets, key_type)

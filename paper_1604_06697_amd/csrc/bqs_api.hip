@@ -910,6 +910,24 @@ bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int6
     return finish(ctx, run_sort(ctx, o, a, true));
 }
 
+bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offsets, int64_t k,
+                                   int64_t n_total, bqs_dtype key, int32_t val_bytes, bqs_ctx* ctx) {
+    if (!ctx || k < 0 || n_total < 0 || (n_total > 0 && (!keys || !vals)) || (k > 0 && !offsets))
+        return BQS_EINVAL;
+    if (val_bytes != 4 && val_bytes != 8) return BQS_EDTYPE;
+    const Ops* o = select_ops(ctx, key, val_bytes);
+    if (!o) return BQS_EDTYPE;
+    if (k == 0 || n_total <= 1) {
+        ctx->stats = bqs_stats{};
+        return BQS_OK;
+    }
+    Args a;
+    bqs_status st = prepare(ctx, o, n_total, key, val_bytes, k, keys, vals, a);
+    if (st != BQS_OK) return st;
+    a.offsets = offsets;
+    return finish(ctx, run_sort(ctx, o, a, true));
+}
+
 bqs_status bqs_ctx_sync_status(bqs_ctx* ctx) {
     if (!ctx) return BQS_EINVAL;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return BQS_EHIP;

@@ -242,6 +242,32 @@ def test_segments_exhaustive_permutations(torch_mod, bqs, oracle):
     assert_same_bits(gpu_segments(torch_mod, bqs, seqs, offs), oracle.sort_segments(seqs, offs))
 
 
+def test_segments_pairs_match_oracle(torch_mod, bqs, oracle):
+    """Segmented pairs: per segment, keys equal the oracle's and every
+    payload (the record's original index) travels with its key."""
+    torch = torch_mod
+    sizes = np.r_[W.log_uniform_sizes(300, 8, 0.0, 15.0), [0, 1, 2, 70_000]].astype(np.int64)
+    offsets = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    n = int(offsets[-1])
+    for kt, gen in (("u64", lambda: W.uniform_u64_pairs(n, 12)[0]),
+                    ("u64", lambda: W.tied_u64_pairs(n, 13)[0]),
+                    ("f64", lambda: W.uniform_f64(n, 14))):
+        keys = gen()
+        vals = np.arange(n, dtype=np.uint32)
+        note(f"segments pairs {kt} n={n}")
+        tk = to_dev(torch, keys)
+        tv = torch.from_numpy(vals.view(np.int32)).cuda()
+        bqs.sort_segments_pairs(tk, tv, torch.from_numpy(offsets).cuda(), key_type=kt)
+        torch.cuda.synchronize()
+        ko = from_dev(tk, keys.dtype)
+        vo = tv.cpu().numpy().view(np.uint32).astype(np.int64)
+        for i in range(len(sizes)):
+            lo, hi = offsets[i], offsets[i + 1]
+            assert_same_bits(ko[lo:hi], oracle.sort(keys[lo:hi]))
+            assert np.all((vo[lo:hi] >= lo) & (vo[lo:hi] < hi))
+        assert np.array_equal(keys[vo].view(np.uint64), ko.view(np.uint64))
+
+
 def test_segments_bad_offsets_reported(torch_mod, bqs):
     keys = W.uniform_i32(1000, 0)
     bad = np.array([0, 600, 500, 1000], dtype=np.int64)
