@@ -64,7 +64,9 @@ typedef enum {
 /* Tunable parameters (bqs_ctx_set_param).  Values <= 0 restore defaults. */
 typedef enum {
     BQS_PARAM_SMALL_CUTOFF = 1, /* segments of at most this many keys are sorted inside one
-                                   workgroup's LDS (clamped to the compiled maximum)          */
+                                   workgroup's LDS (clamped to the compiled maximum: 8192 for
+                                   4-byte keys, 4096 for 8-byte keys, 2048 for pairs; default
+                                   4096, or the maximum where that is smaller)                */
     BQS_PARAM_SAMPLE_MAX = 2,   /* largest pivot sample (odd, <= 255); the pivot is the median
                                    of the sample (Section 2, pivot selection)                  */
     BQS_PARAM_PIVOT_MODE = 3,   /* 0: median of a stratified sample; 3: median of first, middle

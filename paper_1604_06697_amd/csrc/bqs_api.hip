@@ -33,6 +33,7 @@ __global__ void k_init_single(Args a) {
         for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
         c->lc[s].tile_next = 0;
         c->lc[s].pad = 0;
+        c->lc[s].keys = 0;
     }
     c->error = 0;
     c->levels = 0;
@@ -49,6 +50,9 @@ __global__ void k_init_single(Args a) {
         d.nt = nt;
         a.segs[0][0] = d;
         c->lc[0].segs = (static_cast<unsigned long long>(nt) << 32) | 1ull;
+        c->part_keys = static_cast<unsigned long long>(n);
+        c->lc[0].keys = static_cast<unsigned long long>(n);
+        c->tiles = nt;
     } else if (n >= 2) {
         const int cls = small_class(n);
         a.smalls[0][static_cast<size_t>(cls) * a.cap_small] = SmallItem{0, n};
@@ -65,6 +69,7 @@ __global__ void k_zero_ctl(Args a) {
         for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
         c->lc[s].tile_next = 0;
         c->lc[s].pad = 0;
+        c->lc[s].keys = 0;
     }
     c->error = 0;
     c->levels = 0;
@@ -74,43 +79,50 @@ __global__ void k_zero_ctl(Args a) {
 
 // One thread per segment: validate the offsets, then route the segment to
 // the level-0 partition list or straight to the small sort.
-__global__ void k_init_segments(Args a) {
+__global__ __launch_bounds__(256) void k_init_segments(Args a) {
+    __shared__ unsigned long long s_keys, s_tiles;
+    if (threadIdx.x == 0) s_keys = s_tiles = 0;
+    __syncthreads();
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.k) return;
-    const int64_t lo = a.offsets[i], hi = a.offsets[i + 1];
-    const bool bad = lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) ||
-                     (i == a.k - 1 && hi != a.n) || hi - lo >= (int64_t(1) << 31);
-    if (bad) {
-        atomicOr(&a.ctl->error, ERR_OFFSETS);
-        return;
-    }
-    const int64_t m = hi - lo;
     Ctl* c = a.ctl;
-    if (m > a.small_cut) {
-        const int64_t T = a.tile_keys;
-        const uint32_t nt = static_cast<uint32_t>((hi + T - 1) / T - lo / T);
-        const unsigned long long r =
-            atomicAdd(&c->lc[0].segs, (static_cast<unsigned long long>(nt) << 32) | 1ull);
-        const uint32_t idx = static_cast<uint32_t>(r);
-        const uint64_t t0 = r >> 32;
-        if (idx >= a.cap_seg || t0 + nt > a.cap_tile) {
-            atomicOr(&c->error, ERR_OVERFLOW);
-            return;
+    if (i < a.k) {
+        const int64_t lo = a.offsets[i], hi = a.offsets[i + 1];
+        const bool bad = lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) ||
+                         (i == a.k - 1 && hi != a.n) || hi - lo >= (int64_t(1) << 31);
+        const int64_t m = hi - lo;
+        if (bad) {
+            atomicOr(&c->error, ERR_OFFSETS);
+        } else if (m > a.small_cut) {
+            const int64_t T = a.tile_keys;
+            const uint32_t nt = static_cast<uint32_t>((hi + T - 1) / T - lo / T);
+            const unsigned long long r =
+                atomicAdd(&c->lc[0].segs, (static_cast<unsigned long long>(nt) << 32) | 1ull);
+            const uint32_t idx = static_cast<uint32_t>(r);
+            const uint64_t t0 = r >> 32;
+            if (idx >= a.cap_seg || t0 + nt > a.cap_tile) {
+                atomicOr(&c->error, ERR_OVERFLOW);
+            } else {
+                SegDesc d{};
+                d.lo = lo;
+                d.hi = hi;
+                d.t0 = static_cast<uint32_t>(t0);
+                d.nt = nt;
+                a.segs[0][idx] = d;
+                atomicAdd(&s_keys, static_cast<unsigned long long>(m));
+                atomicAdd(&s_tiles, static_cast<unsigned long long>(nt));
+            }
+        } else if (m >= 2) {
+            const int cls = small_class(m);
+            const uint32_t idx = atomicAdd(&c->lc[0].smalls[cls], 1u);
+            if (idx >= a.cap_small) atomicOr(&c->error, ERR_OVERFLOW);
+            else a.smalls[0][static_cast<size_t>(cls) * a.cap_small + idx] = SmallItem{lo, hi};
         }
-        SegDesc d{};
-        d.lo = lo;
-        d.hi = hi;
-        d.t0 = static_cast<uint32_t>(t0);
-        d.nt = nt;
-        a.segs[0][idx] = d;
-    } else if (m >= 2) {
-        const int cls = small_class(m);
-        const uint32_t idx = atomicAdd(&c->lc[0].smalls[cls], 1u);
-        if (idx >= a.cap_small) {
-            atomicOr(&c->error, ERR_OVERFLOW);
-            return;
-        }
-        a.smalls[0][static_cast<size_t>(cls) * a.cap_small + idx] = SmallItem{lo, hi};
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_keys) {
+        atomicAdd(&c->part_keys, s_keys);
+        atomicAdd(&c->lc[0].keys, s_keys);
+        atomicAdd(&c->tiles, s_tiles);
     }
 }
 
@@ -161,6 +173,7 @@ __global__ void k_qclear(Args a) {
             c->lc[s].fills = 0;
             for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
             c->lc[s].tile_next = 0;
+            c->lc[s].keys = 0;
         }
         c->error = 0;
         c->levels = 0;
@@ -328,7 +341,7 @@ const Ops* select_ops(const bqs_ctx* ctx, int dtype, int val_bytes) {
 }
 
 int64_t eff_small_cut(const bqs_ctx* ctx, const Ops* o) {
-    int64_t s = ctx && ctx->small_cut > 0 ? ctx->small_cut : o->small_max;
+    int64_t s = ctx && ctx->small_cut > 0 ? ctx->small_cut : o->small_default;
     if (s > o->small_max) s = o->small_max;
     if (s < 2) s = 2;
     return s;
@@ -443,14 +456,14 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
     const hipStream_t s = ctx->stream;
     bqs_status st = BQS_OK;
     const int64_t level_cap = 4 * static_cast<int64_t>(a.depth_limit) + 64;
-    uint64_t part_before = ctx->pinned->part_keys;
     for (int L = L0;; ++L) {
         a.level = L;
         const uint32_t nseg = static_cast<uint32_t>(cur.segs);
         const uint32_t ntile = static_cast<uint32_t>(cur.segs >> 32);
         const uint32_t nchunk = static_cast<uint32_t>(cur.fills >> 32);
         tm.start();
-        o->plan(a, clamp_grid(std::max<uint64_t>(nseg, nchunk), 2048), s);
+        // plan: one wave per segment (4 per workgroup), one workgroup per fill chunk
+        o->plan(a, clamp_grid(std::max<uint64_t>((nseg + 3) / 4, nchunk), 16384), s);
         if (nseg) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
         tm.stop(0, L);
         for (int cls = 0; cls < kSmallClasses; ++cls) {
@@ -470,6 +483,7 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
             ctx->level_keys.resize(L + 1, 0);
             ctx->level_ms.resize(L + 1, 0.0);
         }
+        ctx->level_keys[L] = static_cast<int64_t>(cur.keys);
         tm.start();
         // one workgroup per tile (tiles are still claimed in order through the
         // level's ticket counter, which the look-back relies on)
@@ -481,8 +495,6 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
         tm.resolve(stats);
         if (ctx->pinned->error) return BQS_EOVERFLOW;
-        ctx->level_keys[L] = static_cast<int64_t>(ctx->pinned->part_keys - part_before);
-        part_before = ctx->pinned->part_keys;
         cur = ctx->pinned->lc[(L + 1) & 1];
     }
     return BQS_OK;

@@ -73,6 +73,7 @@ struct LevelCtr {
     unsigned int smalls[kSmallClasses];  // small segments per size class
     unsigned int tile_next;    // tile claim counter of the level that consumes this slot
     unsigned int pad;
+    unsigned long long keys;   // keys in the segments of this list (statistics)
 };
 
 enum : unsigned { ERR_OVERFLOW = 1u, ERR_OFFSETS = 2u, ERR_STALL = 4u };
@@ -165,7 +166,8 @@ struct Args {
 
 struct Ops {
     int tile_keys;  // keys per partition tile
-    int small_max;  // capacity of the in-LDS small sort
+    int small_max;      // capacity of the in-LDS small sort
+    int small_default;  // default cutoff (measured best for the tile size)
     void (*plan)(const Args&, int grid, hipStream_t);
     void (*map)(const Args&, int grid, hipStream_t);
     void (*small[kSmallClasses])(const Args&, int grid, hipStream_t);  // nullptr beyond small_max

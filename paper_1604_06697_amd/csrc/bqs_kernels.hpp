@@ -258,82 +258,89 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
     using K = KeyT<DT>;
     using R = typename K::raw;
     constexpr bool HV = !std::is_same<V, NoVal>::value;
-    static_assert(NT >= kMaxSample + 1, "one thread per sample");
-    __shared__ R s_samp[kMaxSample + 1];
-    __shared__ R s_pick;
+    constexpr int NW = NT / 64;  // one wave per segment
+    static_assert(kMaxSample < 4 * 64, "a lane holds at most four samples");
+    __shared__ R s_samp[NW][kMaxSample + 1];
+    __shared__ R s_pick[NW];
 
     Ctl* c = a.ctl;
     if (c->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
     const int p = a.level & 1, q = p ^ 1;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
     if (blockIdx.x == 0 && tid == 0) {
         c->lc[q].segs = 0;
         c->lc[q].fills = 0;
         for (int k = 0; k < kSmallClasses; ++k) c->lc[q].smalls[k] = 0;
         c->lc[q].tile_next = 0;
+        c->lc[q].keys = 0;
         if (nseg) c->levels += 1;
     }
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
-    unsigned long long my_keys = 0, my_tiles = 0;  // statistics, one atomic per block
+    R* ws = s_samp[wv];
 
-    for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
-        SegDesc* sd = &a.segs[p][si];
-        const int64_t lo = sd->lo, hi = sd->hi, m = hi - lo;
-        const uint32_t depth = sd->depth;
-        int k;
-        if (a.pivot_mode == 3 && depth < static_cast<uint32_t>(a.depth_limit)) {
-            k = 3;
-        } else {
-            // about sqrt(m)/4 samples, odd, within [7, sample_max]; past the
-            // depth limit the largest sample is used
-            int64_t kk = static_cast<int64_t>(sqrt(static_cast<double>(m))) / 4;
-            if (depth >= static_cast<uint32_t>(a.depth_limit)) kk = a.sample_max;
-            if (kk > a.sample_max) kk = a.sample_max;
-            if (kk < 7) kk = 7;
-            if (kk > m) kk = m;
-            k = static_cast<int>(kk) | 1;
-            if (k > m) k -= 2;
+    // block-uniform trip count (the barriers below); wave wv takes segment base + wv
+    for (uint32_t base = blockIdx.x * NW; base < nseg; base += gridDim.x * NW) {
+        const uint32_t si = base + wv;
+        const bool valid = si < nseg;
+        SegDesc* sd = &a.segs[p][valid ? si : 0];
+        int64_t lo = 0, hi = 0, m = 0;
+        uint32_t depth = 0;
+        int k = 0;
+        if (valid) {
+            lo = sd->lo;
+            hi = sd->hi;
+            m = hi - lo;
+            depth = sd->depth;
+            if (a.pivot_mode == 3 && depth < static_cast<uint32_t>(a.depth_limit)) {
+                k = 3;
+            } else {
+                // about sqrt(m)/4 samples, odd, within [7, sample_max]; past the
+                // depth limit the largest sample is used
+                int64_t kk = static_cast<int64_t>(sqrt(static_cast<double>(m))) / 4;
+                if (depth >= static_cast<uint32_t>(a.depth_limit)) kk = a.sample_max;
+                if (kk > a.sample_max) kk = a.sample_max;
+                if (kk < 7) kk = 7;
+                if (kk > m) kk = m;
+                k = static_cast<int>(kk) | 1;
+                if (k > m) k -= 2;
+            }
         }
-        if (tid < k) {
+        // sample i sits in stratum i at a hashed offset (first, middle and
+        // last key for the median of three)
+        for (int i = lane; i < k; i += 64) {
             int64_t pos;
             if (k == 3) {
-                pos = tid == 0 ? lo : (tid == 1 ? lo + m / 2 : hi - 1);
+                pos = i == 0 ? lo : (i == 1 ? lo + m / 2 : hi - 1);
             } else {
                 const int64_t stride = m / k;
                 const uint64_t h = mix64((static_cast<uint64_t>(lo) * 0x9e3779b97f4a7c15ull) ^
                                          (static_cast<uint64_t>(hi) << 17) ^
-                                         (static_cast<uint64_t>(tid) << 40) ^ depth);
-                pos = lo + tid * stride + static_cast<int64_t>(h % static_cast<uint64_t>(stride));
+                                         (static_cast<uint64_t>(i) << 40) ^ depth);
+                pos = lo + i * stride + static_cast<int64_t>(h % static_cast<uint64_t>(stride));
             }
-            s_samp[tid] = src[pos];
+            ws[i] = src[pos];
         }
         __syncthreads();
-        if (tid < k) {
-            // rank of this sample: smaller samples, plus equal ones of lower index
-            const R mine = s_samp[tid];
+        // the median: the sample of rank k/2 (ties broken by sample index)
+        for (int i = lane; i < k; i += 64) {
+            const R mine = ws[i];
             const auto om = K::ord(mine);
             int rank = 0;
             for (int j = 0; j < k; ++j) {
-                const auto oj = K::ord(s_samp[j]);
-                rank += (oj < om) | ((oj == om) & (j < tid));
+                const auto oj = K::ord(ws[j]);
+                rank += (oj < om) | ((oj == om) & (j < i));
             }
-            if (rank == k / 2) s_pick = mine;
+            if (rank == k / 2) s_pick[wv] = mine;
         }
         __syncthreads();
-        const R piv = s_pick;
-        if (tid == 0) {
+        if (valid && lane == 0) {
+            const R piv = s_pick[wv];
             sd->pivot = static_cast<uint64_t>(K::ord(piv));
             sd->pivot_raw = static_cast<uint64_t>(piv);
             sd->cursor = 0;
-            my_keys += static_cast<unsigned long long>(m);
-            my_tiles += sd->nt;
         }
         __syncthreads();
-    }
-    if (tid == 0 && my_keys) {
-        atomicAdd(&c->part_keys, my_keys);
-        atomicAdd(&c->tiles, my_tiles);
     }
 
     // equal-key runs of the previous level
@@ -703,7 +710,9 @@ __global__ __launch_bounds__(256) void k_complete(Args a) {
     const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
     const int64_t T = a.tile_keys;
     const int64_t S = a.small_cut;
-    unsigned long long fill_keys = 0;
+    // statistics of this thread's appends: equal keys, and keys / tiles the
+    // next level partitions
+    unsigned long long fill_keys = 0, next_keys = 0, next_tiles = 0;
     // wave-uniform trip count: lanes past the list take part with nothing
     for (uint32_t base = blockIdx.x * blockDim.x; base < nseg; base += gridDim.x * blockDim.x) {
         const uint32_t si = base + threadIdx.x;
@@ -771,6 +780,13 @@ __global__ __launch_bounds__(256) void k_complete(Args a) {
                 t0 += nt[h];
             }
         }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (kind[h] == 1) {
+                next_keys += static_cast<unsigned long long>(chi[h] - clo[h]);
+                next_tiles += nt[h];
+            }
+        }
         // small segments, per size class
         for (int k = 0; k < kSmallClasses; ++k) {
             const bool h0 = cls[0] == k, h1 = cls[1] == k;
@@ -816,7 +832,16 @@ __global__ __launch_bounds__(256) void k_complete(Args a) {
         }
     }
     fill_keys = wave_sum(fill_keys);
-    if (lane == 0 && fill_keys) atomicAdd(&c->fill_keys, fill_keys);
+    next_keys = wave_sum(next_keys);
+    next_tiles = wave_sum(next_tiles);
+    if (lane == 0) {
+        if (fill_keys) atomicAdd(&c->fill_keys, fill_keys);
+        if (next_keys) {
+            atomicAdd(&c->part_keys, next_keys);
+            atomicAdd(&c->lc[q].keys, next_keys);
+        }
+        if (next_tiles) atomicAdd(&c->tiles, next_tiles);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1167,16 +1192,14 @@ __global__ __launch_bounds__(NT) void k_qseed(Args a) {
 // Small-segment sort (the paper's Insertionsort stage, Section 2).
 //
 // A group of NTH threads (one wave, or a 256-thread workgroup) sorts one
-// segment of at most E*NTH keys with Batcher's bitonic network held in
-// registers: thread t keeps items t*E .. t*E+E-1.  A compare-exchange whose
-// two items differ in a register bit runs inside the thread, one that
-// differs in a lane bit exchanges through a lane shuffle, one that differs
-// in a wave bit exchanges through LDS.  Every merge of two sorted halves
-// starts with the mirror step (item x against x ^ (2^k - 1)), after which
-// all compare-exchanges put the smaller item at the lower index, so no
-// direction bit is needed.  Padding items are larger than any key; pairs
-// carry the key's index in the segment as a tie-break, which makes the
-// network stable and keeps padding behind real keys.
+// segment of at most E*NTH keys: thread t holds items t*E .. t*E+E-1, sorts
+// them with a bitonic network in registers (every merge of two sorted halves
+// starts with the mirror step, item x against x ^ (2^k - 1), after which all
+// compare-exchanges put the smaller item at the lower index), and the group
+// merges the sorted runs through LDS (merge_sort below).  Padding items are
+// larger than any key; pairs carry the key's index in the segment as a
+// tie-break, which keeps padding behind real keys and makes the result
+// unique.
 
 template <class O, bool HV>
 struct SItem;
@@ -1189,51 +1212,6 @@ struct SItem<O, true> {
     O k;
     uint32_t i;
 };
-
-// Value of lane (lane ^ M) for a mask M fixed at compile time.  Masks with a
-// DPP form stay in the vector ALU (quad permutes for 1, 2, 3; row half-mirror
-// for 7; row mirror for 15); other masks below 32 use ds_swizzle in its xor
-// mode (no address operand); 32 and above go through ds_bpermute.
-template <int M>
-__device__ __forceinline__ uint32_t xlane(uint32_t v) {
-    const int x = static_cast<int>(v);
-    int r;
-    if constexpr (M == 1) {
-        r = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);
-    } else if constexpr (M == 2) {
-        r = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);
-    } else if constexpr (M == 3) {
-        r = __builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, true);
-    } else if constexpr (M == 7) {
-        r = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true);
-    } else if constexpr (M == 15) {
-        r = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true);
-    } else if constexpr (M < 32) {
-        // bit mode: and_mask 0x1f, or_mask 0, xor_mask M (within 32 lanes)
-        r = __builtin_amdgcn_ds_swizzle(x, (M << 10) | 0x1F);
-    } else {
-        r = __shfl_xor(x, M, 64);
-    }
-    return static_cast<uint32_t>(r);
-}
-template <int M>
-__device__ __forceinline__ uint64_t xlane(uint64_t v) {
-    const uint32_t lo = xlane<M>(static_cast<uint32_t>(v));
-    const uint32_t hi = xlane<M>(static_cast<uint32_t>(v >> 32));
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-template <int M, class O>
-__device__ __forceinline__ SItem<O, false> shfl_item(SItem<O, false> a) {
-    a.k = xlane<M>(a.k);
-    return a;
-}
-template <int M, class O>
-__device__ __forceinline__ SItem<O, true> shfl_item(SItem<O, true> a) {
-    a.k = xlane<M>(a.k);
-    a.i = xlane<M>(a.i);
-    return a;
-}
 
 template <class O>
 __device__ __forceinline__ bool item_less(const SItem<O, false>& a, const SItem<O, false>& b) {
@@ -1263,20 +1241,6 @@ __device__ __forceinline__ void cx(SItem<O, true>& a, SItem<O, true>& b) {
     b.k = s ? xk : yk;
     a.i = s ? yi : xi;
     b.i = s ? xi : yi;
-}
-
-// v <- min(v, o) for the lower item of a pair, max(v, o) for the upper one
-template <class O>
-__device__ __forceinline__ void keep(SItem<O, false>& v, const SItem<O, false>& o, bool lower) {
-    const bool s = o.k < v.k;
-    v.k = (s == lower) ? o.k : v.k;
-}
-template <class O>
-__device__ __forceinline__ void keep(SItem<O, true>& v, const SItem<O, true>& o, bool lower) {
-    const bool s = (o.k < v.k) | ((o.k == v.k) & (o.i < v.i));
-    const bool take = s == lower;
-    v.k = take ? o.k : v.k;
-    v.i = take ? o.i : v.i;
 }
 
 template <int E>
@@ -1314,110 +1278,87 @@ __device__ __forceinline__ void reg_mirror(It (&v)[E], int k) {
     }
 }
 
-// Exchange with the item whose index is x ^ pmask through LDS (pmask has its
-// highest bit at `hb`); all NTH threads of the group take part.
-template <class It, class O, int E, int NTH>
-__device__ __forceinline__ void lds_stage(It (&v)[E], int t, O* sk, uint32_t* si, int pmask, int hb) {
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int x = t * E + r;
-        sk[lds_slot<O>(x)] = v[r].k;
-        if constexpr (sizeof(It) > sizeof(O)) si[lds_slot<O>(x)] = v[r].i;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int x = t * E + r;
-        const int y = x ^ pmask;
-        It o;
-        o.k = sk[lds_slot<O>(y)];
-        if constexpr (sizeof(It) > sizeof(O)) o.i = si[lds_slot<O>(y)];
-        keep(v[r], o, ((x >> hb) & 1) == 0);
-    }
-}
-
-// Cross-lane stages inside one wave: the partner of register r sits in lane
-// (lane ^ M).  Half-cleaner: same register; mirror step: register E-1-r.
-template <int M, class It, int E>
-__device__ __forceinline__ void lane_xor_stage(It (&v)[E], bool lower) {
-#pragma unroll
-    for (int r = 0; r < E; ++r) keep(v[r], shfl_item<M>(v[r]), lower);
-}
-template <int M, class It, int E>
-__device__ __forceinline__ void lane_mirror_stage(It (&v)[E], bool lower) {
-    // registers r and E-1-r trade with each other's partner: fetch both
-    // before either changes
-#pragma unroll
-    for (int r = 0; r < (E + 1) / 2; ++r) {
-        const It o1 = shfl_item<M>(v[E - 1 - r]);
-        if (E - 1 - r != r) {
-            const It o2 = shfl_item<M>(v[r]);
-            keep(v[E - 1 - r], o2, lower);
-        }
-        keep(v[r], o1, lower);
-    }
-}
-
-template <class It, class O, int E, int NTH>
-__device__ void bitonic_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
+// Merge sort of the P = E*NTH items of one group (the paper's Insertionsort
+// stage replaced by a sort that suits a workgroup).  Each thread first sorts
+// its E items in registers with a fully unrolled bitonic network, then the
+// group merges runs pairwise through LDS, doubling the run length log2(NTH)
+// times.  For a merge, a thread owns E consecutive outputs of the merged run:
+// a merge-path binary search finds where they start in the two runs, then
+// the thread produces them one by one, reading each next candidate from LDS.
+// Items compare by key, and by index for pairs, so the order is total and
+// the result unique.
+template <class It, class O, int E>
+__device__ __forceinline__ void reg_sort(It (&v)[E]) {
     constexpr int LE = Log2<E>::value;
-    constexpr int LP = LE + Log2<NTH>::value;
-    const int lane = t & 63;
+#pragma unroll
+    for (int k = 1; k <= LE; ++k) {
+        reg_mirror(v, k);
+#pragma unroll
+        for (int j = k - 2; j >= 0; --j) reg_xor(v, j);
+    }
+}
+
+template <class It, class O>
+__device__ __forceinline__ It lds_item(const O* sk, const uint32_t* si, int x) {
+    It it;
+    it.k = sk[lds_slot<O>(x)];
+    if constexpr (sizeof(It) > sizeof(O)) it.i = si[lds_slot<O>(x)];
+    return it;
+}
+
+template <class O>
+__device__ __forceinline__ void pick(SItem<O, false>& d, const SItem<O, false>& x, const SItem<O, false>& y,
+                                     bool take_y) {
+    d.k = take_y ? y.k : x.k;
+}
+template <class O>
+__device__ __forceinline__ void pick(SItem<O, true>& d, const SItem<O, true>& x, const SItem<O, true>& y,
+                                     bool take_y) {
+    d.k = take_y ? y.k : x.k;
+    d.i = take_y ? y.i : x.i;
+}
+
+template <class It, class O, int E, int NTH>
+__device__ void merge_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
+    reg_sort<It, O, E>(v);
 #pragma unroll 1
-    for (int k = 1; k <= LP; ++k) {
-        const int b = k - 1;
-        // mirror step of the merge of blocks of 2^k items
-        if (b < LE) {
-            switch (k) {
-                case 1: if constexpr (LE >= 1) reg_mirror(v, 1); break;
-                case 2: if constexpr (LE >= 2) reg_mirror(v, 2); break;
-                case 3: if constexpr (LE >= 3) reg_mirror(v, 3); break;
-                case 4: if constexpr (LE >= 4) reg_mirror(v, 4); break;
-                case 5: if constexpr (LE >= 5) reg_mirror(v, 5); break;
-                default: break;
-            }
-        } else if (b < LE + 6) {
-            // partner lane: lane ^ (2^(k-LE) - 1); the exchange form is
-            // chosen once per stage
-            const bool lower = ((lane >> (b - LE)) & 1) == 0;
-            switch (k - LE) {
-                case 1: lane_mirror_stage<1>(v, lower); break;
-                case 2: lane_mirror_stage<3>(v, lower); break;
-                case 3: lane_mirror_stage<7>(v, lower); break;
-                case 4: lane_mirror_stage<15>(v, lower); break;
-                case 5: lane_mirror_stage<31>(v, lower); break;
-                default: lane_mirror_stage<63>(v, lower); break;
-            }
-        } else {
-            lds_stage<It, O, E, NTH>(v, t, sk, si, (1 << k) - 1, b);
+    for (int L = E; L < E * NTH; L <<= 1) {
+        __syncthreads();  // the previous level's reads are done
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = t * E + r;
+            sk[lds_slot<O>(x)] = v[r].k;
+            if constexpr (sizeof(It) > sizeof(O)) si[lds_slot<O>(x)] = v[r].i;
         }
-        // half-cleaners
-#pragma unroll 1
-        for (int j = k - 2; j >= 0; --j) {
-            if (j < LE) {
-                switch (j) {
-                    case 0: reg_xor(v, 0); break;
-                    case 1: if constexpr (LE >= 2) reg_xor(v, 1); break;
-                    case 2: if constexpr (LE >= 3) reg_xor(v, 2); break;
-                    case 3: if constexpr (LE >= 4) reg_xor(v, 3); break;
-                    case 4: if constexpr (LE >= 5) reg_xor(v, 4); break;
-                    default: break;
-                }
-            } else if (j < LE + 6) {
-                // partner lane: lane ^ 2^(j-LE)
-                const bool lower = ((lane >> (j - LE)) & 1) == 0;
-                switch (j - LE) {
-                    case 0: lane_xor_stage<1>(v, lower); break;
-                    case 1: lane_xor_stage<2>(v, lower); break;
-                    case 2: lane_xor_stage<4>(v, lower); break;
-                    case 3: lane_xor_stage<8>(v, lower); break;
-                    case 4: lane_xor_stage<16>(v, lower); break;
-                    default: lane_xor_stage<32>(v, lower); break;
-                }
-            } else {
-                lds_stage<It, O, E, NTH>(v, t, sk, si, 1 << j, j);
-            }
+        __syncthreads();
+        // runs A = [base, base+L) and B = [base+L, base+2L); this thread's
+        // outputs are positions [d, d+E) of the merged run
+        const int per = (2 * L) / E;  // threads per merged run
+        const int base = (t / per) * 2 * L;
+        const int d = (t % per) * E;
+        int lo = d > L ? d - L : 0, hi = d < L ? d : L;
+        while (lo < hi) {  // merge path: how many of the first d outputs come from A
+            const int mid = (lo + hi) >> 1;
+            const It am = lds_item<It, O>(sk, si, base + mid);
+            const It bm = lds_item<It, O>(sk, si, base + L + d - 1 - mid);
+            if (item_less(bm, am)) hi = mid;
+            else lo = mid + 1;
+        }
+        int a = lo, b = d - lo;
+        It ka = lds_item<It, O>(sk, si, base + (a < L ? a : L - 1));
+        It kb = lds_item<It, O>(sk, si, base + L + (b < L ? b : L - 1));
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const bool take_b = (b < L) & ((a >= L) | item_less(kb, ka));
+            pick(v[r], ka, kb, take_b);
+            a += take_b ? 0 : 1;
+            b += take_b ? 1 : 0;
+            // refill the consumed side (clamped inside the pair; an exhausted
+            // side is never chosen again)
+            const int nx = take_b ? (L + (b < L ? b : L - 1)) : (a < L ? a : L - 1);
+            const It nxt = lds_item<It, O>(sk, si, base + nx);
+            pick(kb, kb, nxt, take_b);
+            pick(ka, ka, nxt, !take_b);
         }
     }
 }
@@ -1499,7 +1440,7 @@ __global__ __launch_bounds__(256) void k_small(Args a, int cls) {
             v[r].k = sk[lds_slot<O>(x)];
             if constexpr (HV) v[r].i = si[lds_slot<O>(x)];
         }
-        bitonic_sort<It, O, E, NTH>(v, t, sk, si);
+        merge_sort<It, O, E, NTH>(v, t, sk, si);
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < E; ++r) {
@@ -1583,6 +1524,9 @@ struct Launch {
         static const Ops o{
             NT * EPT,
             SMAX,
+            // one partition pass more and 4096-key segments beat sorting up
+            // to 8192 keys in LDS (measured on 2^28 uniform int32 keys)
+            SMAX > 4096 ? 4096 : SMAX,
             &plan,
             &map,
             {&SmallLaunch<DT, V, 1, 64>::run, &SmallLaunch<DT, V, 2, 64>::run,

@@ -416,6 +416,10 @@ def test_stats_account_for_every_key(torch_mod, bqs):
         assert 0.99 * a.size <= done <= a.size
         assert s["levels"] == s["partition_launches"] >= 1
         assert s["graph_launches"] == 0
+        # per-level partitioned keys add up to the total; level 0 holds every key
+        per_level = [k for k, _ in ctx.levels()]
+        assert sum(per_level) == s["partitioned_keys"]
+        assert per_level[0] == a.size
         assert s["partition_ms"] > 0
 
 
