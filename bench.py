@@ -446,6 +446,15 @@ def main():
         "copy_context": copy_bandwidth(torch),
     }
 
+    # the multiway partition step (opt-in; same keys, fewer passes)
+    mctx = bqs.Context(timing=1, multiway=1, small_cutoff=8192)
+    mms, mst, _, mpart_ms, mpart_keys, mok = run_workload(
+        torch, bqs, mctx, "i32_uniform", args.n, max(2, args.steps // 2), 1)
+    out["multiway"] = {"ms": round(mms, 3), "Gkeys/s": round(n / (mms * 1e-3) / 1e9, 3),
+                       "partition_ms": round(mst["partition_ms"], 3), "small_ms": round(mst["small_ms"], 3),
+                       "plan_ms": round(mst["plan_ms"], 3), "levels": mst["levels"],
+                       "partitioned_keys": mst["partitioned_keys"], "small_cutoff": 8192, "correct": mok}
+
     if not args.no_dists:
         dists = {}
         for kind, nn in [("i32_sorted", n), ("i32_reverse", n), ("i32_few_distinct", n),

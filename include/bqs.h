@@ -79,13 +79,20 @@ typedef enum {
     BQS_PARAM_GRAPH = 9,        /* 1: capture the launches of a call into a HIP graph and replay
                                    it for later calls with the same buffers, sizes and parameters
                                    (see "Graph mode" below)                                     */
-    BQS_PARAM_LOOKBACK = 10     /* how a partition tile claims its output ranges.  0 (default):
+    BQS_PARAM_LOOKBACK = 10,    /* how a partition tile claims its output ranges.  0 (default):
                                    keys-only sorts move the segment's two cursors with one atomic
                                    add per tile (the paper's cursors l and r, Algorithm 3), so
                                    runs land in claim order; pairs always use the decoupled
                                    look-back.  1: every tile uses the look-back, runs land in
                                    tile order and the intermediate layout is the same on every
                                    run.  Sorted output is identical either way.                 */
+    BQS_PARAM_MULTIWAY = 11     /* 1: keys-only sorts split each segment around up to 15
+                                   splitters per pass instead of one pivot (a sample-sort step:
+                                   the paper's multi-pivot outlook, Section 5; 31 buckets, keys
+                                   equal to a splitter finish at once), so far fewer passes
+                                   run; pairs keep the two-way step.  0 (default): the paper's
+                                   block partition around one pivot.  Sorted output is
+                                   identical either way.                                        */
 } bqs_param;
 
 /* Execution modes (BQS_PARAM_MODE).

@@ -45,6 +45,7 @@ PARAM_PROFILE = 7
 PARAM_MODE = 8
 PARAM_GRAPH = 9
 PARAM_LOOKBACK = 10
+PARAM_MULTIWAY = 11
 MODE_LEVELS, MODE_QUEUE = 0, 1
 
 _TORCH_DTYPES = {
@@ -194,6 +195,7 @@ class Context:
         "mode": PARAM_MODE,
         "graph": PARAM_GRAPH,
         "lookback": PARAM_LOOKBACK,
+        "multiway": PARAM_MULTIWAY,
     }
 
     def set_param(self, name: str, value: int):

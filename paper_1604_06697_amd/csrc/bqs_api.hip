@@ -229,6 +229,7 @@ void launch_init_segments(const Args& a, hipStream_t s) {
 
 struct Layout {
     size_t ctl, yk, yv, side, segs[2], smalls[2], fills[2], tile_desc, status, total;
+    size_t splitters[2], toff, bcur, bstart;
     size_t qctl, qsegs, qitems, qpub, qstatus;
     uint64_t cap_seg, cap_tile, cap_small, cap_fill;
     uint64_t cap_qseg, cap_qitem, cap_qstatus;
@@ -239,7 +240,8 @@ static size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255);
 // Workspace layout.  Level mode keeps per-level lists (two slots); work-queue
 // mode keeps whole-sort lists whose capacities allow 16 partition passes
 // worth of segments and tiles (beyond that the run reports BQS_EOVERFLOW).
-static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S, bool queue) {
+static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S, bool queue,
+                          bool multiway) {
     Layout L{};
     const uint64_t un = static_cast<uint64_t>(n);
     const uint64_t uk = static_cast<uint64_t>(k);
@@ -255,15 +257,24 @@ static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T,
     L.yv = take(vb ? un * vb : 0);
     L.side = take(vb ? un * vb : 0);
     if (!queue) {
+        // a two-way level gives each segment two children and one equal run;
+        // a multiway level up to 16 children and 15 equal runs
+        const uint64_t fan = multiway ? 16 : 2;
         L.cap_seg = per_level_segs;
         L.cap_tile = un / static_cast<uint64_t>(T) + 2 * L.cap_seg + 2;
-        L.cap_small = 2 * L.cap_seg + uk + 2;
-        L.cap_fill = L.cap_seg + 1;
+        L.cap_small = fan * L.cap_seg + uk + 2;
+        L.cap_fill = (fan - 1) * L.cap_seg + 1;
         for (int s = 0; s < 2; ++s) L.segs[s] = take(L.cap_seg * sizeof(SegDesc));
         for (int s = 0; s < 2; ++s) L.smalls[s] = take(kSmallClasses * L.cap_small * sizeof(SmallItem));
         for (int s = 0; s < 2; ++s) L.fills[s] = take(L.cap_fill * sizeof(FillItem));
         L.tile_desc = take(L.cap_tile * sizeof(TileDesc));
         L.status = take(L.cap_tile * sizeof(unsigned long long));
+        // multiway levels: 16 splitters, 32 bucket cursors and 32 bucket
+        // starts per segment, 32 bucket offsets per tile
+        for (int s = 0; s < 2; ++s) L.splitters[s] = take(L.cap_seg * 16 * sizeof(uint64_t));
+        L.toff = take(L.cap_tile * 32 * sizeof(uint32_t));
+        L.bcur = take(L.cap_seg * 32 * sizeof(uint32_t));
+        L.bstart = take(L.cap_seg * 32 * sizeof(uint32_t));
     } else {
         L.cap_qseg = 16 * per_level_segs + uk + 1024;
         L.cap_qstatus = 16 * (un / static_cast<uint64_t>(T)) + 2 * L.cap_qseg + 4096;
@@ -306,6 +317,7 @@ struct bqs_ctx {
     int64_t mode = BQS_MODE_LEVELS;
     int64_t graph = 0;
     int64_t lookback = 0;  // 1: keys-only tiles also claim by decoupled look-back
+    int64_t multiway = 0;  // 1: keys-only levels split around up to 15 splitters
     // graph mode: the captured launch sequence and the call it belongs to
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph_obj = nullptr;
@@ -463,7 +475,7 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         const uint32_t nchunk = static_cast<uint32_t>(cur.fills >> 32);
         tm.start();
         // plan: one wave per segment (4 per workgroup), one workgroup per fill chunk
-        o->plan(a, clamp_grid(std::max<uint64_t>((nseg + 3) / 4, nchunk), 16384), s);
+        (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(std::max<uint64_t>((nseg + 3) / 4, nchunk), 16384), s);
         if (nseg) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
         tm.stop(0, L);
         for (int cls = 0; cls < kSmallClasses; ++cls) {
@@ -487,8 +499,14 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         tm.start();
         // one workgroup per tile (tiles are still claimed in order through the
         // level's ticket counter, which the look-back relies on)
-        o->tile(a, static_cast<int>(ntile), s);
-        o->complete(a, clamp_grid((nseg + 255) / 256, 4096), s);
+        if (a.ways) {
+            o->mcount(a, static_cast<int>(ntile), s);
+            o->mscan(a, clamp_grid((nseg + 3) / 4, 4096), s);
+            o->mscatter(a, static_cast<int>(ntile), s);
+        } else {
+            o->tile(a, static_cast<int>(ntile), s);
+            o->complete(a, clamp_grid((nseg + 255) / 256, 4096), s);
+        }
         tm.stop(2, L);
         stats.partition_launches++;
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
@@ -541,7 +559,8 @@ std::vector<uint64_t> graph_key(const Ops* o, const Args& a, bool segmented) {
     return {u(o), u(a.ctl), u(a.x_keys), u(a.x_vals), u(a.y_keys), u(a.offsets), static_cast<uint64_t>(a.n),
             static_cast<uint64_t>(a.k), static_cast<uint64_t>(a.small_cut), static_cast<uint64_t>(a.sample_max),
             static_cast<uint64_t>(a.pivot_mode), static_cast<uint64_t>(a.depth_limit),
-            static_cast<uint64_t>(a.prof), static_cast<uint64_t>(a.claim), segmented ? 1ull : 0ull};
+            static_cast<uint64_t>(a.prof), static_cast<uint64_t>(a.claim), static_cast<uint64_t>(a.ways),
+            segmented ? 1ull : 0ull};
 }
 
 void drop_graph(bqs_ctx* ctx) {
@@ -573,7 +592,7 @@ bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, Args a, bool segmented, int
     else launch_init_single(a, cs);
     for (int L = 0; L < levels; ++L) {
         a.level = L;
-        o->plan(a, 2048, cs);
+        (a.ways ? o->plan_multi : o->plan)(a, 2048, cs);
         o->map(a, 4096, cs);
         for (int cls = 0; cls < kSmallClasses; ++cls)
             if (o->small[cls]) o->small[cls](a, 2048, cs);
@@ -584,8 +603,15 @@ bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, Args a, bool segmented, int
             if (g) hipGraphDestroy(g);
             return BQS_EINVAL;
         }
-        o->tile(a, static_cast<int>(std::max<uint64_t>(tb, 1)), cs);
-        o->complete(a, 1024, cs);
+        const int tg = static_cast<int>(std::max<uint64_t>(tb, 1));
+        if (a.ways) {
+            o->mcount(a, tg, cs);
+            o->mscan(a, 1024, cs);
+            o->mscatter(a, tg, cs);
+        } else {
+            o->tile(a, tg, cs);
+            o->complete(a, 1024, cs);
+        }
     }
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return BQS_EHIP;
@@ -704,7 +730,8 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     const size_t kb = key_bytes(dtype);
     const int64_t S = eff_small_cut(ctx, o);
     const bool queue = ctx->mode == BQS_MODE_QUEUE;
-    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, o->tile_keys, S, queue);
+    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, o->tile_keys, S, queue,
+                                 ctx->multiway && o->mscan);
     if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull ||
         L.cap_qseg > 0xffffffffull || L.cap_qitem > 0xffffffffull)
         return BQS_EINVAL;
@@ -727,6 +754,10 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
         a.fills[s] = reinterpret_cast<FillItem*>(w + L.fills[s]);
     }
     a.tile_desc = reinterpret_cast<TileDesc*>(w + L.tile_desc);
+    for (int s = 0; s < 2; ++s) a.splitters[s] = reinterpret_cast<uint64_t*>(w + L.splitters[s]);
+    a.toff = reinterpret_cast<uint32_t*>(w + L.toff);
+    a.bcur = reinterpret_cast<uint32_t*>(w + L.bcur);
+    a.bstart = reinterpret_cast<uint32_t*>(w + L.bstart);
     a.status = reinterpret_cast<unsigned long long*>(w + L.status);
     a.cap_seg = static_cast<uint32_t>(L.cap_seg);
     a.cap_tile = static_cast<uint32_t>(L.cap_tile);
@@ -742,6 +773,7 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.tile_keys = o->tile_keys;
     a.prof = static_cast<int>(ctx->profile);
     a.claim = ctx->lookback ? 0 : 1;
+    a.ways = (ctx->multiway && o->mscan) ? 1 : 0;
     a.queue = queue ? 1 : 0;
     if (queue) {
         a.qctl = reinterpret_cast<QCtl*>(w + L.qctl);
@@ -820,6 +852,7 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             drop_graph(ctx);
             break;
         case BQS_PARAM_LOOKBACK: ctx->lookback = value ? 1 : 0; break;
+        case BQS_PARAM_MULTIWAY: ctx->multiway = value ? 1 : 0; break;
         case BQS_PARAM_MODE:
             // The work-queue kernel took a memory-aperture fault on its first
             // input with partition tiles (n = 8193 int32) and the cause is not
@@ -846,6 +879,7 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_MODE: return ctx->mode;
         case BQS_PARAM_GRAPH: return ctx->graph;
         case BQS_PARAM_LOOKBACK: return ctx->lookback;
+        case BQS_PARAM_MULTIWAY: return ctx->multiway;
         default: return -1;
     }
 }
@@ -870,7 +904,7 @@ size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, i
     if (!o) return 0;
     const Layout L = make_layout(n_total, key_bytes(key), static_cast<size_t>(val_bytes),
                                  std::max<int64_t>(k_segments, 1), o->tile_keys, eff_small_cut(ctx, o),
-                                 ctx && ctx->mode == BQS_MODE_QUEUE);
+                                 ctx && ctx->mode == BQS_MODE_QUEUE, ctx && ctx->multiway && o->mscan);
     return L.total;
 }
 

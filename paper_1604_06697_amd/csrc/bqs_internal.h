@@ -153,6 +153,11 @@ struct Args {
     int tile_keys;
     int prof;
     int claim;  // 1: keys-only tiles claim their ranges with the segment's cursor
+    int ways;   // 1: multiway partition levels (keys only)
+    uint64_t* splitters[2];  // per slot: 16 order keys per segment
+    uint32_t* toff;          // per tile: offset of its keys inside each bucket
+    uint32_t* bcur;          // per segment: bucket cursors (stride 32)
+    uint32_t* bstart;        // per segment: bucket starts from the segment start
     // work-queue mode
     int queue;
     QCtl* qctl;
@@ -176,6 +181,12 @@ struct Ops {
     // segment completion after a partition launch: children and equal runs
     // of every segment of the level
     void (*complete)(const Args&, int grid, hipStream_t);
+    // multiway levels (keys only; nullptr otherwise): splitters + fills,
+    // per-tile histograms, per-segment offsets + lists, per-tile scatter
+    void (*plan_multi)(const Args&, int grid, hipStream_t);
+    void (*mcount)(const Args&, int grid, hipStream_t);
+    void (*mscan)(const Args&, int grid, hipStream_t);
+    void (*mscatter)(const Args&, int grid, hipStream_t);
     // work-queue mode: clear + seed the queue, drain it with `grid` workgroups
     void (*qinit)(const Args&, int grid, hipStream_t);
     void (*qrun)(const Args&, int grid, hipStream_t);

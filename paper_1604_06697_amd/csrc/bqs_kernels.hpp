@@ -241,6 +241,52 @@ __device__ inline void push_fill(const Args& a, int slot, int64_t dst, int64_t l
     atomicAdd(&c->fill_keys, static_cast<unsigned long long>(len));
 }
 
+// Writes the equal-key runs recorded for level p into X: keys get the stored
+// bits of the run's key, pairs their payloads from the side buffer.  One
+// workgroup per work unit of kFillChunk keys (all NT threads).
+template <int DT, class V, int NT>
+__device__ void run_fills(const Args& a, int p) {
+    using R = typename KeyT<DT>::raw;
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    const Ctl* c = a.ctl;
+    const int tid = threadIdx.x;
+    const unsigned long long fc = c->lc[p].fills;
+    const uint32_t nfill = static_cast<uint32_t>(fc);
+    const uint32_t nchunk = static_cast<uint32_t>(fc >> 32);
+    R* xk = static_cast<R*>(a.x_keys);
+    for (uint32_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        // items are ordered by chunk0: find the last one starting at or before ch
+        uint32_t lo_i = 0, hi_i = nfill;
+        while (hi_i - lo_i > 1) {
+            const uint32_t mid = (lo_i + hi_i) >> 1;
+            if (a.fills[p][mid].chunk0 <= ch) lo_i = mid; else hi_i = mid;
+        }
+        const FillItem f = a.fills[p][lo_i];
+        const int64_t b = static_cast<int64_t>(ch - f.chunk0) * kFillChunk;
+        const int64_t e = b + kFillChunk < f.len ? b + kFillChunk : f.len;
+        const R raw = static_cast<R>(f.raw);
+        for (int64_t t = b + tid; t < e; t += NT) {
+            xk[f.dst + t] = raw;
+            if constexpr (HV) {
+                static_cast<V*>(a.x_vals)[f.dst + t] = static_cast<const V*>(a.side)[f.side + t];
+            }
+        }
+    }
+}
+
+// Block 0 of a plan kernel clears the lists that level p's partition fills
+// (slot q) and counts the level.
+__device__ inline void reset_next_slot(Ctl* c, int q, uint32_t nseg) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->lc[q].segs = 0;
+        c->lc[q].fills = 0;
+        for (int k = 0; k < kSmallClasses; ++k) c->lc[q].smalls[k] = 0;
+        c->lc[q].tile_next = 0;
+        c->lc[q].keys = 0;
+        if (nseg) c->levels += 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Plan kernel, level L.
 //  (1) For every segment of level L: the pivot is the median of a sample of
@@ -268,14 +314,7 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
     const int p = a.level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
-    if (blockIdx.x == 0 && tid == 0) {
-        c->lc[q].segs = 0;
-        c->lc[q].fills = 0;
-        for (int k = 0; k < kSmallClasses; ++k) c->lc[q].smalls[k] = 0;
-        c->lc[q].tile_next = 0;
-        c->lc[q].keys = 0;
-        if (nseg) c->levels += 1;
-    }
+    reset_next_slot(c, q, nseg);
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
     R* ws = s_samp[wv];
 
@@ -343,29 +382,7 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
         __syncthreads();
     }
 
-    // equal-key runs of the previous level
-    const unsigned long long fc = c->lc[p].fills;
-    const uint32_t nfill = static_cast<uint32_t>(fc);
-    const uint32_t nchunk = static_cast<uint32_t>(fc >> 32);
-    R* xk = static_cast<R*>(a.x_keys);
-    for (uint32_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        // items are ordered by chunk0: find the last one starting at or before ch
-        uint32_t lo_i = 0, hi_i = nfill;
-        while (hi_i - lo_i > 1) {
-            const uint32_t mid = (lo_i + hi_i) >> 1;
-            if (a.fills[p][mid].chunk0 <= ch) lo_i = mid; else hi_i = mid;
-        }
-        const FillItem f = a.fills[p][lo_i];
-        const int64_t b = static_cast<int64_t>(ch - f.chunk0) * kFillChunk;
-        const int64_t e = b + kFillChunk < f.len ? b + kFillChunk : f.len;
-        const R raw = static_cast<R>(f.raw);
-        for (int64_t t = b + tid; t < e; t += NT) {
-            xk[f.dst + t] = raw;
-            if constexpr (HV) {
-                static_cast<V*>(a.x_vals)[f.dst + t] = static_cast<const V*>(a.side)[f.side + t];
-            }
-        }
-    }
+    run_fills<DT, V, NT>(a, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -1474,6 +1491,42 @@ __global__ __launch_bounds__(256) void k_small(Args a, int cls) {
 // Host-side launchers for one (dtype, payload, tile shape).  SMAX is the
 // largest small segment (a power of two between 64 and 8192).
 
+}  // namespace bqs
+
+#include "bqs_multiway.hpp"
+
+namespace bqs {
+
+// multiway launchers (keys only), or nullptr without instantiating them
+template <int DT, int NT, int EPT, bool ON>
+struct MultiFns {
+    static void plan(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_plan_multi<DT, NoVal, 256>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void count(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_mcount<DT, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
+    }
+    static void scan(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_mscan<DT, 256>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void scatter(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_mscatter<DT, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
+    }
+    using Fn = void (*)(const Args&, int, hipStream_t);
+    static constexpr Fn p() { return &plan; }
+    static constexpr Fn c() { return &count; }
+    static constexpr Fn sc() { return &scan; }
+    static constexpr Fn sa() { return &scatter; }
+};
+template <int DT, int NT, int EPT>
+struct MultiFns<DT, NT, EPT, false> {
+    using Fn = void (*)(const Args&, int, hipStream_t);
+    static constexpr Fn p() { return nullptr; }
+    static constexpr Fn c() { return nullptr; }
+    static constexpr Fn sc() { return nullptr; }
+    static constexpr Fn sa() { return nullptr; }
+};
+
 template <int DT, class V, int E, int NTH>
 struct SmallLaunch {
     static void run(const Args& a, int grid, hipStream_t s) {
@@ -1538,6 +1591,10 @@ struct Launch {
             {4, 4, 4, 4, 4, 1, 1, 1},
             &tile,
             &complete,
+            MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::p(),
+            MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::c(),
+            MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::sc(),
+            MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::sa(),
             &qinit,
             &qrun,
             &qblocks_per_cu};

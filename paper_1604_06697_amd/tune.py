@@ -41,9 +41,12 @@ def plan_key(n: int, k: int, key_code: int, val_bytes: int) -> str:
 def candidates(key_code: int, val_bytes: int) -> list[dict]:
     """Plans the library compiles for this key type: the tile shape is
     selectable for int32 keys only; the cutoff is clamped by the library to
-    the largest in-LDS size it compiles for the type."""
-    epts = EPT_CHOICES if (key_code == 1 and val_bytes == 0) else (0,)
-    return [{"tile_ept": e, "small_cutoff": c} for e in epts for c in CUTOFF_CHOICES]
+    the largest in-LDS size it compiles for the type; keys-only int32 sorts
+    also try the multiway partition step."""
+    i32 = key_code == 1 and val_bytes == 0
+    epts = EPT_CHOICES if i32 else (0,)
+    ways = (0, 1) if i32 else (0,)
+    return [{"tile_ept": e, "small_cutoff": c, "multiway": w} for w in ways for e in epts for c in CUTOFF_CHOICES]
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> dict:

@@ -310,6 +310,76 @@ def test_lookback_layout_is_deterministic(torch_mod, bqs):
     assert runs[0] == runs[1]
 
 
+# ------------------------------------------------------------- multiway --
+
+@pytest.mark.parametrize("cut", [256, 4096])
+def test_multiway_int32_families(torch_mod, bqs, oracle, cut):
+    """Multiway levels (up to 15 splitters, equal-key buckets finished at
+    once) against the oracle: every int32 family of the paper's benchmark
+    and the duplicate-heavy ones, tile-aligned and ragged sizes."""
+    ctx = bqs.Context(multiway=1, small_cutoff=cut)
+    fams = dict(W.I32_FAMILIES)
+    fams.update(W.I32_EXTRA_FAMILIES)
+    for fam, gen in fams.items():
+        for n in (8192 * 3, 8192 * 7 + 5, 1_000_003):
+            a = gen(n, 21)
+            note(f"multiway cut={cut} {fam} n={n}")
+            assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+
+
+def test_multiway_key_types_and_specials(torch_mod, bqs, oracle):
+    ctx = bqs.Context(multiway=1, small_cutoff=512)
+    rng = np.random.Generator(np.random.PCG64(31))
+    for dt in (np.uint32, np.int64, np.uint64):
+        a = rng.integers(np.iinfo(dt).min, np.iinfo(dt).max, size=700_001, dtype=dt, endpoint=True)
+        note(f"multiway {np.dtype(dt).name}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+    for fam, gen in W.F64_FAMILIES.items():
+        a = gen(600_007, 5)
+        note(f"multiway f64 {fam}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+    for n in (10_000, 200_000):
+        a = W.special_f64(n, n)
+        note(f"multiway f64 special n={n}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+        with np.errstate(over="ignore"):
+            f = a.astype(np.float32)
+        assert_same_bits(gpu_sort(torch_mod, bqs, f, ctx), oracle.sort(f))
+    z = np.array([0.0, -0.0] * 60000)
+    note("multiway f64 zeros")
+    out = gpu_sort(torch_mod, bqs, z, ctx)
+    assert np.all(np.signbit(out[:60000])) and not np.any(np.signbit(out[60000:]))
+
+
+def test_multiway_segments_and_graph(torch_mod, bqs, oracle):
+    torch = torch_mod
+    keys, offsets = W.segmented_i32(800, 6, 4.0, 17.0)
+    ctx = bqs.Context(multiway=1)
+    note(f"multiway segments n={keys.size}")
+    assert_same_bits(gpu_segments(torch, bqs, keys, offsets, ctx), oracle.sort_segments(keys, offsets))
+    # graph replays on one set of buffers, with a deeper input after a shallow one
+    gctx = bqs.Context(multiway=1, graph=1)
+    buf = torch.empty(keys.size, dtype=torch.int32, device="cuda")
+    off = torch.from_numpy(offsets).cuda()
+    for i, (fam, seed) in enumerate([("few_distinct", 1), ("uniform", 2), ("uniform", 3), ("sorted", 0)]):
+        a = W.I32_FAMILIES[fam](keys.size, seed)
+        note(f"multiway graph replay {i} {fam}")
+        buf.copy_(torch.from_numpy(a))
+        gctx.sort_segments(buf, off)
+        torch.cuda.synchronize()
+        assert_same_bits(buf.cpu().numpy(), oracle.sort_segments(a, offsets))
+        assert gctx.stats()["graph_launches"] == (0 if i == 0 else 1)
+
+
+def test_multiway_pairs_use_two_way(torch_mod, bqs, oracle):
+    """Pairs keep the two-way step; the parameter only changes keys-only sorts."""
+    k, v = W.tied_u64_pairs(300_000, 3)
+    ctx = bqs.Context(multiway=1)
+    note("multiway param with pairs")
+    ko, vo = gpu_pairs(torch_mod, bqs, k, v, ctx)
+    check_pairs(k, ko, vo, oracle.sort(k))
+
+
 # ------------------------------------------------------------ graph mode --
 
 def test_graph_replays_match_oracle(torch_mod, bqs, oracle):

@@ -24,10 +24,12 @@ def test_candidates_follow_compiled_shapes(tune):
     i32 = tune.candidates(1, 0)
     assert {c["tile_ept"] for c in i32} == {8, 16, 32}
     assert {c["small_cutoff"] for c in i32} == set(tune.CUTOFF_CHOICES)
-    assert len(i32) == 12
+    assert {c["multiway"] for c in i32} == {0, 1}
+    assert len(i32) == 24
     # other key types and pairs compile one tile shape (0 = library default)
     assert {c["tile_ept"] for c in tune.candidates(6, 0)} == {0}
     assert {c["tile_ept"] for c in tune.candidates(1, 4)} == {0}
+    assert {c["multiway"] for c in tune.candidates(1, 4)} == {0}
 
 
 def test_cache_round_trip(tune, tmp_path):
@@ -45,11 +47,12 @@ def test_cache_round_trip(tune, tmp_path):
 
 def test_tuned_context_applies_cached_plan(tune, tmp_path):
     path = str(tmp_path / "plans.json")
-    tune.save_cache({tune.plan_key(1 << 20, 1, 1, 0): {"plan": {"tile_ept": 8, "small_cutoff": 1024},
-                                                       "ms": 1.0}}, path)
+    tune.save_cache({tune.plan_key(1 << 20, 1, 1, 0): {"plan": {"tile_ept": 8, "small_cutoff": 1024,
+                                                                "multiway": 1}, "ms": 1.0}}, path)
     ctx = tune.tuned_context(1 << 20, 1, 1, 0, path, graph=1)
     assert ctx.get_param("tile_ept") == 8
     assert ctx.get_param("small_cutoff") == 1024
+    assert ctx.get_param("multiway") == 1
     assert ctx.get_param("graph") == 1
     assert tune.tuned_context(1 << 10, 1, 1, 0, path).get_param("tile_ept") == 0
 
@@ -67,7 +70,7 @@ def test_autotune_segments_matches_oracle(tune, oracle, tmp_path):
     path = str(tmp_path / "plans.json")
     res = tune.autotune(t, o, graph=True, reps=1, path=path)
     assert res["plan"] in tune.candidates(1, 0)
-    assert len(res["table"]) == 12
+    assert len(res["table"]) == 24
     ref = oracle.sort_segments(keys, offsets)
     assert np.array_equal(t.cpu().numpy(), ref)
     # the cached plan sorts a fresh copy identically
