@@ -67,8 +67,9 @@ typedef enum {
                                    workgroup's LDS (clamped to the compiled maximum: 8192 for
                                    4-byte keys, 4096 for 8-byte keys, 2048 for pairs; default
                                    4096, or the maximum where that is smaller)                */
-    BQS_PARAM_SAMPLE_MAX = 2,   /* largest pivot sample (odd, <= 255); the pivot is the median
-                                   of the sample (Section 2, pivot selection)                  */
+    BQS_PARAM_SAMPLE_MAX = 2,   /* largest pivot sample (<= 255; default 127, 255 with
+                                   BQS_PARAM_MULTIWAY); the pivot is the median of the sample
+                                   (Section 2, pivot selection)                                */
     BQS_PARAM_PIVOT_MODE = 3,   /* 0: median of a stratified sample; 3: median of first, middle
                                    and last key (median-of-three, Section 2)                    */
     BQS_PARAM_TIMING = 4,       /* 1: time every partition / small-sort launch with HIP events */

@@ -766,14 +766,17 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.n = n;
     a.k = k;
     a.small_cut = static_cast<int>(S);
+    // default sample: 127 keys for one pivot, 255 for the multiway splitters
+    // (measured on 2^28 uniform int32 keys)
+    const bool multiway = ctx->multiway && o->mscan;
     a.sample_max = static_cast<int>(ctx->sample_max > 0 ? std::min<int64_t>(ctx->sample_max, kMaxSample)
-                                                        : kMaxSample);
+                                                        : (multiway ? kMaxSample : 127));
     a.pivot_mode = static_cast<int>(ctx->pivot_mode);
     a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
     a.tile_keys = o->tile_keys;
     a.prof = static_cast<int>(ctx->profile);
     a.claim = ctx->lookback ? 0 : 1;
-    a.ways = (ctx->multiway && o->mscan) ? 1 : 0;
+    a.ways = multiway ? 1 : 0;
     a.queue = queue ? 1 : 0;
     if (queue) {
         a.qctl = reinterpret_cast<QCtl*>(w + L.qctl);

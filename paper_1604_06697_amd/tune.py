@@ -1,11 +1,12 @@
 """Autotuner for the launch plan of the block-partition sort.
 
-A plan is the pair (keys per thread in a partition tile, small-segment
-cutoff).  The tile size sets how many keys one workgroup scans and how many
-decoupled look-backs a pass needs; the cutoff sets where the recursion stops
-and the in-LDS sort takes over (the paper's Insertionsort threshold, Section
-2).  Both change only the launch shapes, never the result: keys come out bit
-for bit the same under every plan.
+A plan is (keys per thread in a partition tile, small-segment cutoff,
+partition step).  The tile size sets how many keys one workgroup scans and
+how many output-range claims a pass makes; the cutoff sets where the
+recursion stops and the in-LDS sort takes over (the paper's Insertionsort
+threshold, Section 2); the step is the paper's two-way block partition or
+the multiway (sample-sort) step for keys-only int32 sorts.  None of them
+changes the result: keys come out bit for bit the same under every plan.
 
 `autotune` times every candidate plan on the caller's own input (sorted from
 a pristine copy each time, in the same mode the caller will use) and keeps
