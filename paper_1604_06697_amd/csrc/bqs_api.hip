@@ -42,7 +42,7 @@ __global__ void k_init_single(Args a) {
     const int64_t n = a.n;
     if (n > a.small_cut) {
         const int64_t T = a.tile_keys;
-        const uint32_t nt = static_cast<uint32_t>((n + T - 1) / T);
+        const uint32_t nt = seg_tiles(0, n, T);
         SegDesc d{};
         d.lo = 0;
         d.hi = n;
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_init_segments(Args a) {
             atomicOr(&c->error, ERR_OFFSETS);
         } else if (m > a.small_cut) {
             const int64_t T = a.tile_keys;
-            const uint32_t nt = static_cast<uint32_t>((hi + T - 1) / T - lo / T);
+            const uint32_t nt = seg_tiles(lo, hi, T);
             const unsigned long long r =
                 atomicAdd(&c->lc[0].segs, (static_cast<unsigned long long>(nt) << 32) | 1ull);
             const uint32_t idx = static_cast<uint32_t>(r);

@@ -33,6 +33,13 @@ __host__ __device__ inline int small_class(int64_t m) {
 }
 constexpr int kMaxSample = 255;   // largest pivot sample
 
+// Tiles of a segment [lo, hi) of a partition level with T keys per tile:
+// tile j covers [lo + j*T, min(lo + (j+1)*T, hi)), so only a segment's last
+// tile is partial.
+__host__ __device__ inline uint32_t seg_tiles(int64_t lo, int64_t hi, int64_t T) {
+    return static_cast<uint32_t>((hi - lo + T - 1) / T);
+}
+
 struct SegDesc {
     int64_t lo, hi;      // [lo, hi) in the level's source buffer
     uint64_t pivot;      // pivot as an order key (set by the plan kernel)

@@ -185,7 +185,7 @@ __device__ inline void push_segment(const Args& a, int slot, int64_t lo, int64_t
     Ctl* c = a.ctl;
     if (m > a.small_cut) {
         const int64_t T = a.tile_keys;
-        const uint32_t nt = static_cast<uint32_t>((hi + T - 1) / T - lo / T);
+        const uint32_t nt = seg_tiles(lo, hi, T);
         const unsigned long long r =
             atomicAdd(&c->lc[slot].segs, (static_cast<unsigned long long>(nt) << 32) | 1ull);
         const uint32_t idx = static_cast<uint32_t>(r);
@@ -391,9 +391,9 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
 // One workgroup partitions one tile of T = NT*EPT keys of a segment [lo, hi)
 // around the segment's pivot: keys < pivot go to the left run, keys > pivot
 // to the right run, keys == pivot are counted (keys) or parked in the side
-// buffer (payloads).  Tile j of a segment covers [ (lo/T + j)*T, +T ) clipped
-// to the segment, so full tiles are aligned.  `status` points at the status
-// words of the segment's tiles (index j).
+// buffer (payloads).  Tile j of a segment covers [lo + j*T, +T) clipped to
+// the segment (seg_tiles), so only its last tile is partial.  `status`
+// points at the status words of the segment's tiles (index j).
 
 __device__ __forceinline__ uint64_t cycles() { return static_cast<uint64_t>(clock64()); }
 
@@ -455,8 +455,8 @@ __device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned lon
     VS* vdst = static_cast<VS*>(io.vdst);
     VS* side = static_cast<VS*>(io.side);
     const uint32_t j = io.j;
-    const int64_t tbase = (io.lo / T + j) * static_cast<int64_t>(T);
-    const int sl = io.lo > tbase ? static_cast<int>(io.lo - tbase) : 0;
+    const int64_t tbase = io.lo + static_cast<int64_t>(j) * T;
+    const int sl = 0;
     const int el = io.hi < tbase + T ? static_cast<int>(io.hi - tbase) : T;
     const bool full = sl == 0 && el == T;
     const O piv = static_cast<O>(io.pivot);
@@ -769,7 +769,7 @@ __global__ __launch_bounds__(256) void k_complete(Args a) {
         for (int h = 0; h < 2; ++h) {
             const int64_t m = chi[h] - clo[h];
             kind[h] = m <= 0 ? 0 : (m > S ? 1 : ((m == 1 && q == 0) ? 0 : 2));
-            nt[h] = kind[h] == 1 ? static_cast<uint32_t>((chi[h] + T - 1) / T - clo[h] / T) : 0u;
+            nt[h] = kind[h] == 1 ? seg_tiles(clo[h], chi[h], T) : 0u;
             cls[h] = kind[h] == 2 ? small_class(m) : -1;
         }
         // segments of level L+1 (count | tiles << 32)
@@ -994,7 +994,7 @@ __device__ void q_spawn(const Args& a, int64_t lo, int64_t hi, uint32_t depth, u
     }
     const R* src = static_cast<const R*>(buf ? a.y_keys : a.x_keys);
     const R piv = pick_pivot<DT, NT>(src, lo, hi, depth, a);
-    const uint32_t nt = static_cast<uint32_t>((hi + T - 1) / T - lo / T);
+    const uint32_t nt = seg_tiles(lo, hi, T);
     if (tid == 0) {
         QCtl* q = a.qctl;
         const uint32_t si = atomicAdd(&q->segs, 1u);

@@ -13,7 +13,7 @@
 // two-way step.
 //
 // One pass over a level, with the level's tiles laid out as in the two-way
-// step (tile j of a segment covers [(lo/T + j)*T, +T) clipped to it):
+// step (tile j of a segment covers [lo + j*T, +T) clipped to it):
 //   k_mcount   per tile: bucket histogram (read 4 B / key); each (tile,
 //              bucket) claims its offset inside the bucket with one atomic
 //              add on the segment's bucket cursor (the paper's cursors, one
@@ -162,8 +162,8 @@ __global__ __launch_bounds__(NT) void k_mcount(Args a) {
 #pragma unroll
     for (int b = 0; b < kBStride; ++b) s_c[b][tid] = 0;
     __syncthreads();
-    const int64_t tbase = (td.lo / T + (tile - td.t0)) * static_cast<int64_t>(T);
-    const int sl = td.lo > tbase ? static_cast<int>(td.lo - tbase) : 0;
+    const int64_t tbase = td.lo + static_cast<int64_t>(tile - td.t0) * T;
+    const int sl = 0;
     const int el = td.hi < tbase + T ? static_cast<int>(td.hi - tbase) : T;
     const R* tsrc = static_cast<const R*>(p ? a.y_keys : a.x_keys) + tbase;
 #pragma unroll 8
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
         uint32_t nt = 0;
         if (used && !eqb && m > 0) {
             kind = m > S ? 1 : ((m == 1 && q == 0) ? 0 : 2);
-            if (kind == 1) nt = static_cast<uint32_t>((blo + m + T - 1) / T - blo / T);
+            if (kind == 1) nt = seg_tiles(blo, blo + m, T);
             if (kind == 2) cls = small_class(m);
         }
         const uint64_t sinc = kind == 1 ? (1ull | (static_cast<uint64_t>(nt) << 32)) : 0ull;
@@ -344,8 +344,8 @@ __global__ __launch_bounds__(NT) void k_mscatter(Args a) {
                      a.toff[static_cast<size_t>(tile) * kBStride + tid];
     }
     __syncthreads();
-    const int64_t tbase = (td.lo / T + (tile - td.t0)) * static_cast<int64_t>(T);
-    const int sl = td.lo > tbase ? static_cast<int>(td.lo - tbase) : 0;
+    const int64_t tbase = td.lo + static_cast<int64_t>(tile - td.t0) * T;
+    const int sl = 0;
     const int el = td.hi < tbase + T ? static_cast<int>(td.hi - tbase) : T;
     const R* tsrc = static_cast<const R*>(p ? a.y_keys : a.x_keys) + tbase;
     R* dst = static_cast<R*>(p ? a.x_keys : a.y_keys) + td.lo;
