@@ -341,6 +341,62 @@ def check_requests(torch, reqs):
     return True
 
 
+def paper_families(torch, bqs, n=1 << 26, reps=3):
+    """The int32 input families of the paper's benchmark (random
+    permutation, few-distinct and structured inputs), n keys each, default
+    plan; each timed call sorts a fresh copy of the input."""
+    import workloads as W
+
+    out = {}
+    ctx = bqs.Context()
+    for fam, gen in W.I32_EXTRA_FAMILIES.items():
+        pristine = torch.from_numpy(gen(n, 3)).cuda()
+        ref = torch.sort(pristine).values
+        t = torch.empty_like(pristine)
+        times = []
+        for r in range(reps + 1):
+            t.copy_(pristine)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sort(t)
+            torch.cuda.synchronize()
+            if r:
+                times.append(time.perf_counter() - t0)
+        ms = 1e3 * min(times)
+        st = ctx.stats()
+        out[fam] = {"ms": round(ms, 3), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3), "levels": st["levels"],
+                    "correct": bool(torch.equal(t, ref))}
+        del pristine, ref, t
+    return {"n": n, "families": out}
+
+
+def pivot_study(torch, bqs, n, reps=3):
+    """Median of three (the paper's pivot) against the median of a sample
+    (the default), on the headline input."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    pristine = torch.randint(-(2**31), 2**31, (n,), dtype=torch.int32, device="cuda", generator=g)
+    t = torch.empty_like(pristine)
+    out = {}
+    for name, params in (("median_of_3", {"pivot_mode": 3}), ("median_of_sample", {})):
+        ctx = bqs.Context(timing=1, **params)
+        times = []
+        for r in range(reps + 1):
+            t.copy_(pristine)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sort(t)
+            torch.cuda.synchronize()
+            if r:
+                times.append(time.perf_counter() - t0)
+        st = ctx.stats()
+        out[name] = {"ms": round(1e3 * min(times), 3), "levels": st["levels"],
+                     "partitioned_keys": st["partitioned_keys"],
+                     "partition_ms": round(st["partition_ms"], 3)}
+    del pristine, t
+    return out
+
+
 def record_bytes(kind):
     if kind.startswith("i32"):
         return 4
@@ -476,6 +532,10 @@ def main():
                 "levels": dst["levels"], "correct": dok,
             }
         out["distributions"] = dists
+
+    if not args.no_dists:
+        out["paper_families"] = paper_families(torch, bqs)
+        out["pivot_study"] = pivot_study(torch, bqs, n)
 
     if not args.no_batched:
         out["segmented"] = batched_segments(torch, bqs, max(2, args.steps // 3), 1)

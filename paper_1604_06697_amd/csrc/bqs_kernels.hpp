@@ -366,6 +366,7 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
             const R mine = ws[i];
             const auto om = K::ord(mine);
             int rank = 0;
+#pragma unroll 8
             for (int j = 0; j < k; ++j) {
                 const auto oj = K::ord(ws[j]);
                 rank += (oj < om) | ((oj == om) & (j < i));
@@ -1497,9 +1498,14 @@ __global__ __launch_bounds__(256) void k_small(Args a, int cls) {
 
 namespace bqs {
 
-// multiway launchers (keys only), or nullptr without instantiating them
-template <int DT, int NT, int EPT, bool ON>
+// multiway launchers (keys only), or nullptr without instantiating them.
+// The per-tile kernels run 512 threads over the same T-key tiles (twice the
+// waves of the two-way tile, to hide the latency of their LDS work).
+template <int DT, int NT0, int EPT0, bool ON>
 struct MultiFns {
+    static constexpr int NT = 512;
+    static constexpr int EPT = NT0 * EPT0 / NT;
+    static_assert(NT * EPT == NT0 * EPT0, "same tile size as the two-way step");
     static void plan(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_plan_multi<DT, NoVal, 256>), dim3(grid), dim3(256), 0, s, a);
     }

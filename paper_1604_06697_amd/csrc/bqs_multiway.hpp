@@ -100,6 +100,7 @@ __global__ __launch_bounds__(NT) void k_plan_multi(Args a) {
         for (int i = lane; i < k; i += 64) {
             const auto om = K::ord(ws[i]);
             int rank = 0;
+#pragma unroll 8
             for (int j = 0; j < k; ++j) {
                 const auto oj = K::ord(ws[j]);
                 rank += (oj < om) | ((oj == om) & (j < i));
@@ -318,9 +319,10 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
     }
 }
 
-// Per tile: keys staged in LDS in bucket order (a position per key from an
-// LDS counter per bucket), then every bucket's run copied out coalesced to
-// its place in the other buffer.
+// Per tile: keys staged in LDS in bucket order (a key's rank in its bucket
+// from one LDS counter per bucket, its position that rank past the bucket's
+// start in the tile), then every bucket's run copied out coalesced to its
+// place in the other buffer.
 template <int DT, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_mscatter(Args a) {
     using K = KeyT<DT>;
@@ -329,7 +331,7 @@ __global__ __launch_bounds__(NT) void k_mscatter(Args a) {
     __shared__ uint64_t s_spl[16];
     __shared__ R s_k[T];
     __shared__ uint8_t s_b[T];
-    __shared__ uint32_t s_cnt[kBStride], s_start[kBStride], s_cur[kBStride], s_off[kBStride];
+    __shared__ uint32_t s_cnt[kBStride], s_start[kBStride], s_off[kBStride];
     const Ctl* c = a.ctl;
     const int p = a.level & 1;
     const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
@@ -350,32 +352,31 @@ __global__ __launch_bounds__(NT) void k_mscatter(Args a) {
     const R* tsrc = static_cast<const R*>(p ? a.y_keys : a.x_keys) + tbase;
     R* dst = static_cast<R*>(p ? a.x_keys : a.y_keys) + td.lo;
     R key[EPT];
-    uint8_t bk[EPT];
+    uint32_t br[EPT];  // bucket | rank of the key among the tile's keys of that bucket << 8
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
         const int off = i * NT + tid;
         const bool ok = off >= sl && off < el;
         key[i] = ok ? tsrc[off] : R(0);
-        bk[i] = ok ? static_cast<uint8_t>(bucket_of(static_cast<uint64_t>(K::ord(key[i])), s_spl, u)) : uint8_t(0xff);
-        if (ok) atomicAdd(&s_cnt[bk[i]], 1u);
+        const uint32_t b = ok ? static_cast<uint32_t>(bucket_of(static_cast<uint64_t>(K::ord(key[i])), s_spl, u))
+                              : 0xffu;
+        br[i] = ok ? (b | (atomicAdd(&s_cnt[b], 1u) << 8)) : 0xffu;
     }
     __syncthreads();
     if (tid < 64) {
         // exclusive scan of the tile's bucket counts (one wave)
         const uint32_t v = lane < kBStride ? s_cnt[lane] : 0u;
         const uint32_t inc = static_cast<uint32_t>(wave_inclusive_sum(v, lane));
-        if (lane < kBStride) {
-            s_start[lane] = inc - v;
-            s_cur[lane] = inc - v;
-        }
+        if (lane < kBStride) s_start[lane] = inc - v;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        if (bk[i] != 0xff) {
-            const uint32_t pos = atomicAdd(&s_cur[bk[i]], 1u);
+        const uint32_t b = br[i] & 0xffu;
+        if (b != 0xffu) {
+            const uint32_t pos = s_start[b] + (br[i] >> 8);
             s_k[pos] = key[i];
-            s_b[pos] = bk[i];
+            s_b[pos] = static_cast<uint8_t>(b);
         }
     }
     __syncthreads();
