@@ -65,8 +65,8 @@ typedef enum {
 typedef enum {
     BQS_PARAM_SMALL_CUTOFF = 1, /* segments of at most this many keys are sorted inside one
                                    workgroup's LDS (clamped to the compiled maximum: 8192 for
-                                   4-byte keys, 4096 for 8-byte keys, 2048 for pairs; default
-                                   4096, or the maximum where that is smaller)                */
+                                   4-byte keys, 4096 for 8-byte keys, 2048 for pairs, which are
+                                   also the defaults)                                          */
     BQS_PARAM_SAMPLE_MAX = 2,   /* largest pivot sample (<= 255; default 127, 255 with
                                    BQS_PARAM_MULTIWAY); the pivot is the median of the sample
                                    (Section 2, pivot selection)                                */

@@ -1385,14 +1385,15 @@ __device__ void merge_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
 // threads holds 256/NTH groups, each group sorts one segment of at most
 // E*NTH keys.
 template <int DT, class V, int E, int NTH>
-__global__ __launch_bounds__(256) void k_small(Args a, int cls) {
+__global__ __launch_bounds__(NTH > 256 ? NTH : 256) void k_small(Args a, int cls) {
     using K = KeyT<DT>;
     using R = typename K::raw;
     using O = decltype(K::ord(R()));
     using VS = typename ValStore<V>::type;
     constexpr bool HV = !std::is_same<V, NoVal>::value;
     using It = SItem<O, HV>;
-    constexpr int G = 256 / NTH;     // groups per workgroup
+    constexpr int WG = NTH > 256 ? NTH : 256;  // workgroup size
+    constexpr int G = WG / NTH;      // groups per workgroup
     constexpr int P = E * NTH;       // items per group
     constexpr int PS = P + P / 16;   // padded LDS items per group (covers both pad rules)
     __shared__ O s_k[G * PS];
@@ -1536,7 +1537,7 @@ struct MultiFns<DT, NT, EPT, false> {
 template <int DT, class V, int E, int NTH>
 struct SmallLaunch {
     static void run(const Args& a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_small<DT, V, E, NTH>), dim3(grid), dim3(256), 0, s, a,
+        hipLaunchKernelGGL((k_small<DT, V, E, NTH>), dim3(grid), dim3(NTH > 256 ? NTH : 256), 0, s, a,
                            small_class(static_cast<int64_t>(E) * NTH));
     }
 };
@@ -1583,9 +1584,9 @@ struct Launch {
         static const Ops o{
             NT * EPT,
             SMAX,
-            // one partition pass more and 4096-key segments beat sorting up
-            // to 8192 keys in LDS (measured on 2^28 uniform int32 keys)
-            SMAX > 4096 ? 4096 : SMAX,
+            // default cutoff: the largest in-LDS size (measured best on 2^28
+            // uniform int32 keys)
+            SMAX,
             &plan,
             &map,
             {&SmallLaunch<DT, V, 1, 64>::run, &SmallLaunch<DT, V, 2, 64>::run,
@@ -1593,7 +1594,7 @@ struct Launch {
              SmallFn<DT, V, 16, 64, (SMAX >= 1024)>::get(),
              SmallFn<DT, V, 8, 256, (SMAX >= 2048)>::get(),
              SmallFn<DT, V, 16, 256, (SMAX >= 4096)>::get(),
-             SmallFn<DT, V, 32, 256, (SMAX >= 8192)>::get()},
+             SmallFn<DT, V, 16, 512, (SMAX >= 8192)>::get()},
             {4, 4, 4, 4, 4, 1, 1, 1},
             &tile,
             &complete,
