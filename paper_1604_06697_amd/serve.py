@@ -134,7 +134,11 @@ class SortService:
     one library context each)."""
 
     def __init__(self, budget_bytes: int, workers: int = 3, max_batch_keys: int = 1 << 27,
-                 graph: bool = False, clock=time.perf_counter, keep_output=lambda r: True):
+                 clock=time.perf_counter, keep_output=lambda r: True,
+                 params=None):
+        # library parameters of the workers' contexts; keys-only batches use
+        # the multiway partition step by default (pairs ignore it)
+        self.params = dict(multiway=1) if params is None else dict(params)
         self.keep_output = keep_output  # results of other requests are dropped once done
         self.budget = Budget(budget_bytes)
         self.max_batch_keys = int(max_batch_keys)
@@ -147,7 +151,7 @@ class SortService:
         self._closing = False
         self._errors: list = []
         self._ingest = torch.cuda.Stream()
-        self._workers = [threading.Thread(target=self._work, args=(i, graph), daemon=True)
+        self._workers = [threading.Thread(target=self._work, args=(i,), daemon=True)
                          for i in range(workers)]
         for w in self._workers:
             w.start()
@@ -185,9 +189,9 @@ class SortService:
             raise self._errors[0]
 
     # ------------------------------------------------------------ workers --
-    def _work(self, wid: int, graph: bool):
+    def _work(self, wid: int):
         stream = torch.cuda.Stream()
-        ctx = Context()
+        ctx = Context(**self.params)
         try:
             while True:
                 with self._cv:
