@@ -397,6 +397,40 @@ def pivot_study(torch, bqs, n, reps=3):
     return out
 
 
+def records(torch, bqs, n=1 << 23, reps=3):
+    """The paper's large element types: Vector (10 doubles, by the sum of
+    squares) and Record (21 int32, by the first component), n records each;
+    every call sorts from a pristine input into an output buffer."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    out = {}
+    for name, src in (("vector", torch.randn((n, 10), dtype=torch.float64, device="cuda", generator=g)),
+                      ("record", torch.randint(-(2**31), 2**31, (n, 21), dtype=torch.int32, device="cuda",
+                                               generator=g))):
+        dst = torch.empty_like(src)
+        ctx = bqs.Context()
+        times = []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sort_records(src, dst)
+            torch.cuda.synchronize()
+            if r:
+                times.append(time.perf_counter() - t0)
+        ms = 1e3 * min(times)
+        if name == "vector":
+            k = dst[:, 0] * dst[:, 0]
+            for i in range(1, 10):
+                k = k + dst[:, i] * dst[:, i]
+        else:
+            k = dst[:, 0]
+        ok = bool((k[1:] >= k[:-1]).all())
+        out[name] = {"n": n, "record_bytes": src.shape[1] * src.element_size(), "ms": round(ms, 3),
+                     "Mrecords/s": round(n / (ms * 1e-3) / 1e6, 1), "sorted": ok}
+        del src, dst
+    return out
+
+
 def record_bytes(kind):
     if kind.startswith("i32"):
         return 4
@@ -536,6 +570,7 @@ def main():
     if not args.no_dists:
         out["paper_families"] = paper_families(torch, bqs)
         out["pivot_study"] = pivot_study(torch, bqs, n)
+        out["records"] = records(torch, bqs)
 
     if not args.no_batched:
         out["segmented"] = batched_segments(torch, bqs, max(2, args.steps // 3), 1)

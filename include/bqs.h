@@ -206,6 +206,23 @@ bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int6
 bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offsets, int64_t k,
                                    int64_t n_total, bqs_dtype key, int32_t val_bytes, bqs_ctx* ctx);
 
+/* The paper's large element types (Section 4, experimental setup):
+ *   BQS_RECORD_VECTOR: 10 doubles (80 bytes), ordered by the sum of the
+ *     squares of the components (left to right, every product and sum
+ *     rounded, no fused multiply-add); no NaN or infinite components;
+ *   BQS_RECORD_RECORD: 21 int32 (84 bytes), ordered by the first component.
+ * bqs_sort_records sorts n records from `in` into `out` (device pointers,
+ * caller-owned, not overlapping each other or the workspace): it computes
+ * every record's key once, sorts (key, index) pairs with bqs_sort_pairs'
+ * machinery (host-driven; BQS_PARAM_GRAPH does not apply) and gathers the
+ * records in key order.  Records with equal keys come out in an unspecified
+ * order (Quicksort is not stable).  n >= 2^31 -> BQS_EINVAL; an unknown kind
+ * -> BQS_EDTYPE.  The workspace must hold bqs_records_workspace_bytes(n,
+ * kind) bytes. */
+typedef enum { BQS_RECORD_VECTOR = 1, BQS_RECORD_RECORD = 2 } bqs_record;
+size_t bqs_records_workspace_bytes(const bqs_ctx* ctx, int64_t n, int kind);
+bqs_status bqs_sort_records(const void* in, void* out, int64_t n, int kind, bqs_ctx* ctx);
+
 /* Synchronises the context's stream and returns the latched device status. */
 bqs_status bqs_ctx_sync_status(bqs_ctx* ctx);
 

@@ -64,7 +64,7 @@ class Stats:
 def compile_library(out: str = LIBRARY, mutant: int = 0) -> str:
     """Compiles the oracle with g++ (host only).  ``mutant`` > 0 plants one of
     the numbered mistakes used to show that the pins catch them."""
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", out, SOURCE]
+    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC", "-o", out, SOURCE]
     if mutant:
         cmd.insert(1, f"-DORACLE_MUTANT={int(mutant)}")
     subprocess.run(cmd, check=True)
@@ -86,6 +86,8 @@ class Oracle:
         L.oracle_sort_segments.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.c_int, P]
         L.oracle_sort_segments.restype = ctypes.c_int
+        L.oracle_sort_records.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, P]
+        L.oracle_sort_records.restype = ctypes.c_int
         L.oracle_partition.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int, P]
         L.oracle_partition.restype = ctypes.c_int64
@@ -136,6 +138,19 @@ class Oracle:
                          kw.get("check", False))
         self._rc(self.lib.oracle_sort_segments(a.ctypes.data, off.ctypes.data, off.size - 1,
                                                self._code(a), ctypes.byref(p)))
+        return a
+
+    def sort_records(self, recs: np.ndarray, **kw) -> np.ndarray:
+        """Sorts the paper's Vector records (n x 10 float64, by the sum of
+        squares) or Record records (n x 21 int32, by the first component)."""
+        a = np.ascontiguousarray(recs).copy()
+        if a.ndim != 2 or (a.dtype, a.shape[1]) not in ((np.dtype(np.float64), 10), (np.dtype(np.int32), 21)):
+            raise OracleError("records are n x 10 float64 (Vector) or n x 21 int32 (Record)")
+        kind = 1 if a.dtype == np.float64 else 2
+        p = self._params(kw.get("block", 0), kw.get("is_thresh", 0), kw.get("depth_limit", -1),
+                         kw.get("check", False))
+        self._rc(self.lib.oracle_sort_records(a.ctypes.data, a.shape[0], kind, ctypes.byref(p)))
+        self.last = Stats(p.comparisons, p.partitions, p.heapsorts, p.check_failures)
         return a
 
     def partition(self, keys: np.ndarray, lo: int = 0, hi: int | None = None, *, block=0):

@@ -34,7 +34,8 @@
 //   * Floating-point keys use the IEEE-754 total order restricted to
 //     non-NaN values: -0.0 < +0.0.  A NaN input is rejected.
 //
-// Build: g++ -O2 -std=c++17 -shared -fPIC -o liboracle.so bqs_oracle.cpp
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -shared -fPIC -o liboracle.so bqs_oracle.cpp
+// (no fused multiply-add: the Vector comparator rounds every product and sum)
 // A planted mistake for the pin tests is selected with -DORACLE_MUTANT=k.
 
 #include <cmath>
@@ -102,12 +103,36 @@ struct KeyLess<K, true> {
     }
 };
 
+// The paper's two large element types (Section 4, experimental setup):
+// Vector, ten doubles ordered by the sum of the squares of the components,
+// computed afresh at every comparison (left to right: x0*x0 + x1*x1 + ...);
+// Record, 21 int32 of which only the first is compared.
+struct VectorRec {
+    double x[10];
+};
+struct RecordRec {
+    int32_t x[21];
+};
+
+inline double sum_of_squares(const VectorRec& v) {
+    double s = v.x[0] * v.x[0];
+    for (int i = 1; i < 10; ++i) s = s + v.x[i] * v.x[i];
+    return s;
+}
+
+template <class R>
+inline bool rec_less(const R& a, const R& b) {
+    return KeyLess<decltype(a.key)>::lt(a.key, b.key);
+}
+inline bool rec_less(const VectorRec& a, const VectorRec& b) { return sum_of_squares(a) < sum_of_squares(b); }
+inline bool rec_less(const RecordRec& a, const RecordRec& b) { return a.x[0] < b.x[0]; }
+
 template <class R>
 struct Less {
     int64_t* count;
     bool operator()(const R& a, const R& b) const {
         ++*count;
-        return KeyLess<decltype(a.key)>::lt(a.key, b.key);
+        return rec_less(a, b);
     }
 };
 
@@ -508,6 +533,21 @@ int64_t oracle_partition(void* keys, int64_t lo, int64_t hi, int dtype, oracle_p
         case OR_F64: return partition_once_t<double>(keys, lo, hi, p);
         default: return -1;
     }
+}
+
+// Sorts n records of the paper's Vector (kind 1, 80 bytes) or Record (kind
+// 2, 84 bytes) type in place with their comparators.
+int oracle_sort_records(void* recs, int64_t n, int kind, oracle_params* p) {
+    if (n < 0 || (n > 0 && !recs) || !p) return OR_EINVAL;
+    if (kind == 1) {
+        block_quicksort(static_cast<VectorRec*>(recs), n, p);
+        return OR_OK;
+    }
+    if (kind == 2) {
+        block_quicksort(static_cast<RecordRec*>(recs), n, p);
+        return OR_OK;
+    }
+    return OR_EDTYPE;
 }
 
 int oracle_mutant(void) { return ORACLE_MUTANT; }

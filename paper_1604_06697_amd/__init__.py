@@ -46,6 +46,7 @@ PARAM_MODE = 8
 PARAM_GRAPH = 9
 PARAM_LOOKBACK = 10
 PARAM_MULTIWAY = 11
+RECORD_VECTOR, RECORD_RECORD = 1, 2
 MODE_LEVELS, MODE_QUEUE = 0, 1
 
 _TORCH_DTYPES = {
@@ -62,7 +63,8 @@ EXPORTED = [
     "bqs_ctx_create", "bqs_ctx_destroy", "bqs_ctx_set_stream", "bqs_ctx_set_workspace",
     "bqs_ctx_set_param", "bqs_ctx_get_param", "bqs_ctx_get_stats", "bqs_ctx_get_level",
     "bqs_workspace_bytes",
-    "bqs_sort", "bqs_sort_pairs", "bqs_sort_segments", "bqs_sort_segments_pairs", "bqs_ctx_sync_status",
+    "bqs_sort", "bqs_sort_pairs", "bqs_sort_segments", "bqs_sort_segments_pairs",
+    "bqs_records_workspace_bytes", "bqs_sort_records", "bqs_ctx_sync_status",
     "bqs_status_str", "bqs_version",
 ]
 
@@ -123,6 +125,8 @@ def _load(path: str = LIBRARY) -> ctypes.CDLL:
         "bqs_sort_pairs": ([vp, vp, i64, ctypes.c_int, i32, vp], st),
         "bqs_sort_segments": ([vp, vp, i64, i64, ctypes.c_int, vp], st),
         "bqs_sort_segments_pairs": ([vp, vp, vp, i64, i64, ctypes.c_int, i32, vp], st),
+        "bqs_records_workspace_bytes": ([vp, i64, ctypes.c_int], sz),
+        "bqs_sort_records": ([vp, vp, i64, ctypes.c_int, vp], st),
         "bqs_ctx_sync_status": ([vp], st),
         "bqs_status_str": ([st], ctypes.c_char_p),
         "bqs_version": ([], ctypes.c_int),
@@ -278,6 +282,30 @@ class Context:
                    "bqs_sort_segments")
         return keys
 
+    def sort_records(self, recs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """The paper's record types: an (n, 10) float64 tensor of Vector
+        records (ordered by the sum of squares) or an (n, 21) int32 tensor of
+        Record records (ordered by the first component); returns the records
+        in key order in `out` (a new tensor by default)."""
+        if not recs.is_cuda or recs.dim() != 2 or not recs.is_contiguous():
+            raise BqsError(1, "records must be a 2-D contiguous GPU tensor")
+        if recs.dtype == torch.float64 and recs.shape[1] == 10:
+            kind = RECORD_VECTOR
+        elif recs.dtype == torch.int32 and recs.shape[1] == 21:
+            kind = RECORD_RECORD
+        else:
+            raise BqsError(2, "records are (n, 10) float64 or (n, 21) int32")
+        if out is None:
+            out = torch.empty_like(recs)
+        elif out.shape != recs.shape or out.dtype != recs.dtype or not out.is_contiguous():
+            raise BqsError(1, "out must match the records' shape and dtype")
+        n = recs.shape[0]
+        with self._lock, torch.cuda.device(recs.device):
+            self._prepare(recs.device, int(lib.bqs_records_workspace_bytes(self._h, n, kind)))
+            _check(lib.bqs_sort_records(ctypes.c_void_p(recs.data_ptr()), ctypes.c_void_p(out.data_ptr()), n,
+                                        kind, self._h), "bqs_sort_records")
+        return out
+
     def sort_segments_pairs(self, keys: torch.Tensor, vals: torch.Tensor, offsets: torch.Tensor,
                             key_type=None):
         self._check_tensor(keys, "keys")
@@ -329,3 +357,7 @@ def sort_segments(keys: torch.Tensor, offsets: torch.Tensor, ctx: Context | None
 def sort_segments_pairs(keys: torch.Tensor, vals: torch.Tensor, offsets: torch.Tensor,
                         ctx: Context | None = None, key_type=None):
     return (ctx or default_context()).sort_segments_pairs(keys, vals, offsets, key_type)
+
+
+def sort_records(recs: torch.Tensor, out: torch.Tensor | None = None, ctx: Context | None = None):
+    return (ctx or default_context()).sort_records(recs, out)

@@ -211,6 +211,44 @@ void launch_qbin(const Args& a, hipStream_t s) {
     hipLaunchKernelGGL(k_qbin, dim3(256), dim3(256), 0, s, a);
 }
 
+// ------------------------------------------------------------- records --
+// The paper's large element types (Section 4, experimental setup), sorted as
+// (key, index) pairs and then gathered.  Vector: ten doubles ordered by the
+// sum of the squares of the components, summed left to right with every
+// product and sum rounded (no fused multiply-add), as the comparison
+// computes it.  Record: 21 int32 ordered by the first component.
+
+__global__ __launch_bounds__(256) void k_vector_keys(const double* in, int64_t n, double* keys, uint32_t* idx) {
+#pragma clang fp contract(off)
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* v = in + i * 10;
+    double s = v[0] * v[0];
+#pragma unroll
+    for (int k = 1; k < 10; ++k) s = s + v[k] * v[k];
+    keys[i] = s;
+    idx[i] = static_cast<uint32_t>(i);
+}
+
+__global__ __launch_bounds__(256) void k_record_keys(const int32_t* in, int64_t n, int32_t* keys, uint32_t* idx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = in[i * 21];
+    idx[i] = static_cast<uint32_t>(i);
+}
+
+// out record i = in record idx[i], one 4-byte word per thread (W words per
+// record): consecutive threads write consecutive words.
+__global__ __launch_bounds__(256) void k_gather_words(const uint32_t* in, const uint32_t* idx, int64_t n, int W,
+                                                      uint32_t* out) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; x < n * W; x += stride) {
+        const int64_t i = x / W;
+        const int w = static_cast<int>(x - i * W);
+        out[x] = in[static_cast<int64_t>(idx[i]) * W + w];
+    }
+}
+
 void launch_map(const Args& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_map, dim3(grid), dim3(256), 0, s, a);
 }
@@ -791,6 +829,19 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     return BQS_OK;
 }
 
+struct RecordKind {
+    int key_dtype;  // key type of the (key, index) sort
+    int words;      // 4-byte words per record
+};
+bool record_kind(int kind, RecordKind& rk) {
+    if (kind == BQS_RECORD_VECTOR) rk = {BQS_F64, 20};
+    else if (kind == BQS_RECORD_RECORD) rk = {BQS_I32, 21};
+    else return false;
+    return true;
+}
+size_t record_head(int64_t n, const RecordKind& rk) {
+    return align_up(static_cast<size_t>(n) * key_bytes(rk.key_dtype)) + align_up(static_cast<size_t>(n) * 4);
+}
 bqs_status finish(bqs_ctx* ctx, bqs_status st) {
     if (st != BQS_OK) ctx->latched = st;
     return st;
@@ -975,6 +1026,67 @@ bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offset
     if (st != BQS_OK) return st;
     a.offsets = offsets;
     return finish(ctx, run_sort(ctx, o, a, true));
+}
+
+// ------------------------------------------------------------- records --
+
+size_t bqs_records_workspace_bytes(const bqs_ctx* ctx, int64_t n, int kind) {
+    RecordKind rk;
+    if (n < 0 || !record_kind(kind, rk)) return 0;
+    return record_head(n, rk) + bqs_workspace_bytes(ctx, std::max<int64_t>(n, 2), static_cast<bqs_dtype>(rk.key_dtype),
+                                                    4, 1);
+}
+
+bqs_status bqs_sort_records(const void* in, void* out, int64_t n, int kind, bqs_ctx* ctx) {
+    RecordKind rk;
+    if (!ctx || n < 0 || (n > 0 && (!in || !out))) return BQS_EINVAL;
+    if (!record_kind(kind, rk)) return BQS_EDTYPE;
+    if (n >= (int64_t(1) << 31)) return BQS_EINVAL;
+    const size_t rec = static_cast<size_t>(rk.words) * 4;
+    if (overlaps(in, n * rec, out, n * rec) || overlaps(in, n * rec, ctx->ws, ctx->ws_bytes) ||
+        overlaps(out, n * rec, ctx->ws, ctx->ws_bytes))
+        return BQS_EINVAL;
+    ctx->stats = bqs_stats{};
+    if (n == 0) return BQS_OK;
+    const size_t head = record_head(n, rk);
+    if (!ctx->ws || ctx->ws_bytes < bqs_records_workspace_bytes(ctx, n, kind)) return BQS_EINVAL;
+    char* w = static_cast<char*>(ctx->ws);
+    void* keys = w;
+    uint32_t* idx = reinterpret_cast<uint32_t*>(w + align_up(static_cast<size_t>(n) * key_bytes(rk.key_dtype)));
+    const hipStream_t s = ctx->stream;
+    const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+    if (kind == BQS_RECORD_VECTOR)
+        hipLaunchKernelGGL(k_vector_keys, dim3(blocks), dim3(256), 0, s, static_cast<const double*>(in), n,
+                           static_cast<double*>(keys), idx);
+    else
+        hipLaunchKernelGGL(k_record_keys, dim3(blocks), dim3(256), 0, s, static_cast<const int32_t*>(in), n,
+                           static_cast<int32_t*>(keys), idx);
+    if (hipGetLastError() != hipSuccess) return finish(ctx, BQS_EHIP);
+    bqs_status st = BQS_OK;
+    if (n > 1) {
+        // the (key, index) sort runs in the rest of the workspace, host-driven
+        const Ops* o = select_ops(ctx, rk.key_dtype, 4);
+        if (!o) return BQS_EDTYPE;
+        void* ws0 = ctx->ws;
+        const size_t wb0 = ctx->ws_bytes;
+        const int64_t graph0 = ctx->graph;
+        ctx->ws = w + head;
+        ctx->ws_bytes = wb0 - head;
+        ctx->graph = 0;
+        Args a;
+        st = prepare(ctx, o, n, rk.key_dtype, 4, 1, keys, idx, a);
+        if (st == BQS_OK) st = run_sort(ctx, o, a, false);
+        ctx->ws = ws0;
+        ctx->ws_bytes = wb0;
+        ctx->graph = graph0;
+        if (st != BQS_OK) return finish(ctx, st);
+    }
+    const int64_t words = n * rk.words;
+    const unsigned gblocks = static_cast<unsigned>(std::min<int64_t>((words + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_gather_words, dim3(gblocks), dim3(256), 0, s, static_cast<const uint32_t*>(in), idx, n,
+                       rk.words, static_cast<uint32_t*>(out));
+    if (hipGetLastError() != hipSuccess) return finish(ctx, BQS_EHIP);
+    return BQS_OK;
 }
 
 bqs_status bqs_ctx_sync_status(bqs_ctx* ctx) {

@@ -457,6 +457,57 @@ def test_graph_bad_offsets_on_replay(torch_mod, bqs):
     assert e.value.status == 1
 
 
+# --------------------------------------------------------------- records --
+
+def _sum_sq(v):
+    # left to right, every product and sum rounded, as the comparator does
+    s = v[:, 0] * v[:, 0]
+    for i in range(1, 10):
+        s = s + v[:, i] * v[:, i]
+    return s
+
+
+def _rows_sorted(a):
+    return a[np.lexsort(a.T[::-1])]
+
+
+def test_records_match_oracle(torch_mod, bqs, oracle):
+    """The paper's Vector and Record types: the key sequence of the output
+    equals the oracle's bit for bit, and the output holds the same records
+    (records with equal keys may come in another order)."""
+    torch = torch_mod
+    for n in (0, 1, 2, 1000, 100_003, 1_000_000):
+        v = np.random.default_rng(n + 1).standard_normal((n, 10))
+        note(f"records vector n={n}")
+        got = bqs.sort_records(torch.from_numpy(v).cuda())
+        torch.cuda.synchronize()
+        g = got.cpu().numpy()
+        e = oracle.sort_records(v)
+        assert_same_bits(_sum_sq(g), _sum_sq(e))
+        assert np.array_equal(_rows_sorted(g), _rows_sorted(v))
+    rng = np.random.default_rng(3)
+    for n, spread in ((5000, 4), (300_007, 1000), (1_000_000, 2**31 - 1)):
+        r = rng.integers(-2**31, 2**31 - 1, size=(n, 21), dtype=np.int32)
+        r[:, 0] = rng.integers(-spread, spread, size=n)
+        note(f"records record n={n} spread={spread}")
+        got = bqs.sort_records(torch.from_numpy(r).cuda())
+        torch.cuda.synchronize()
+        g = got.cpu().numpy()
+        e = oracle.sort_records(r)
+        assert np.array_equal(g[:, 0], e[:, 0])
+        assert np.array_equal(_rows_sorted(g), _rows_sorted(r))
+
+
+def test_records_reject_bad_arguments(torch_mod, bqs):
+    torch = torch_mod
+    note("records bad arguments")
+    with pytest.raises(bqs.BqsError):
+        bqs.sort_records(torch.zeros((10, 9), dtype=torch.float64, device="cuda"))
+    t = torch.zeros((10, 21), dtype=torch.int32, device="cuda")
+    with pytest.raises(bqs.BqsError):
+        bqs.sort_records(t, out=t)  # out overlaps the input
+
+
 # ------------------------------------------------------------- contract --
 
 def test_workspace_too_small_is_rejected(torch_mod, bqs):

@@ -274,3 +274,52 @@ def test_planted_mistakes_are_caught(tmp_path, mutant):
     orc = oracle_mod.Oracle(path)
     assert orc.mutant() == mutant
     assert not pins_pass(orc), f"mutant {mutant} survived the pins"
+
+
+# ------------------------------------------------------------------ records --
+# The paper's Vector (10 x float64, by the sum of squares) and Record
+# (21 x int32, by the first component) types.
+
+def _sum_sq(v):
+    # left to right, every product and sum rounded, as the comparator does
+    s = v[:, 0] * v[:, 0]
+    for i in range(1, 10):
+        s = s + v[:, i] * v[:, i]
+    return s
+
+
+def _rows_sorted(a):
+    return a[np.lexsort(a.T[::-1])]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 17, 1000, 50_000])
+def test_oracle_vector_records(oracle, n):
+    v = np.random.default_rng(n + 5).standard_normal((n, 10))
+    out = oracle.sort_records(v, check=True)
+    assert oracle.last.check_failures == 0
+    k = _sum_sq(out)
+    assert np.all(k[1:] >= k[:-1])
+    assert np.array_equal(k, np.sort(_sum_sq(v)))
+    assert np.array_equal(_rows_sorted(out), _rows_sorted(v))
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 1000, 60_000])
+def test_oracle_record_records_with_ties(oracle, n):
+    rng = np.random.default_rng(n + 9)
+    r = rng.integers(-2**31, 2**31 - 1, size=(n, 21), dtype=np.int32)
+    r[:, 0] = rng.integers(-8, 8, size=n)  # many equal keys
+    out = oracle.sort_records(r, check=True)
+    assert oracle.last.check_failures == 0
+    assert np.array_equal(out[:, 0], np.sort(r[:, 0]))
+    assert np.array_equal(_rows_sorted(out), _rows_sorted(r))
+    # the order among equal keys is a valid one: only the first field is compared
+    assert np.all(np.diff(out[:, 0].astype(np.int64)) >= 0)
+
+
+def test_oracle_records_reject_other_shapes(oracle):
+    import oracle as O
+
+    with pytest.raises(O.OracleError):
+        oracle.sort_records(np.zeros((4, 9)))
+    with pytest.raises(O.OracleError):
+        oracle.sort_records(np.zeros((4, 21), dtype=np.int64))
