@@ -74,9 +74,10 @@ typedef enum {
                                    and last key (median-of-three, Section 2)                    */
     BQS_PARAM_TIMING = 4,       /* 1: time every partition / small-sort launch with HIP events */
     BQS_PARAM_TILE_EPT = 5,     /* keys per thread in a partition tile (8, 16 or 32; 0 = auto)  */
-    BQS_PARAM_GRID = 6,         /* workgroups per launch of the persistent kernels (0 = auto)  */
+    BQS_PARAM_GRID = 6,         /* workgroups of the persistent kernel (0 = all that can be
+                                   resident at once)                                            */
     BQS_PARAM_PROFILE = 7,      /* 1: count cycles and look-back rounds inside partition tiles */
-    BQS_PARAM_MODE = 8,         /* BQS_MODE_LEVELS (default) or BQS_MODE_QUEUE                  */
+    BQS_PARAM_MODE = 8,         /* BQS_MODE_LEVELS (default) or BQS_MODE_PERSISTENT              */
     BQS_PARAM_GRAPH = 9,        /* 1: capture the launches of a call into a HIP graph and replay
                                    it for later calls with the same buffers, sizes and parameters
                                    (see "Graph mode" below)                                     */
@@ -97,12 +98,27 @@ typedef enum {
 } bqs_param;
 
 /* Execution modes (BQS_PARAM_MODE).
- *   LEVELS: one partition launch per recursion level; the host reads the
- *           next level's size between levels (per-level statistics).
- *   QUEUE : the recursion as a device-resident work queue drained by one
- *           persistent kernel.  Closed: selecting it returns BQS_EINVAL (its
- *           kernel faulted on the device and the cause is not yet known). */
-typedef enum { BQS_MODE_LEVELS = 0, BQS_MODE_QUEUE = 1 } bqs_mode;
+ *   LEVELS    : one partition launch per recursion level; the host reads the
+ *               next level's size between levels (per-level statistics).
+ *   QUEUE     : the recursion as a device-resident work queue drained by one
+ *               persistent kernel.  Closed: selecting it returns BQS_EINVAL
+ *               (its kernel faulted on the device and the cause is not yet
+ *               known).
+ *   PERSISTENT: every level in one cooperative launch (Quicksort's main
+ *               loop, Algorithm 1, run on the device): the workgroups that
+ *               fit on the GPU at once drain each level's device-resident
+ *               lists -- pivots, equal runs and small segments, tile
+ *               descriptors, partition tiles, segment completion -- with a
+ *               grid-wide barrier between steps, and the loop ends on the
+ *               device when no segment is left to partition.  The host waits
+ *               once per call.  The small-sort cutoff is clamped to 4096
+ *               keys.  BQS_PARAM_GRAPH does not apply (one launch already);
+ *               BQS_PARAM_MULTIWAY = 1 returns BQS_EINVAL; per-level
+ *               statistics are not kept.  A barrier that waits more than
+ *               about a second (the GPU cannot hold the whole grid at once)
+ *               ends the launch and the call returns BQS_EHIP.  Results are
+ *               identical to LEVELS. */
+typedef enum { BQS_MODE_LEVELS = 0, BQS_MODE_QUEUE = 1, BQS_MODE_PERSISTENT = 2 } bqs_mode;
 
 /* Graph mode (BQS_PARAM_GRAPH = 1).  The first call with a given set of
  * buffers (keys, vals, offsets, workspace), sizes and parameters sorts with

@@ -47,7 +47,7 @@ PARAM_GRAPH = 9
 PARAM_LOOKBACK = 10
 PARAM_MULTIWAY = 11
 RECORD_VECTOR, RECORD_RECORD = 1, 2
-MODE_LEVELS, MODE_QUEUE = 0, 1
+MODE_LEVELS, MODE_QUEUE, MODE_PERSISTENT = 0, 1, 2
 
 _TORCH_DTYPES = {
     torch.int32: I32,

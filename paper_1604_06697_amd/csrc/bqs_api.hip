@@ -39,6 +39,12 @@ __global__ void k_init_single(Args a) {
     c->levels = 0;
     c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
     for (int i = 0; i < 8; ++i) c->prof[i] = 0;
+    c->bar_arrive = 0;
+    c->bar_gen = 0;
+    for (int x = 0; x < kMaxXcd; ++x) {
+        c->xcd_arrive[x][0] = 0;
+        c->xcd_n[x] = 0;
+    }
     const int64_t n = a.n;
     if (n > a.small_cut) {
         const int64_t T = a.tile_keys;
@@ -75,6 +81,12 @@ __global__ void k_zero_ctl(Args a) {
     c->levels = 0;
     c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
     for (int i = 0; i < 8; ++i) c->prof[i] = 0;
+    c->bar_arrive = 0;
+    c->bar_gen = 0;
+    for (int x = 0; x < kMaxXcd; ++x) {
+        c->xcd_arrive[x][0] = 0;
+        c->xcd_n[x] = 0;
+    }
 }
 
 // One thread per segment: validate the offsets, then route the segment to
@@ -130,29 +142,8 @@ __global__ __launch_bounds__(256) void k_init_segments(Args a) {
 // segment list is ordered by first tile) and writes the tile descriptor;
 // it also clears the tile's look-back status word.
 __global__ __launch_bounds__(256) void k_map(Args a) {
-    Ctl* c = a.ctl;
-    if (c->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
-    const int p = a.level & 1;
-    const unsigned long long sc = c->lc[p].segs;
-    const uint32_t nseg = static_cast<uint32_t>(sc);
-    const uint32_t ntile = static_cast<uint32_t>(sc >> 32);
-    const SegDesc* segs = a.segs[p];
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntile; t += gridDim.x * blockDim.x) {
-        uint32_t lo_i = 0, hi_i = nseg;
-        while (hi_i - lo_i > 1) {
-            const uint32_t mid = (lo_i + hi_i) >> 1;
-            if (segs[mid].t0 <= t) lo_i = mid; else hi_i = mid;
-        }
-        const SegDesc& sd = segs[lo_i];
-        TileDesc d;
-        d.lo = sd.lo;
-        d.hi = sd.hi;
-        d.pivot = sd.pivot;
-        d.t0 = sd.t0;
-        d.si = lo_i;
-        a.tile_desc[t] = d;
-        a.status[t] = 0;
-    }
+    if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
+    map_tiles(a, a.level, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // Clears the queue state (flags, status pool, counters).
@@ -363,6 +354,8 @@ struct bqs_ctx {
     std::vector<uint64_t> gkey;
     int glevels = 0;
     int64_t queue_grid = 0;  // resident workgroups of the queue kernel (cached)
+    int64_t persist_grid = 0;  // resident workgroups of the persistent kernel (cached per table)
+    const void* persist_ops = nullptr;
     bqs_stats stats{};
     bqs_status latched = BQS_OK;
     bqs::Ctl* pinned = nullptr;
@@ -393,6 +386,7 @@ const Ops* select_ops(const bqs_ctx* ctx, int dtype, int val_bytes) {
 int64_t eff_small_cut(const bqs_ctx* ctx, const Ops* o) {
     int64_t s = ctx && ctx->small_cut > 0 ? ctx->small_cut : o->small_default;
     if (s > o->small_max) s = o->small_max;
+    if (ctx && ctx->mode == BQS_MODE_PERSISTENT && s > o->persist_small_max) s = o->persist_small_max;
     if (s < 2) s = 2;
     return s;
 }
@@ -497,6 +491,7 @@ void fill_stats(bqs_stats& stats, const Ctl& c) {
 }
 
 bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented);
+bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented);
 void drop_graph(bqs_ctx* ctx);
 
 // Levels L0, L0+1, ... driven from the host: each level's counts are read
@@ -713,6 +708,7 @@ bqs_status run_graph(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
 // The entry points' common driver.
 bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     if (ctx->mode == BQS_MODE_QUEUE) return run_queue(ctx, o, a, segmented);
+    if (ctx->mode == BQS_MODE_PERSISTENT) return run_persist(ctx, o, a, segmented);
     if (ctx->graph) return run_graph(ctx, o, a, segmented);
     return run_levels(ctx, o, a, segmented);
 }
@@ -759,6 +755,50 @@ bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     if (err) return (err & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
     stats.partition_launches = 1;
     fill_stats(stats, *ctx->pinned);
+    ctx->stats = stats;
+    return BQS_OK;
+}
+
+// Persistent mode: init, then one cooperative launch of every workgroup the
+// GPU holds at once, which runs all levels; one host wait for the status.
+bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
+    if (a.ways) return BQS_EINVAL;  // the multiway step has no persistent form
+    bqs_status st = ensure_device_state(ctx);
+    if (st != BQS_OK) return st;
+    const hipStream_t s = ctx->stream;
+    Timer tm{ctx, ctx->timing != 0};
+    tm.resolve(ctx->stats);
+    bqs_stats stats{};
+    stats.tile_keys = o->tile_keys;
+    stats.small_cutoff = a.small_cut;
+    ctx->level_keys.clear();
+    ctx->level_ms.clear();
+    if (ctx->persist_grid <= 0 || ctx->persist_ops != o) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return BQS_EHIP;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return BQS_EHIP;
+        const int per = o->persist_blocks_per_cu();
+        if (per <= 0 || cus <= 0) return BQS_EHIP;
+        ctx->persist_grid = static_cast<int64_t>(per) * cus;
+        ctx->persist_ops = o;
+    }
+    const int grid = static_cast<int>(ctx->grid > 0 ? std::min<int64_t>(ctx->grid, ctx->persist_grid)
+                                                    : ctx->persist_grid);
+    a.prof = 0;
+    if (segmented) launch_init_segments(a, s);
+    else launch_init_single(a, s);
+    tm.start();
+    const hipError_t e = o->persist(a, grid, s);
+    tm.stop(2, 0);
+    if (e != hipSuccess || hipGetLastError() != hipSuccess) return BQS_EHIP;
+    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+    tm.resolve(stats);
+    const unsigned err = ctx->pinned->error;
+    if (err & ERR_OFFSETS) return BQS_EINVAL;
+    if (err & ERR_STALL) return BQS_EHIP;
+    if (err) return BQS_EOVERFLOW;
+    fill_stats(stats, *ctx->pinned);
+    stats.partition_launches = 1;
     ctx->stats = stats;
     return BQS_OK;
 }
@@ -910,10 +950,11 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
         case BQS_PARAM_MODE:
             // The work-queue kernel took a memory-aperture fault on its first
             // input with partition tiles (n = 8193 int32) and the cause is not
-            // known; the mode stays closed until it is.
-            if (value != BQS_MODE_LEVELS) return BQS_EINVAL;
+            // known; that mode stays closed until it is.
+            if (value != BQS_MODE_LEVELS && value != BQS_MODE_PERSISTENT) return BQS_EINVAL;
             ctx->mode = value;
             ctx->queue_grid = 0;
+            drop_graph(ctx);
             break;
         default: return BQS_EINVAL;
     }

@@ -85,6 +85,8 @@ struct LevelCtr {
 
 enum : unsigned { ERR_OVERFLOW = 1u, ERR_OFFSETS = 2u, ERR_STALL = 4u };
 
+constexpr int kMaxXcd = 16;  // XCD ids the persistent barrier can index (MI355X has 8)
+
 // ---- work-queue mode --------------------------------------------------------
 // The recursion as a device-resident queue: items are published into a
 // linear array (a flag per slot, set after a release fence) and claimed in
@@ -134,6 +136,13 @@ struct Ctl {
     // profile counters (only with Args::prof): tiles, look-back rounds,
     // look-back polls, look-back cycles, tile cycles, load+count cycles
     unsigned long long prof[8];
+    // persistent mode: grid barrier.  Global arrivals (one per XCD) and the
+    // generation that waiting workgroups poll, each on a line of its own;
+    // arrivals per XCD (one line each); resident workgroups per XCD.
+    alignas(256) unsigned int bar_arrive;
+    alignas(256) unsigned int bar_gen;
+    alignas(256) unsigned int xcd_arrive[kMaxXcd][64];
+    unsigned int xcd_n[kMaxXcd];
 };
 
 struct Args {
@@ -198,7 +207,39 @@ struct Ops {
     void (*qinit)(const Args&, int grid, hipStream_t);
     void (*qrun)(const Args&, int grid, hipStream_t);
     int (*qblocks_per_cu)();
+    // persistent mode: every level in one cooperative launch of `grid`
+    // resident workgroups; small segments up to persist_small_max keys
+    hipError_t (*persist)(const Args&, int grid, hipStream_t);
+    int (*persist_blocks_per_cu)();
+    int persist_small_max;
 };
+
+// The map step of level `level`, as thread `gtid` of `gstride`: every tile
+// finds its segment (the list is ordered by first tile) and gets its
+// descriptor; its look-back status word is cleared.
+__device__ inline void map_tiles(const Args& a, int level, uint32_t gtid, uint32_t gstride) {
+    const int p = level & 1;
+    const unsigned long long sc = a.ctl->lc[p].segs;
+    const uint32_t nseg = static_cast<uint32_t>(sc);
+    const uint32_t ntile = static_cast<uint32_t>(sc >> 32);
+    const SegDesc* segs = a.segs[p];
+    for (uint32_t t = gtid; t < ntile; t += gstride) {
+        uint32_t lo_i = 0, hi_i = nseg;
+        while (hi_i - lo_i > 1) {
+            const uint32_t mid = (lo_i + hi_i) >> 1;
+            if (segs[mid].t0 <= t) lo_i = mid; else hi_i = mid;
+        }
+        const SegDesc& sd = segs[lo_i];
+        TileDesc d;
+        d.lo = sd.lo;
+        d.hi = sd.hi;
+        d.pivot = sd.pivot;
+        d.t0 = sd.t0;
+        d.si = lo_i;
+        a.tile_desc[t] = d;
+        a.status[t] = 0;
+    }
+}
 
 // Kernel tables, one per payload kind; nullptr for an unsupported request.
 const Ops* ops_keys(int dtype, int ept);

@@ -243,9 +243,10 @@ __device__ inline void push_fill(const Args& a, int slot, int64_t dst, int64_t l
 
 // Writes the equal-key runs recorded for level p into X: keys get the stored
 // bits of the run's key, pairs their payloads from the side buffer.  One
-// workgroup per work unit of kFillChunk keys (all NT threads).
+// workgroup per work unit of kFillChunk keys (all NT threads); `bid` of
+// `nblk` workgroups.
 template <int DT, class V, int NT>
-__device__ void run_fills(const Args& a, int p) {
+__device__ void run_fills(const Args& a, int p, uint32_t bid, uint32_t nblk) {
     using R = typename KeyT<DT>::raw;
     constexpr bool HV = !std::is_same<V, NoVal>::value;
     const Ctl* c = a.ctl;
@@ -254,7 +255,7 @@ __device__ void run_fills(const Args& a, int p) {
     const uint32_t nfill = static_cast<uint32_t>(fc);
     const uint32_t nchunk = static_cast<uint32_t>(fc >> 32);
     R* xk = static_cast<R*>(a.x_keys);
-    for (uint32_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    for (uint32_t ch = bid; ch < nchunk; ch += nblk) {
         // items are ordered by chunk0: find the last one starting at or before ch
         uint32_t lo_i = 0, hi_i = nfill;
         while (hi_i - lo_i > 1) {
@@ -274,10 +275,10 @@ __device__ void run_fills(const Args& a, int p) {
     }
 }
 
-// Block 0 of a plan kernel clears the lists that level p's partition fills
-// (slot q) and counts the level.
-__device__ inline void reset_next_slot(Ctl* c, int q, uint32_t nseg) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+// Workgroup 0 of a plan step clears the lists that level p's partition
+// fills (slot q) and counts the level.
+__device__ inline void reset_next_slot(Ctl* c, int q, uint32_t nseg, uint32_t bid) {
+    if (bid == 0 && threadIdx.x == 0) {
         c->lc[q].segs = 0;
         c->lc[q].fills = 0;
         for (int k = 0; k < kSmallClasses; ++k) c->lc[q].smalls[k] = 0;
@@ -299,27 +300,31 @@ __device__ inline void reset_next_slot(Ctl* c, int q, uint32_t nseg) {
 //  Block 0 also clears the counters of slot (L+1)&1, which the partition
 //  kernel of level L fills.
 
+template <int DT, int NT>
+struct PlanLds {
+    typename KeyT<DT>::raw samp[NT / 64][kMaxSample + 1];
+    typename KeyT<DT>::raw pick[NT / 64];
+};
+
+// The plan step as workgroup `bid` of `nblk` (all NT threads).
 template <int DT, class V, int NT>
-__global__ __launch_bounds__(NT) void k_plan(Args a) {
+__device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk, PlanLds<DT, NT>& lds) {
     using K = KeyT<DT>;
     using R = typename K::raw;
-    constexpr bool HV = !std::is_same<V, NoVal>::value;
     constexpr int NW = NT / 64;  // one wave per segment
     static_assert(kMaxSample < 4 * 64, "a lane holds at most four samples");
-    __shared__ R s_samp[NW][kMaxSample + 1];
-    __shared__ R s_pick[NW];
+    auto& s_pick = lds.pick;
 
     Ctl* c = a.ctl;
-    if (c->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
-    const int p = a.level & 1, q = p ^ 1;
+    const int p = level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
-    reset_next_slot(c, q, nseg);
+    reset_next_slot(c, q, nseg, bid);
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
-    R* ws = s_samp[wv];
+    R* ws = lds.samp[wv];
 
     // block-uniform trip count (the barriers below); wave wv takes segment base + wv
-    for (uint32_t base = blockIdx.x * NW; base < nseg; base += gridDim.x * NW) {
+    for (uint32_t base = bid * NW; base < nseg; base += nblk * NW) {
         const uint32_t si = base + wv;
         const bool valid = si < nseg;
         SegDesc* sd = &a.segs[p][valid ? si : 0];
@@ -383,7 +388,14 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
         __syncthreads();
     }
 
-    run_fills<DT, V, NT>(a, p);
+    run_fills<DT, V, NT>(a, p, bid, nblk);
+}
+
+template <int DT, class V, int NT>
+__global__ __launch_bounds__(NT) void k_plan(Args a) {
+    __shared__ PlanLds<DT, NT> s_lds;
+    if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
+    plan_body<DT, V, NT>(a, a.level, blockIdx.x, gridDim.x, s_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,31 +433,51 @@ struct TileOut {
     bool ok;            // the claimed ranges are consistent
 };
 
+// LDS of one partition tile: the staged keys (and payloads) plus T spare
+// slots for keys that stay behind, the per-(item, wave) counts, the tile
+// totals and the claimed offsets.  Kernels that run other work between tiles
+// share this space with it.
 template <int DT, class V, int NT, int EPT>
-__device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned long long* s_prof) {
+struct TileLds {
+    static constexpr bool HV = !std::is_same<V, NoVal>::value;
+    static constexpr int T = NT * EPT;
+    static constexpr int NE = EPT * (NT / 64);
+    // per-(item, wave) counts: less | greater (| equal for pairs) packed in
+    // FW-bit fields; prefix sums stay below 2^FW
+    using Cnt = typename std::conditional<HV, uint64_t, uint32_t>::type;
+    static constexpr int FW = HV ? 21 : 16;
+    typename KeyT<DT>::raw k[T + 64];
+    typename ValStore<V>::type v[HV ? T + 64 : 1];
+    Cnt cnt[NE];
+    Cnt tot;
+    int64_t ex[2];
+};
+
+template <int DT, class V, int NT, int EPT>
+__device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned long long* s_prof,
+                                                  TileLds<DT, V, NT, EPT>& lds) {
     using K = KeyT<DT>;
     using R = typename K::raw;
     using O = decltype(K::ord(R()));
     using VS = typename ValStore<V>::type;
     using Cls = typename std::conditional<(EPT <= 16), uint32_t, uint64_t>::type;
-    constexpr bool HV = !std::is_same<V, NoVal>::value;
-    constexpr int T = NT * EPT;
+    using LT = TileLds<DT, V, NT, EPT>;
+    constexpr bool HV = LT::HV;
+    constexpr int T = LT::T;
     constexpr int NW = NT / 64;
-    constexpr int NE = EPT * NW;
+    constexpr int NE = LT::NE;
     constexpr int C = (NE + 63) / 64;
     static_assert(EPT <= 32, "class codes are packed in 64 bits");
-    // per-(item, wave) counts: less | greater (| equal for pairs) packed in
-    // FW-bit fields; prefix sums stay below 2^FW
-    using Cnt = typename std::conditional<HV, uint64_t, uint32_t>::type;
-    constexpr int FW = HV ? 21 : 16;
+    using Cnt = typename LT::Cnt;
+    constexpr int FW = LT::FW;
     constexpr Cnt FM = (Cnt(1) << FW) - 1;
     static_assert(T < (1 << FW), "tile counts must fit their packed fields");
 
-    __shared__ R s_k[T + 64];
-    __shared__ VS s_v[HV ? T + 64 : 1];
-    __shared__ Cnt s_cnt[NE];
-    __shared__ Cnt s_tot;
-    __shared__ int64_t s_ex[2];
+    auto& s_k = lds.k;
+    auto& s_v = lds.v;
+    auto& s_cnt = lds.cnt;
+    auto& s_tot = lds.tot;
+    auto& s_ex = lds.ex;
 
     const int tid = static_cast<int>(threadIdx.x), lane = tid & 63, wv = tid >> 6;
     const bool prof = s_prof != nullptr;
@@ -643,12 +675,41 @@ __device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned lon
 }
 
 // ---------------------------------------------------------------------------
+// One tile of level `level` (all threads of the workgroup): the tile's
+// segment, buffers and claim form, then the partition.
+template <int DT, class V, int NT, int EPT>
+__device__ __forceinline__ void tile_body(const Args& a, int level, uint32_t tile, const TileDesc& td,
+                                          TileLds<DT, V, NT, EPT>& lds, unsigned long long* s_prof) {
+    Ctl* c = a.ctl;
+    const int p = level & 1;
+    const int tid = threadIdx.x;
+    TileIO io;
+    io.error = &c->error;
+    io.src = p ? a.y_keys : a.x_keys;
+    io.dst = p ? a.x_keys : a.y_keys;
+    io.vsrc = p ? a.y_vals : a.x_vals;
+    io.vdst = p ? a.x_vals : a.y_vals;
+    io.side = a.side;
+    io.status = a.status + td.t0;
+    SegDesc* seg = &a.segs[p][td.si];
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    // payloads keep the look-back: their equal-key runs are parked by tile order
+    const bool use_cursor = !HV && a.claim != 0;
+    io.cursor = use_cursor ? &seg->cursor : nullptr;
+    io.lo = td.lo;
+    io.hi = td.hi;
+    io.pivot = td.pivot;
+    io.j = tile - td.t0;
+    const TileOut r = tile_partition<DT, V, NT, EPT>(io, s_prof, lds);
+    if (!r.ok && tid == 0) atomicOr(&c->error, ERR_OVERFLOW);  // inconsistent claim: nothing was written
+}
+
 // Partition kernel, level mode: one tile per workgroup.  Tiles are claimed in
 // order through the level's ticket counter, so every tile that a look-back
 // waits for is held by a running workgroup.
-
 template <int DT, class V, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_partition(Args a) {
+    __shared__ TileLds<DT, V, NT, EPT> s_lds;
     __shared__ TileDesc s_desc;
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_prof[6];
@@ -669,25 +730,7 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     const uint32_t tile = s_tile;
     if (tile >= ntiles) return;
     const TileDesc td = s_desc;
-    TileIO io;
-    io.error = &c->error;
-    io.src = p ? a.y_keys : a.x_keys;
-    io.dst = p ? a.x_keys : a.y_keys;
-    io.vsrc = p ? a.y_vals : a.x_vals;
-    io.vdst = p ? a.x_vals : a.y_vals;
-    io.side = a.side;
-    io.status = a.status + td.t0;
-    SegDesc* seg = &a.segs[p][td.si];
-    constexpr bool HV = !std::is_same<V, NoVal>::value;
-    // payloads keep the look-back: their equal-key runs are parked by tile order
-    const bool use_cursor = !HV && a.claim != 0;
-    io.cursor = use_cursor ? &seg->cursor : nullptr;
-    io.lo = td.lo;
-    io.hi = td.hi;
-    io.pivot = td.pivot;
-    io.j = tile - td.t0;
-    const TileOut r = tile_partition<DT, V, NT, EPT>(io, a.prof ? s_prof : nullptr);
-    if (!r.ok && tid == 0) atomicOr(&c->error, ERR_OVERFLOW);  // inconsistent claim: nothing was written
+    tile_body<DT, V, NT, EPT>(a, a.level, tile, td, s_lds, a.prof ? s_prof : nullptr);
     if (a.prof) {
         __syncthreads();
         if (tid < 6) atomicAdd(&c->prof[tid], s_prof[tid]);
@@ -717,12 +760,13 @@ __device__ __forceinline__ uint64_t wave_append(unsigned long long* ctr, uint64_
     return bcast64(base, 63) + incl - inc;
 }
 
+// The completion step as workgroup `bid` of `nblk` workgroups of 256 threads.
 template <class V>
-__global__ __launch_bounds__(256) void k_complete(Args a) {
+__device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t nblk) {
     constexpr bool HV = !std::is_same<V, NoVal>::value;
+    constexpr uint32_t WG = 256;
     Ctl* c = a.ctl;
-    if (c->error & ERR_OFFSETS) return;
-    const int p = a.level & 1, q = p ^ 1;
+    const int p = level & 1, q = p ^ 1;
     const int lane = lane_id();
     const bool cursor = !HV && a.claim != 0;
     const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
@@ -732,7 +776,7 @@ __global__ __launch_bounds__(256) void k_complete(Args a) {
     // next level partitions
     unsigned long long fill_keys = 0, next_keys = 0, next_tiles = 0;
     // wave-uniform trip count: lanes past the list take part with nothing
-    for (uint32_t base = blockIdx.x * blockDim.x; base < nseg; base += gridDim.x * blockDim.x) {
+    for (uint32_t base = bid * WG; base < nseg; base += nblk * WG) {
         const uint32_t si = base + threadIdx.x;
         const bool valid = si < nseg;
         int64_t lo = 0, hi = 0, Lt = 0, Gt = 0;
@@ -860,6 +904,12 @@ __global__ __launch_bounds__(256) void k_complete(Args a) {
         }
         if (next_tiles) atomicAdd(&c->tiles, next_tiles);
     }
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_complete(Args a) {
+    if (a.ctl->error & ERR_OFFSETS) return;
+    complete_body<V>(a, a.level, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,6 +1134,7 @@ __device__ void q_complete(const Args& a, uint32_t si, int64_t Lt, int64_t Gt) {
 template <int DT, class V, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_queue(Args a) {
     constexpr bool HV = !std::is_same<V, NoVal>::value;
+    __shared__ TileLds<DT, V, NT, EPT> s_tl;
     __shared__ QItem s_item;
     __shared__ int s_exit;
     __shared__ int s_fin;
@@ -1141,7 +1192,7 @@ __global__ __launch_bounds__(NT) void k_queue(Args a) {
             io.hi = sd.hi;
             io.pivot = sd.pivot;
             io.j = it.j;
-            const TileOut r = tile_partition<DT, V, NT, EPT>(io, nullptr);
+            const TileOut r = tile_partition<DT, V, NT, EPT>(io, nullptr, s_tl);
             __threadfence();  // release this tile's output
             __syncthreads();
             if (tid == 0) {
@@ -1381,28 +1432,43 @@ __device__ void merge_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
     }
 }
 
-// One launch sorts the segments of one size class: a workgroup of 256
-// threads holds 256/NTH groups, each group sorts one segment of at most
+// The small sort of one size class: a workgroup of max(NTH, 256) threads
+// holds max(NTH, 256)/NTH groups, each group sorts one segment of at most
 // E*NTH keys.
 template <int DT, class V, int E, int NTH>
-__global__ __launch_bounds__(NTH > 256 ? NTH : 256) void k_small(Args a, int cls) {
+struct SmallLds {
+    using O = decltype(KeyT<DT>::ord(typename KeyT<DT>::raw()));
+    static constexpr bool HV = !std::is_same<V, NoVal>::value;
+    static constexpr int WG = NTH > 256 ? NTH : 256;  // workgroup size
+    static constexpr int G = WG / NTH;                 // groups per workgroup
+    static constexpr int P = E * NTH;                  // items per group
+    static constexpr int PS = P + P / 16;              // padded LDS items per group (covers both pad rules)
+    O k[G * PS];
+    uint32_t i[HV ? G * PS : 1];
+    typename ValStore<V>::type v[HV ? G * P : 1];
+    unsigned long long done[G];  // keys sorted by each group (statistics)
+};
+
+// The small sort of class `cls` as workgroup `bid` of `nblk`.
+template <int DT, class V, int E, int NTH>
+__device__ void small_body(const Args& a, int level, int cls, uint32_t bid, uint32_t nblk,
+                           SmallLds<DT, V, E, NTH>& lds) {
     using K = KeyT<DT>;
     using R = typename K::raw;
-    using O = decltype(K::ord(R()));
+    using SL = SmallLds<DT, V, E, NTH>;
+    using O = typename SL::O;
     using VS = typename ValStore<V>::type;
-    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    constexpr bool HV = SL::HV;
     using It = SItem<O, HV>;
-    constexpr int WG = NTH > 256 ? NTH : 256;  // workgroup size
-    constexpr int G = WG / NTH;      // groups per workgroup
-    constexpr int P = E * NTH;       // items per group
-    constexpr int PS = P + P / 16;   // padded LDS items per group (covers both pad rules)
-    __shared__ O s_k[G * PS];
-    __shared__ uint32_t s_i[HV ? G * PS : 1];
-    __shared__ VS s_v[HV ? G * P : 1];
+    constexpr int G = SL::G;
+    constexpr int P = SL::P;
+    constexpr int PS = SL::PS;
+    O* s_k = lds.k;
+    uint32_t* s_i = lds.i;
+    VS* s_v = lds.v;
 
     Ctl* c = a.ctl;
-    if (c->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
-    const int p = a.level & 1;
+    const int p = level & 1;
     const int tid = threadIdx.x;
     const int grp = tid / NTH;
     const int t = tid % NTH;
@@ -1420,10 +1486,10 @@ __global__ __launch_bounds__(NTH > 256 ? NTH : 256) void k_small(Args a, int cls
     O* sk = s_k + grp * PS;
     uint32_t* si = HV ? s_i + grp * PS : s_i;
     VS* sv = HV ? s_v + grp * P : s_v;
-    __shared__ unsigned long long s_done[G];  // keys sorted by each group (statistics)
+    unsigned long long* s_done = lds.done;
     unsigned long long my_keys = 0;
 
-    for (uint32_t base = blockIdx.x * G; base < nsm; base += gridDim.x * G) {
+    for (uint32_t base = bid * G; base < nsm; base += nblk * G) {
         const uint32_t it = base + grp;
         const bool have = it < nsm;
         int64_t lo = 0;
@@ -1486,6 +1552,201 @@ __global__ __launch_bounds__(NTH > 256 ? NTH : 256) void k_small(Args a, int cls
         unsigned long long sum = 0;
         for (int g = 0; g < G; ++g) sum += s_done[g];
         if (sum) atomicAdd(&c->small_keys, sum);
+    }
+}
+
+// One launch sorts the segments of one size class.
+template <int DT, class V, int E, int NTH>
+__global__ __launch_bounds__(NTH > 256 ? NTH : 256) void k_small(Args a, int cls) {
+    __shared__ SmallLds<DT, V, E, NTH> s_lds;
+    if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
+    small_body<DT, V, E, NTH>(a, a.level, cls, blockIdx.x, gridDim.x, s_lds);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent mode: the recursion of every level in one cooperative launch.
+// The resident workgroups drain the level's device lists step by step --
+// (1) pivots, equal runs and small sorts recorded by the previous level,
+// (2) tile descriptors, (3) partition tiles claimed in order with the
+// level's ticket counter, (4) segment completion, which appends the next
+// level's lists -- with a grid-wide barrier after each step.  The loop ends
+// on the device, at the first level with no segment left to partition, so
+// the host waits once per sort.  The steps run the same code as the
+// level-mode kernels.
+
+// Waits (one thread) until the barrier generation reaches `want`; 0 when
+// the wait ran out or another workgroup latched ERR_STALL.
+__device__ inline int wait_gen(Ctl* c, uint32_t want) {
+    const unsigned long long t0 = wall_clock64();
+    while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+        if (__hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_STALL) return 0;
+        if (wall_clock64() - t0 > kSpinTicks) {
+            atomicOr(&c->error, ERR_STALL);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return 1;
+}
+
+// Grid barriers.  On MI355X each XCD has its own L2, so a workgroup's
+// writes become visible to the other XCDs only once that L2 is written back
+// (agent-scope release), and a reader must drop what its CU and L2 hold
+// (agent-scope acquire).  Every wait is bounded by the wall clock: a barrier
+// that waits too long latches ERR_STALL, every other waiting workgroup sees
+// it and gives up too, and the launch ends; the functions then return false
+// in every thread and the caller leaves the kernel.
+
+// Plain barrier (used once, to count the workgroups of each XCD): thread 0
+// of each workgroup releases, counts itself in, and the last one to arrive
+// opens the next generation.
+__device__ inline bool grid_sync(Ctl* c, uint32_t nblk, uint32_t& gen, int* s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t want = gen + 1u;
+        int ok = 1;
+        __threadfence();
+        const uint32_t prev = atomicAdd(&c->bar_arrive, 1u);
+        if (prev == nblk - 1u) {
+            __hip_atomic_store(&c->bar_arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->bar_gen, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = wait_gen(c, want);
+        }
+        __threadfence();
+        gen = want;
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// Barrier with one L2 writeback per XCD.  Every thread waits for its own
+// stores to reach the L2; thread 0 then counts the workgroup in on its XCD's
+// counter.  The XCD's last workgroup writes the (shared) L2 back once for all
+// of them and counts the XCD in; the last XCD opens the next generation.
+// Acquire stays per workgroup.  `my_n`: resident workgroups on this
+// workgroup's XCD; `nxcd`: XCDs with resident workgroups.
+__device__ inline bool grid_sync_xcd(Ctl* c, uint32_t xcd, uint32_t my_n, uint32_t nxcd, uint32_t& gen, int* s_ok) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t want = gen + 1u;
+        const uint32_t prev = atomicAdd(&c->xcd_arrive[xcd][0], 1u);
+        if (prev == my_n - 1u) {
+            __hip_atomic_store(&c->xcd_arrive[xcd][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (atomicAdd(&c->bar_arrive, 1u) == nxcd - 1u) {
+                __hip_atomic_store(&c->bar_arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&c->bar_gen, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        const int ok = wait_gen(c, want);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        gen = want;
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// LDS of the persistent kernel: one region that each step views as its own
+// layout (steps are separated by barriers).
+template <int DT, class V, int NT, int EPT, int SP>
+struct PersistLds {
+    static constexpr size_t mx(size_t x, size_t y) { return x > y ? x : y; }
+    template <int E, int NTH>
+    static constexpr size_t small() {
+        return (NTH <= NT && E * NTH <= SP) ? sizeof(SmallLds<DT, V, E, NTH>) : 0;
+    }
+    static constexpr size_t bytes =
+        mx(mx(sizeof(TileLds<DT, V, NT, EPT>), sizeof(PlanLds<DT, NT>)),
+           mx(mx(mx(small<1, 64>(), small<2, 64>()), mx(small<4, 64>(), small<8, 64>())),
+              mx(small<16, 64>(), mx(small<8, 256>(), small<16, 256>()))));
+};
+
+template <int DT, class V, int NT, int E, int NTH, int SP>
+__device__ __forceinline__ void persist_small(const Args& a, int level, uint32_t bid, uint32_t nblk,
+                                              unsigned char* raw) {
+    if constexpr (NTH <= NT && E * NTH <= SP) {
+        const int cls = small_class(static_cast<int64_t>(E) * NTH);
+        if (a.ctl->lc[level & 1].smalls[cls] == 0) return;
+        small_body<DT, V, E, NTH>(a, level, cls, bid, nblk, *reinterpret_cast<SmallLds<DT, V, E, NTH>*>(raw));
+        __syncthreads();
+    }
+}
+
+template <int DT, class V, int NT, int EPT, int SP>
+__global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
+    static_assert(NT == 256, "the plan, map and completion steps run 256 threads");
+    using PL = PersistLds<DT, V, NT, EPT, SP>;
+    __shared__ alignas(16) unsigned char s_raw[PL::bytes];
+    __shared__ TileDesc s_desc;
+    __shared__ uint32_t s_tile;
+    __shared__ int s_ok;
+    Ctl* c = a.ctl;
+    if (c->error & ERR_OFFSETS) return;  // set by the init launch only: the same for every workgroup
+    const uint32_t bid = blockIdx.x, nblk = gridDim.x;
+    const int tid = threadIdx.x;
+    const int level_cap = 4 * a.depth_limit + 64;
+    uint32_t gen = 0;
+    // count the workgroups of each XCD (hardware register XCC_ID)
+    __shared__ uint32_t s_xn[2];
+    const uint32_t xcd = static_cast<uint32_t>(__builtin_amdgcn_s_getreg((3 << 11) | 20)) % kMaxXcd;
+    if (tid == 0) atomicAdd(&c->xcd_n[xcd], 1u);
+    if (!grid_sync(c, nblk, gen, &s_ok)) return;
+    if (tid == 0) {
+        uint32_t nx = 0;
+        for (int x = 0; x < kMaxXcd; ++x)
+            nx += __hip_atomic_load(&c->xcd_n[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+        s_xn[0] = __hip_atomic_load(&c->xcd_n[xcd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_xn[1] = nx;
+    }
+    __syncthreads();
+    const uint32_t my_n = s_xn[0], nxcd = s_xn[1];
+    for (int L = 0;; ++L) {
+        const int p = L & 1;
+        const unsigned long long sc = c->lc[p].segs;
+        const uint32_t nseg = static_cast<uint32_t>(sc);
+        const uint32_t ntile = static_cast<uint32_t>(sc >> 32);
+        // (1) pivots of level L; equal runs and small segments of level L-1
+        plan_body<DT, V, NT>(a, L, bid, nblk, *reinterpret_cast<PlanLds<DT, NT>*>(s_raw));
+        __syncthreads();
+        persist_small<DT, V, NT, 1, 64, SP>(a, L, bid, nblk, s_raw);
+        persist_small<DT, V, NT, 2, 64, SP>(a, L, bid, nblk, s_raw);
+        persist_small<DT, V, NT, 4, 64, SP>(a, L, bid, nblk, s_raw);
+        persist_small<DT, V, NT, 8, 64, SP>(a, L, bid, nblk, s_raw);
+        persist_small<DT, V, NT, 16, 64, SP>(a, L, bid, nblk, s_raw);
+        persist_small<DT, V, NT, 8, 256, SP>(a, L, bid, nblk, s_raw);
+        persist_small<DT, V, NT, 16, 256, SP>(a, L, bid, nblk, s_raw);
+        if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
+        if (nseg == 0) break;
+        if (L >= level_cap) {
+            if (bid == 0 && tid == 0) atomicOr(&c->error, ERR_OVERFLOW);
+            break;
+        }
+        // (2) tile descriptors
+        map_tiles(a, L, bid * NT + tid, nblk * NT);
+        if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
+        // (3) partition tiles, claimed in order
+        auto& tl = *reinterpret_cast<TileLds<DT, V, NT, EPT>*>(s_raw);
+        for (;;) {
+            if (tid == 0) {
+                const uint32_t t = atomicAdd(&c->lc[p].tile_next, 1u);
+                s_tile = t;
+                if (t < ntile) s_desc = a.tile_desc[t];
+            }
+            __syncthreads();
+            const uint32_t tile = s_tile;
+            if (tile >= ntile) break;
+            const TileDesc td = s_desc;
+            tile_body<DT, V, NT, EPT>(a, L, tile, td, tl, nullptr);
+            __syncthreads();  // the tile's LDS, s_tile and s_desc are free again
+        }
+        if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
+        // (4) completion: the lists of level L+1
+        complete_body<V>(a, L, bid, nblk);
+        if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
     }
 }
 
@@ -1580,6 +1841,21 @@ struct Launch {
         return nb;
     }
     static void map(const Args& a, int grid, hipStream_t s) { launch_map(a, grid, s); }
+    // persistent mode: small segments up to 4096 keys (the classes whose
+    // groups fit a 256-thread workgroup)
+    static constexpr int kPersistSmall = SMAX < 4096 ? SMAX : 4096;
+    static hipError_t persist(const Args& a, int grid, hipStream_t s) {
+        void* args[] = {const_cast<Args*>(&a)};
+        return hipLaunchCooperativeKernel(k_persist<DT, V, NT, EPT, kPersistSmall>, dim3(grid), dim3(NT), args, 0,
+                                          s);
+    }
+    static int persist_blocks_per_cu() {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<DT, V, NT, EPT, kPersistSmall>, NT, 0) !=
+            hipSuccess)
+            return 0;
+        return nb;
+    }
     static const Ops* ops() {
         static const Ops o{
             NT * EPT,
@@ -1604,7 +1880,10 @@ struct Launch {
             MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::sa(),
             &qinit,
             &qrun,
-            &qblocks_per_cu};
+            &qblocks_per_cu,
+            &persist,
+            &persist_blocks_per_cu,
+            kPersistSmall};
         return &o;
     }
 };

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(NT) void k_plan_multi(Args a) {
     const int p = a.level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
-    reset_next_slot(c, q, nseg);
+    reset_next_slot(c, q, nseg, blockIdx.x);
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
     R* ws = s_samp[wv];
     R* so = s_sorted[wv];
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_plan_multi(Args a) {
         }
         __syncthreads();
     }
-    run_fills<DT, V, NT>(a, p);
+    run_fills<DT, V, NT>(a, p, blockIdx.x, gridDim.x);
 }
 
 // Loads the splitters of segment si into LDS (16 entries, all threads) and

@@ -61,6 +61,22 @@ def test_ctx_params_roundtrip(bqs):
     with pytest.raises(bqs.BqsError):
         ctx.set_param("mode", bqs.MODE_QUEUE)
     assert ctx.get_param("mode") == bqs.MODE_LEVELS
+    ctx.set_param("mode", bqs.MODE_PERSISTENT)
+    assert ctx.get_param("mode") == bqs.MODE_PERSISTENT
+    with pytest.raises(bqs.BqsError):
+        ctx.set_param("mode", 3)
+    assert ctx.get_param("mode") == bqs.MODE_PERSISTENT
+
+
+def test_persistent_mode_clamps_the_cutoff_in_the_workspace_size(bqs):
+    # the persistent kernel sorts small segments of at most 4096 keys, so
+    # its lists are sized for that cutoff
+    n = 1 << 22
+    lv = bqs.Context(small_cutoff=8192)
+    ps = bqs.Context(small_cutoff=8192, mode=bqs.MODE_PERSISTENT)
+    p4 = bqs.Context(small_cutoff=4096, mode=bqs.MODE_PERSISTENT)
+    ws = bqs.lib.bqs_workspace_bytes
+    assert ws(ps._h, n, bqs.I32, 0, 1) == ws(p4._h, n, bqs.I32, 0, 1) > ws(lv._h, n, bqs.I32, 0, 1)
 
 
 def test_workspace_bytes(bqs):

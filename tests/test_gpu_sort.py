@@ -569,3 +569,125 @@ def test_full_size_2p28_uniform_properties(torch_mod, bqs):
     torch.cuda.synchronize()
     for i in idx[:4]:
         assert int(t[int(i)]) == int(np.partition(host, int(i))[int(i)])
+
+
+# ------------------------------------------------------- persistent mode --
+# Every level in one cooperative launch (grid barriers between the steps).
+# The results must be the oracle's, as in the level-by-level mode.
+
+def _pctx(bqs, **kw):
+    return bqs.Context(mode=bqs.MODE_PERSISTENT, **kw)
+
+
+def test_persistent_int32_families(torch_mod, bqs, oracle):
+    ctx = _pctx(bqs)
+    fams = dict(W.I32_FAMILIES)
+    fams.update(W.I32_EXTRA_FAMILIES)
+    for fam, gen in fams.items():
+        for n in (0, 1, 2, 4096, 4097, 8192 * 3, 8192 * 7 + 5, 1_000_003):
+            a = gen(n, 23)
+            note(f"persistent {fam} n={n}")
+            assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+        s = ctx.stats()
+        assert s["partition_launches"] == 1 and s["small_cutoff"] <= 4096
+
+
+def test_persistent_deep_recursion_and_grids(torch_mod, bqs, oracle):
+    """Small cutoffs give many levels (four barriers each); smaller grids
+    give workgroups several tiles per level."""
+    for cut, grid in ((2, 0), (16, 0), (300, 64), (4096, 8), (100, 1)):
+        ctx = _pctx(bqs, small_cutoff=cut, grid=grid)
+        a = W.uniform_i32(200_003, cut + grid)
+        note(f"persistent cutoff={cut} grid={grid}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+        assert ctx.stats()["levels"] >= 1
+
+
+def test_persistent_key_types_and_specials(torch_mod, bqs, oracle):
+    ctx = _pctx(bqs)
+    rng = np.random.Generator(np.random.PCG64(37))
+    for dt in (np.uint32, np.int64, np.uint64):
+        a = rng.integers(np.iinfo(dt).min, np.iinfo(dt).max, size=700_001, dtype=dt, endpoint=True)
+        note(f"persistent {np.dtype(dt).name}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+    for fam, gen in W.F64_FAMILIES.items():
+        a = gen(600_007, 6)
+        note(f"persistent f64 {fam}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+    a = W.special_f64(200_000, 4)
+    note("persistent f64/f32 specials")
+    assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+    with np.errstate(over="ignore"):
+        f = a.astype(np.float32)
+    assert_same_bits(gpu_sort(torch_mod, bqs, f, ctx), oracle.sort(f))
+
+
+def test_persistent_pairs(torch_mod, bqs, oracle):
+    ctx = _pctx(bqs)
+    for n in (2, 2049, 100_000, 1 << 20):
+        k, v = W.uniform_u64_pairs(n, n + 1)
+        note(f"persistent pairs u64/u32 n={n}")
+        ko, vo = gpu_pairs(torch_mod, bqs, k, v, ctx)
+        check_pairs(k, ko, vo, oracle.sort(k))
+    k, v = W.tied_u64_pairs(300_000, 4)
+    note("persistent pairs tied u64/u64")
+    ko, vo = gpu_pairs(torch_mod, bqs, k, v.astype(np.uint64), ctx)
+    check_pairs(k, ko, vo, oracle.sort(k))
+    a = W.few_distinct_i32(300_000, 6)
+    note("persistent pairs i32 few-distinct")
+    ko, vo = gpu_pairs(torch_mod, bqs, a, np.arange(a.size, dtype=np.uint32), ctx)
+    check_pairs(a, ko, vo, oracle.sort(a))
+
+
+def test_persistent_segments(torch_mod, bqs, oracle):
+    ctx = _pctx(bqs)
+    for k, hi in [(1, 10.0), (50, 14.0), (2000, 16.0)]:
+        keys, offsets = W.segmented_i32(k, k + 3, 0.0, hi)
+        note(f"persistent segments k={k} n={keys.size}")
+        assert_same_bits(gpu_segments(torch_mod, bqs, keys, offsets, ctx), oracle.sort_segments(keys, offsets))
+    sizes = np.array([0, 1, 0, 2, 9000, 0, 1, 30_000, 3, 0], dtype=np.int64)
+    offsets = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    keys = W.uniform_i32(int(offsets[-1]), 2)
+    note("persistent segments with empties")
+    assert_same_bits(gpu_segments(torch_mod, bqs, keys, offsets, ctx), oracle.sort_segments(keys, offsets))
+    bad = np.array([0, 600, 500, 1000], dtype=np.int64)
+    note("persistent segments bad offsets")
+    with pytest.raises(bqs.BqsError) as e:
+        gpu_segments(torch_mod, bqs, W.uniform_i32(1000, 0), bad, ctx)
+    assert e.value.status == 1
+
+
+def test_persistent_records(torch_mod, bqs, oracle):
+    torch = torch_mod
+    ctx = _pctx(bqs)
+    v = np.random.default_rng(5).standard_normal((100_003, 10))
+    note("persistent records vector")
+    g = ctx.sort_records(torch.from_numpy(v).cuda()).cpu().numpy()
+    assert_same_bits(_sum_sq(g), _sum_sq(oracle.sort_records(v)))
+    assert np.array_equal(_rows_sorted(g), _rows_sorted(v))
+
+
+def test_persistent_rejects_multiway(torch_mod, bqs):
+    note("persistent + multiway rejected")
+    t = to_dev(torch_mod, W.uniform_i32(100_000, 0))
+    with pytest.raises(bqs.BqsError) as e:
+        _pctx(bqs, multiway=1).sort(t)
+    assert e.value.status == 1
+
+
+def test_persistent_full_size_2p28(torch_mod, bqs):
+    """2^28 int32 keys in one persistent launch: equal to torch.sort of the
+    same input (an independent library routine)."""
+    torch = torch_mod
+    n = 1 << 28
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    note("persistent 2^28 uniform int32")
+    t = torch.randint(-(2**31), 2**31, (n,), dtype=torch.int32, device="cuda", generator=g)
+    ref = torch.sort(t).values
+    ctx = _pctx(bqs)
+    ctx.sort(t)
+    torch.cuda.synchronize()
+    assert bool(torch.equal(t, ref))
+    s = ctx.stats()
+    assert s["partition_launches"] == 1 and s["levels"] >= 15
