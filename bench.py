@@ -370,15 +370,31 @@ def paper_families(torch, bqs, n=1 << 26, reps=3):
     return {"n": n, "families": out}
 
 
+PIVOT_STRATEGIES = (
+    ("median_of_3", {"pivot_mode": 3}),
+    ("median_of_5", {"pivot_mode": 5}),
+    ("median_of_23", {"pivot_mode": 23}),
+    ("mo3_of_mo3", {"pivot_mode": 33}),
+    ("mo3_of_mo5", {"pivot_mode": 35}),
+    ("mo5_of_mo5", {"pivot_mode": 55}),
+    ("median_of_sqrt_n", {"pivot_mode": 1}),
+    ("median_of_sample", {}),
+    ("skew_4", {"pivot_skew": 4}),
+    ("skew_16", {"pivot_skew": 16}),
+)
+
+
 def pivot_study(torch, bqs, n, reps=3):
-    """Median of three (the paper's pivot) against the median of a sample
-    (the default), on the headline input."""
+    """The paper's pivot strategies (Section 4: median of 3, 5, 23; medians
+    of medians; median of sqrt(n); skewed pivots, here the 1/s quantile of
+    the default sample) against the default median of a sample, on the
+    headline input."""
     g = torch.Generator(device="cuda")
     g.manual_seed(0)
     pristine = torch.randint(-(2**31), 2**31, (n,), dtype=torch.int32, device="cuda", generator=g)
     t = torch.empty_like(pristine)
     out = {}
-    for name, params in (("median_of_3", {"pivot_mode": 3}), ("median_of_sample", {})):
+    for name, params in PIVOT_STRATEGIES:
         ctx = bqs.Context(timing=1, **params)
         times = []
         for r in range(reps + 1):

@@ -70,8 +70,17 @@ typedef enum {
     BQS_PARAM_SAMPLE_MAX = 2,   /* largest pivot sample (<= 255; default 127, 255 with
                                    BQS_PARAM_MULTIWAY); the pivot is the median of the sample
                                    (Section 2, pivot selection)                                */
-    BQS_PARAM_PIVOT_MODE = 3,   /* 0: median of a stratified sample; 3: median of first, middle
-                                   and last key (median-of-three, Section 2)                    */
+    BQS_PARAM_PIVOT_MODE = 3,   /* pivot strategy (Section 2; Section 4, pivot selection):
+                                   0  median of a stratified sample of about sqrt(m)/4 keys
+                                      (7 .. BQS_PARAM_SAMPLE_MAX; default);
+                                   1  median of sqrt(m) keys (at most BQS_PARAM_SAMPLE_MAX),
+                                      median of five medians of five below 20000 keys;
+                                   3  median of the first, middle and last key;
+                                   5, 23  median of 5 / 23 stratified keys;
+                                   33, 35, 55  median of three medians of three, of three
+                                      medians of five, of five medians of five.
+                                   Past the depth limit 2 log2 n + 3 every strategy takes the
+                                   largest sample.  Other values: BQS_EINVAL                    */
     BQS_PARAM_TIMING = 4,       /* 1: time every partition / small-sort launch with HIP events */
     BQS_PARAM_TILE_EPT = 5,     /* keys per thread in a partition tile (8, 16 or 32; 0 = auto)  */
     BQS_PARAM_GRID = 6,         /* workgroups of the persistent kernel (0 = all that can be
@@ -88,6 +97,12 @@ typedef enum {
                                    look-back.  1: every tile uses the look-back, runs land in
                                    tile order and the intermediate layout is the same on every
                                    run.  Sorted output is identical either way.                 */
+    BQS_PARAM_PIVOT_SKEW = 12,  /* skewed pivots (Section 4, skewed pivot experiments): s >= 2
+                                   takes the sample key of rank floor(k/s) instead of the median
+                                   (s = 2 is the median; single-sample strategies only, at most
+                                   64; past the depth limit the median again).  0 (default):
+                                   the median.  Sorted output is identical; only the number of
+                                   levels changes                                               */
     BQS_PARAM_MULTIWAY = 11     /* 1: keys-only sorts split each segment around up to 15
                                    splitters per pass instead of one pivot (a sample-sort step:
                                    the paper's multi-pivot outlook, Section 5; 31 buckets, keys

@@ -46,6 +46,7 @@ PARAM_MODE = 8
 PARAM_GRAPH = 9
 PARAM_LOOKBACK = 10
 PARAM_MULTIWAY = 11
+PARAM_PIVOT_SKEW = 12
 RECORD_VECTOR, RECORD_RECORD = 1, 2
 MODE_LEVELS, MODE_QUEUE, MODE_PERSISTENT = 0, 1, 2
 
@@ -200,6 +201,7 @@ class Context:
         "graph": PARAM_GRAPH,
         "lookback": PARAM_LOOKBACK,
         "multiway": PARAM_MULTIWAY,
+        "pivot_skew": PARAM_PIVOT_SKEW,
     }
 
     def set_param(self, name: str, value: int):

@@ -339,6 +339,7 @@ struct bqs_ctx {
     int64_t small_cut = 0;
     int64_t sample_max = 0;
     int64_t pivot_mode = 0;
+    int64_t pivot_skew = 0;
     int64_t timing = 0;
     int64_t ept = 0;
     int64_t grid = 0;
@@ -591,7 +592,7 @@ std::vector<uint64_t> graph_key(const Ops* o, const Args& a, bool segmented) {
     auto u = [](const void* p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); };
     return {u(o), u(a.ctl), u(a.x_keys), u(a.x_vals), u(a.y_keys), u(a.offsets), static_cast<uint64_t>(a.n),
             static_cast<uint64_t>(a.k), static_cast<uint64_t>(a.small_cut), static_cast<uint64_t>(a.sample_max),
-            static_cast<uint64_t>(a.pivot_mode), static_cast<uint64_t>(a.depth_limit),
+            static_cast<uint64_t>(a.pivot_mode), static_cast<uint64_t>(a.pivot_skew), static_cast<uint64_t>(a.depth_limit),
             static_cast<uint64_t>(a.prof), static_cast<uint64_t>(a.claim), static_cast<uint64_t>(a.ways),
             segmented ? 1ull : 0ull};
 }
@@ -850,6 +851,7 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.sample_max = static_cast<int>(ctx->sample_max > 0 ? std::min<int64_t>(ctx->sample_max, kMaxSample)
                                                         : (multiway ? kMaxSample : 127));
     a.pivot_mode = static_cast<int>(ctx->pivot_mode);
+    a.pivot_skew = static_cast<int>(ctx->pivot_skew);
     a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
     a.tile_keys = o->tile_keys;
     a.prof = static_cast<int>(ctx->profile);
@@ -931,8 +933,14 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
         case BQS_PARAM_SMALL_CUTOFF: ctx->small_cut = value; break;
         case BQS_PARAM_SAMPLE_MAX: ctx->sample_max = value; break;
         case BQS_PARAM_PIVOT_MODE:
-            if (value != 0 && value != 3) return BQS_EINVAL;
+            if (value != 0 && value != 1 && value != 3 && value != 5 && value != 23 && value != 33 &&
+                value != 35 && value != 55)
+                return BQS_EINVAL;
             ctx->pivot_mode = value;
+            break;
+        case BQS_PARAM_PIVOT_SKEW:
+            if (value == 1 || value > 64) return BQS_EINVAL;
+            ctx->pivot_skew = value;
             break;
         case BQS_PARAM_TIMING: ctx->timing = value ? 1 : 0; break;
         case BQS_PARAM_TILE_EPT:
@@ -967,6 +975,7 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_SMALL_CUTOFF: return ctx->small_cut;
         case BQS_PARAM_SAMPLE_MAX: return ctx->sample_max;
         case BQS_PARAM_PIVOT_MODE: return ctx->pivot_mode;
+        case BQS_PARAM_PIVOT_SKEW: return ctx->pivot_skew;
         case BQS_PARAM_TIMING: return ctx->timing;
         case BQS_PARAM_TILE_EPT: return ctx->ept;
         case BQS_PARAM_GRID: return ctx->grid;

@@ -165,6 +165,7 @@ struct Args {
     int small_cut;
     int sample_max;
     int pivot_mode;
+    int pivot_skew;  // >= 2: pivot = the sample's 1/skew quantile (skewed-pivot study)
     int depth_limit;
     int tile_keys;
     int prof;

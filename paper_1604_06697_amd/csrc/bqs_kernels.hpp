@@ -303,8 +303,54 @@ __device__ inline void reset_next_slot(Ctl* c, int q, uint32_t nseg, uint32_t bi
 template <int DT, int NT>
 struct PlanLds {
     typename KeyT<DT>::raw samp[NT / 64][kMaxSample + 1];
+    typename KeyT<DT>::raw grp[NT / 64][8];  // group medians (medians of medians)
     typename KeyT<DT>::raw pick[NT / 64];
 };
+
+// Sample of one segment of m keys at recursion depth `depth` (the paper's
+// pivot strategies, Section 4): k samples; g > 0 means the pivot is the
+// median of the k/g medians of g consecutive samples; otherwise it is the
+// sample of rank `rk` (the median, or the 1/skew quantile of a skewed-pivot
+// run).  Past the depth limit every strategy takes the median of the
+// largest sample (the guard that keeps the recursion depth logarithmic).
+struct PivotPlan {
+    int k, g, rk;
+};
+__device__ inline PivotPlan pivot_plan(const Args& a, int64_t m, uint32_t depth) {
+    PivotPlan pp{0, 0, 0};
+    const int mode = a.pivot_mode;
+    const bool deep = depth >= static_cast<uint32_t>(a.depth_limit);
+    int64_t kk;
+    if (!deep && mode == 3) {
+        kk = 3;
+    } else if (!deep && (mode == 5 || mode == 23)) {
+        kk = mode;
+    } else if (!deep && (mode == 33 || mode == 35 || mode == 55 || (mode == 1 && m < 20000))) {
+        // medians of three (five) medians of three (five); the median of
+        // sqrt(m) takes the median of five medians of five below 20000 keys
+        const int outer = mode == 55 || mode == 1 ? 5 : 3;
+        pp.g = mode == 33 ? 3 : 5;
+        kk = outer * pp.g;
+    } else if (!deep && mode == 1) {
+        kk = static_cast<int64_t>(sqrt(static_cast<double>(m)));
+        if (kk > a.sample_max) kk = a.sample_max;
+    } else {
+        // default: about sqrt(m)/4 samples within [7, sample_max]
+        kk = deep ? a.sample_max : static_cast<int64_t>(sqrt(static_cast<double>(m))) / 4;
+        if (kk > a.sample_max) kk = a.sample_max;
+        if (kk < 7) kk = 7;
+    }
+    if (kk > m) {
+        kk = m;
+        pp.g = 0;
+    }
+    int k = static_cast<int>(kk) | 1;
+    if (k > m) k -= 2;
+    if (pp.g) k = static_cast<int>(kk);  // a whole number of groups (odd: 9, 15, 25)
+    pp.k = k;
+    pp.rk = (!deep && pp.g == 0 && a.pivot_skew >= 2) ? k / a.pivot_skew : k / 2;
+    return pp;
+}
 
 // The plan step as workgroup `bid` of `nblk` (all NT threads).
 template <int DT, class V, int NT>
@@ -330,31 +376,20 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
         SegDesc* sd = &a.segs[p][valid ? si : 0];
         int64_t lo = 0, hi = 0, m = 0;
         uint32_t depth = 0;
-        int k = 0;
+        PivotPlan pp{0, 0, 0};
         if (valid) {
             lo = sd->lo;
             hi = sd->hi;
             m = hi - lo;
             depth = sd->depth;
-            if (a.pivot_mode == 3 && depth < static_cast<uint32_t>(a.depth_limit)) {
-                k = 3;
-            } else {
-                // about sqrt(m)/4 samples, odd, within [7, sample_max]; past the
-                // depth limit the largest sample is used
-                int64_t kk = static_cast<int64_t>(sqrt(static_cast<double>(m))) / 4;
-                if (depth >= static_cast<uint32_t>(a.depth_limit)) kk = a.sample_max;
-                if (kk > a.sample_max) kk = a.sample_max;
-                if (kk < 7) kk = 7;
-                if (kk > m) kk = m;
-                k = static_cast<int>(kk) | 1;
-                if (k > m) k -= 2;
-            }
+            pp = pivot_plan(a, m, depth);
         }
+        const int k = pp.k;
         // sample i sits in stratum i at a hashed offset (first, middle and
         // last key for the median of three)
         for (int i = lane; i < k; i += 64) {
             int64_t pos;
-            if (k == 3) {
+            if (k == 3 && pp.g == 0) {
                 pos = i == 0 ? lo : (i == 1 ? lo + m / 2 : hi - 1);
             } else {
                 const int64_t stride = m / k;
@@ -366,17 +401,36 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
             ws[i] = src[pos];
         }
         __syncthreads();
-        // the median: the sample of rank k/2 (ties broken by sample index)
-        for (int i = lane; i < k; i += 64) {
-            const R mine = ws[i];
+        // medians of medians: lane t takes the median of group t
+        if (pp.g > 0 && lane < k / pp.g) {
+            const R* grp = ws + lane * pp.g;
+            R med = grp[0];
+            for (int i = 0; i < pp.g; ++i) {
+                const auto om = K::ord(grp[i]);
+                int rank = 0;
+                for (int j = 0; j < pp.g; ++j) {
+                    const auto oj = K::ord(grp[j]);
+                    rank += (oj < om) | ((oj == om) & (j < i));
+                }
+                if (rank == pp.g / 2) med = grp[i];
+            }
+            lds.grp[wv][lane] = med;
+        }
+        __syncthreads();
+        // the pick: the candidate of the target rank (ties broken by index)
+        const R* cand = pp.g > 0 ? lds.grp[wv] : ws;
+        const int kc = pp.g > 0 ? k / pp.g : k;
+        const int target = pp.g > 0 ? kc / 2 : pp.rk;
+        for (int i = lane; i < kc; i += 64) {
+            const R mine = cand[i];
             const auto om = K::ord(mine);
             int rank = 0;
 #pragma unroll 8
-            for (int j = 0; j < k; ++j) {
-                const auto oj = K::ord(ws[j]);
+            for (int j = 0; j < kc; ++j) {
+                const auto oj = K::ord(cand[j]);
                 rank += (oj < om) | ((oj == om) & (j < i));
             }
-            if (rank == k / 2) s_pick[wv] = mine;
+            if (rank == target) s_pick[wv] = mine;
         }
         __syncthreads();
         if (valid && lane == 0) {

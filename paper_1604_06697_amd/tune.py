@@ -1,12 +1,13 @@
 """Autotuner for the launch plan of the block-partition sort.
 
 A plan is (keys per thread in a partition tile, small-segment cutoff,
-partition step).  The tile size sets how many keys one workgroup scans and
-how many output-range claims a pass makes; the cutoff sets where the
-recursion stops and the in-LDS sort takes over (the paper's Insertionsort
-threshold, Section 2); the step is the paper's two-way block partition or
-the multiway (sample-sort) step for keys-only int32 sorts.  None of them
-changes the result: keys come out bit for bit the same under every plan.
+partition step, pivot strategy).  The tile size sets how many keys one
+workgroup scans and how many output-range claims a pass makes; the cutoff
+sets where the recursion stops and the in-LDS sort takes over (the paper's
+Insertionsort threshold, Section 2); the step is the paper's two-way block
+partition or the multiway (sample-sort) step for keys-only int32 sorts; the
+pivot strategy is one of the paper's (Section 4).  None of them changes the
+result: keys come out bit for bit the same under every plan.
 
 `autotune` times every candidate plan on the caller's own input (sorted from
 a pristine copy each time, in the same mode the caller will use) and keeps
@@ -28,6 +29,7 @@ from . import BqsError, Context, _key_code
 
 EPT_CHOICES = (8, 16, 32)
 CUTOFF_CHOICES = (1024, 2048, 4096, 8192)
+PIVOT_CHOICES = (0, 55)
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")
 
 
@@ -43,11 +45,17 @@ def candidates(key_code: int, val_bytes: int) -> list[dict]:
     """Plans the library compiles for this key type: the tile shape is
     selectable for int32 keys only; the cutoff is clamped by the library to
     the largest in-LDS size it compiles for the type; keys-only int32 sorts
-    also try the multiway partition step."""
+    also try the multiway partition step; two-way plans try the default
+    sampled median and the median of five medians of five (Section 4's
+    fastest strategy for int keys) as pivot."""
     i32 = key_code == 1 and val_bytes == 0
     epts = EPT_CHOICES if i32 else (0,)
-    ways = (0, 1) if i32 else (0,)
-    return [{"tile_ept": e, "small_cutoff": c, "multiway": w} for w in ways for e in epts for c in CUTOFF_CHOICES]
+    out = [{"tile_ept": e, "small_cutoff": c, "multiway": 0, "pivot_mode": pm}
+           for pm in PIVOT_CHOICES for e in epts for c in CUTOFF_CHOICES]
+    if i32:
+        out += [{"tile_ept": e, "small_cutoff": c, "multiway": 1, "pivot_mode": 0}
+                for e in epts for c in CUTOFF_CHOICES]
+    return out
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> dict:

@@ -53,7 +53,17 @@ def test_ctx_params_roundtrip(bqs):
     assert ctx.get_param("pivot_mode") == 3
     assert ctx.get_param("tile_ept") == 32
     with pytest.raises(bqs.BqsError):
-        ctx.set_param("pivot_mode", 5)
+        ctx.set_param("pivot_mode", 7)
+    for mode in (0, 1, 3, 5, 23, 33, 35, 55):
+        ctx.set_param("pivot_mode", mode)
+        assert ctx.get_param("pivot_mode") == mode
+    ctx.set_param("pivot_mode", 3)
+    ctx.set_param("pivot_skew", 8)
+    assert ctx.get_param("pivot_skew") == 8
+    for bad in (1, 65):
+        with pytest.raises(bqs.BqsError):
+            ctx.set_param("pivot_skew", bad)
+    ctx.set_param("pivot_skew", 0)
     with pytest.raises(bqs.BqsError):
         ctx.set_param("tile_ept", 12)
     assert bqs.lib.bqs_ctx_set_param(ctx._h, 77, 1) == 1

@@ -571,6 +571,41 @@ def test_full_size_2p28_uniform_properties(torch_mod, bqs):
         assert int(t[int(i)]) == int(np.partition(host, int(i))[int(i)])
 
 
+# ------------------------------------------------------ pivot strategies --
+
+@pytest.mark.parametrize("mode", [1, 3, 5, 23, 33, 35, 55])
+def test_pivot_strategies_match_oracle(torch_mod, bqs, oracle, mode):
+    """The paper's pivot strategies (Section 4) change only the recursion,
+    never the sorted keys."""
+    ctx = bqs.Context(pivot_mode=mode, small_cutoff=512)
+    for fam in ("uniform", "few_distinct", "sorted", "reverse"):
+        for n in (1000, 8192 * 5 + 3, 400_001):
+            a = W.I32_FAMILIES[fam](n, mode)
+            note(f"pivot mode {mode} {fam} n={n}")
+            assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+    f = W.special_f64(100_000, mode)
+    note(f"pivot mode {mode} f64 specials")
+    assert_same_bits(gpu_sort(torch_mod, bqs, f, ctx), oracle.sort(f))
+
+
+def test_skewed_pivots_deepen_the_recursion(torch_mod, bqs, oracle):
+    """Skew factor s takes the 1/s quantile of the sample as pivot: the keys
+    still match the oracle, and the recursion gets deeper as s grows."""
+    a = W.uniform_i32(1 << 20, 77)
+    expect = oracle.sort(a)
+    levels = []
+    for skew in (0, 4, 16, 64):
+        ctx = bqs.Context(pivot_skew=skew, small_cutoff=1024)
+        note(f"pivot skew {skew}")
+        assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), expect)
+        levels.append(ctx.stats()["levels"])
+    assert levels[0] < levels[1] < levels[2] < levels[3]
+    k, v = W.tied_u64_pairs(200_000, 9)
+    note("pivot skew 8 pairs")
+    ko, vo = gpu_pairs(torch_mod, bqs, k, v, bqs.Context(pivot_skew=8))
+    check_pairs(k, ko, vo, oracle.sort(k))
+
+
 # ------------------------------------------------------- persistent mode --
 # Every level in one cooperative launch (grid barriers between the steps).
 # The results must be the oracle's, as in the level-by-level mode.

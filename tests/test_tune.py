@@ -25,7 +25,10 @@ def test_candidates_follow_compiled_shapes(tune):
     assert {c["tile_ept"] for c in i32} == {8, 16, 32}
     assert {c["small_cutoff"] for c in i32} == set(tune.CUTOFF_CHOICES)
     assert {c["multiway"] for c in i32} == {0, 1}
-    assert len(i32) == 24
+    # two-way plans with each pivot strategy, multiway plans with the default
+    assert {c["pivot_mode"] for c in i32 if not c["multiway"]} == set(tune.PIVOT_CHOICES)
+    assert {c["pivot_mode"] for c in i32 if c["multiway"]} == {0}
+    assert len(i32) == 12 * len(tune.PIVOT_CHOICES) + 12
     # other key types and pairs compile one tile shape (0 = library default)
     assert {c["tile_ept"] for c in tune.candidates(6, 0)} == {0}
     assert {c["tile_ept"] for c in tune.candidates(1, 4)} == {0}
@@ -70,7 +73,7 @@ def test_autotune_segments_matches_oracle(tune, oracle, tmp_path):
     path = str(tmp_path / "plans.json")
     res = tune.autotune(t, o, graph=True, reps=1, path=path)
     assert res["plan"] in tune.candidates(1, 0)
-    assert len(res["table"]) == 24
+    assert len(res["table"]) == len(tune.candidates(1, 0))
     ref = oracle.sort_segments(keys, offsets)
     assert np.array_equal(t.cpu().numpy(), ref)
     # the cached plan sorts a fresh copy identically
