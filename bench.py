@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched segmented workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the persistent-mode line (a cooperative launch, which some profilers "
+                         "do not shut down cleanly)")
     ap.add_argument("--serve-requests", type=int, default=100_000)
     ap.add_argument("--cpu-log2", type=int, default=26, help="CPU sample: arrays of 2^x keys")
     ap.add_argument("--cpu-arrays", type=int, default=6)
@@ -562,12 +565,13 @@ def main():
                        "partitioned_keys": mst["partitioned_keys"], "small_cutoff": 8192, "correct": mok}
 
     # persistent mode: every level in one cooperative launch, one host wait
-    pctx = bqs.Context(mode=bqs.MODE_PERSISTENT)
-    pms, pst, _, _, _, pok = run_workload(
-        torch, bqs, pctx, "i32_uniform", args.n, max(2, args.steps // 2), 1)
-    out["persistent"] = {"ms": round(pms, 3), "Gkeys/s": round(n / (pms * 1e-3) / 1e9, 3),
-                         "levels": pst["levels"], "partition_launches": pst["partition_launches"],
-                         "small_cutoff": pst["small_cutoff"], "correct": pok}
+    if not args.no_persistent:
+        pctx = bqs.Context(mode=bqs.MODE_PERSISTENT)
+        pms, pst, _, _, _, pok = run_workload(
+            torch, bqs, pctx, "i32_uniform", args.n, max(2, args.steps // 2), 1)
+        out["persistent"] = {"ms": round(pms, 3), "Gkeys/s": round(n / (pms * 1e-3) / 1e9, 3),
+                             "levels": pst["levels"], "partition_launches": pst["partition_launches"],
+                             "small_cutoff": pst["small_cutoff"], "correct": pok}
 
     if not args.no_dists:
         dists = {}

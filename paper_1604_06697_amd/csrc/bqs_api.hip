@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -420,7 +421,10 @@ bqs_status ensure_device_state(bqs_ctx* ctx) {
 
 // Copies the device control block to pinned host memory and waits.
 bqs_status read_ctl(bqs_ctx* ctx, const Ctl* dev) {
-    if (hipMemcpyAsync(ctx->pinned, dev, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+    // the host reads the counters and the status; the barrier lines of the
+    // persistent mode (the last ~5 KB) stay on the device
+    if (hipMemcpyAsync(ctx->pinned, dev, offsetof(Ctl, bar_arrive), hipMemcpyDeviceToHost, ctx->stream) !=
+        hipSuccess)
         return BQS_EHIP;
     return hip_ok(hipStreamSynchronize(ctx->stream));
 }

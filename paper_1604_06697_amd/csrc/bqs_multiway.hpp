@@ -383,7 +383,7 @@ __global__ __launch_bounds__(NT) void k_mscatter(Args a) {
     const int cnt = el - sl;
     for (int x = tid; x < cnt; x += NT) {
         const int b = s_b[x];
-        dst[s_off[b] + (x - static_cast<int>(s_start[b]))] = s_k[x];
+        __builtin_nontemporal_store(s_k[x], dst + s_off[b] + (x - static_cast<int>(s_start[b])));  // streaming
     }
 }
 
