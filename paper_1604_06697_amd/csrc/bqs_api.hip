@@ -385,6 +385,11 @@ const Ops* select_ops(const bqs_ctx* ctx, int dtype, int val_bytes) {
     return nullptr;
 }
 
+// Keys per partition tile of a call: the multiway levels have their own.
+int64_t eff_tile_keys(const bqs_ctx* ctx, const Ops* o) {
+    return ctx && ctx->multiway && o->mscan ? o->multi_tile_keys : o->tile_keys;
+}
+
 int64_t eff_small_cut(const bqs_ctx* ctx, const Ops* o) {
     int64_t s = ctx && ctx->small_cut > 0 ? ctx->small_cut : o->small_default;
     if (s > o->small_max) s = o->small_max;
@@ -564,7 +569,7 @@ bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     Timer tm{ctx, ctx->timing != 0};
     tm.resolve(ctx->stats);  // drop events a failed call may have left
     bqs_stats stats{};
-    stats.tile_keys = o->tile_keys;
+    stats.tile_keys = a.tile_keys;
     stats.small_cutoff = a.small_cut;
 
     if (segmented) launch_init_segments(a, s);
@@ -681,7 +686,7 @@ bqs_status run_graph(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     Timer tm{ctx, ctx->timing != 0};
     tm.resolve(ctx->stats);
     bqs_stats stats{};
-    stats.tile_keys = o->tile_keys;
+    stats.tile_keys = a.tile_keys;
     stats.small_cutoff = a.small_cut;
     ctx->level_keys.clear();
     ctx->level_ms.clear();
@@ -727,7 +732,7 @@ bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     Timer tm{ctx, ctx->timing != 0};
     tm.resolve(ctx->stats);
     bqs_stats stats{};
-    stats.tile_keys = o->tile_keys;
+    stats.tile_keys = a.tile_keys;
     stats.small_cutoff = a.small_cut;
     ctx->level_keys.clear();
     ctx->level_ms.clear();
@@ -774,7 +779,7 @@ bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     Timer tm{ctx, ctx->timing != 0};
     tm.resolve(ctx->stats);
     bqs_stats stats{};
-    stats.tile_keys = o->tile_keys;
+    stats.tile_keys = a.tile_keys;
     stats.small_cutoff = a.small_cut;
     ctx->level_keys.clear();
     ctx->level_ms.clear();
@@ -813,7 +818,7 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     const size_t kb = key_bytes(dtype);
     const int64_t S = eff_small_cut(ctx, o);
     const bool queue = ctx->mode == BQS_MODE_QUEUE;
-    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, o->tile_keys, S, queue,
+    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S, queue,
                                  ctx->multiway && o->mscan);
     if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull ||
         L.cap_qseg > 0xffffffffull || L.cap_qitem > 0xffffffffull)
@@ -857,7 +862,7 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.pivot_mode = static_cast<int>(ctx->pivot_mode);
     a.pivot_skew = static_cast<int>(ctx->pivot_skew);
     a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
-    a.tile_keys = o->tile_keys;
+    a.tile_keys = static_cast<int>(eff_tile_keys(ctx, o));
     a.prof = static_cast<int>(ctx->profile);
     a.claim = ctx->lookback ? 0 : 1;
     a.ways = multiway ? 1 : 0;
@@ -1011,7 +1016,7 @@ size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, i
     const Ops* o = select_ops(ctx, key, val_bytes);
     if (!o) return 0;
     const Layout L = make_layout(n_total, key_bytes(key), static_cast<size_t>(val_bytes),
-                                 std::max<int64_t>(k_segments, 1), o->tile_keys, eff_small_cut(ctx, o),
+                                 std::max<int64_t>(k_segments, 1), eff_tile_keys(ctx, o), eff_small_cut(ctx, o),
                                  ctx && ctx->mode == BQS_MODE_QUEUE, ctx && ctx->multiway && o->mscan);
     return L.total;
 }

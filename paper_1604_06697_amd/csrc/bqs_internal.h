@@ -213,6 +213,7 @@ struct Ops {
     hipError_t (*persist)(const Args&, int grid, hipStream_t);
     int (*persist_blocks_per_cu)();
     int persist_small_max;
+    int multi_tile_keys;  // keys per tile of the multiway levels (0 without them)
 };
 
 // The map step of level `level`, as thread `gtid` of `gstride`: every tile
