@@ -81,7 +81,11 @@ typedef enum {
                                       medians of five, of five medians of five.
                                    Past the depth limit 2 log2 n + 3 every strategy takes the
                                    largest sample.  Other values: BQS_EINVAL                    */
-    BQS_PARAM_TIMING = 4,       /* 1: time every partition / small-sort launch with HIP events */
+    BQS_PARAM_TIMING = 4,       /* HIP-event timing on the context's stream: 1 every launch
+                                   (partition_ms: the partition kernels alone; plan_ms: pivots,
+                                   fills, tile map and segment completion; small_ms); 2 the
+                                   partition kernels only (two events per level, so the timing
+                                   itself costs the host less); 0 none                          */
     BQS_PARAM_TILE_EPT = 5,     /* keys per thread in a partition tile (8, 16 or 32; 0 = auto)  */
     BQS_PARAM_GRID = 6,         /* workgroups of the persistent kernel (0 = all that can be
                                    resident at once)                                            */
@@ -156,9 +160,10 @@ typedef struct {
     int64_t tiles;              /* partition tiles processed                                    */
     double partition_ms;        /* summed partition-kernel time (BQS_PARAM_TIMING only)         */
     int64_t partition_launches;
-    double small_ms;            /* summed small-sort kernel time (BQS_PARAM_TIMING only)        */
+    double small_ms;            /* summed small-sort kernel time (BQS_PARAM_TIMING = 1 only)    */
     int64_t small_launches;
-    double plan_ms;             /* summed pivot/fill kernel time (BQS_PARAM_TIMING only)        */
+    double plan_ms;             /* summed pivot, fill, map and completion kernel time          
+                                   (BQS_PARAM_TIMING = 1 only)                                  */
     int64_t tile_keys;          /* compiled tile size used (keys per tile)                      */
     int64_t small_cutoff;       /* small-sort cutoff used                                       */
     /* BQS_PARAM_PROFILE only (sums over all partition tiles; cycles of the shader clock): */

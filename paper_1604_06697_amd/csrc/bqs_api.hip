@@ -447,8 +447,16 @@ hipEvent_t take_event(bqs_ctx* ctx) {
 
 struct Timer {
     bqs_ctx* ctx;
-    bool on;
+    bool on;           // partition passes are timed
+    bool all = false;  // every other launch too
     hipEvent_t a = nullptr;
+    // other launches (plan, small sorts, completion): timed with all only
+    void start_aux() {
+        if (all) start();
+    }
+    void stop_aux(int kind, int level) {
+        if (all) stop(kind, level);
+    }
     void start() {
         if (!on) return;
         a = take_event(ctx);
@@ -516,19 +524,19 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         const uint32_t nseg = static_cast<uint32_t>(cur.segs);
         const uint32_t ntile = static_cast<uint32_t>(cur.segs >> 32);
         const uint32_t nchunk = static_cast<uint32_t>(cur.fills >> 32);
-        tm.start();
+        tm.start_aux();
         // plan: one wave per segment (4 per workgroup), one workgroup per fill chunk
         (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(std::max<uint64_t>((nseg + 3) / 4, nchunk), 16384), s);
         if (nseg) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
-        tm.stop(0, L);
+        tm.stop_aux(0, L);
         for (int cls = 0; cls < kSmallClasses; ++cls) {
             const uint32_t cnt = cur.smalls[cls];
             if (!cnt) continue;
             if (!o->small[cls]) return BQS_EOVERFLOW;  // cannot happen: classes follow small_cut
             const uint32_t per = static_cast<uint32_t>(o->small_per_block[cls]);
-            tm.start();
+            tm.start_aux();
             o->small[cls](a, clamp_grid((cnt + per - 1) / per, 16384), s);
-            tm.stop(1, L);
+            tm.stop_aux(1, L);
             stats.small_launches++;
         }
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
@@ -546,11 +554,14 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
             o->mcount(a, static_cast<int>(ntile), s);
             o->mscan(a, clamp_grid((nseg + 3) / 4, 4096), s);
             o->mscatter(a, static_cast<int>(ntile), s);
+            tm.stop(2, L);
         } else {
             o->tile(a, static_cast<int>(ntile), s);
+            tm.stop(2, L);  // the partition kernel alone
+            tm.start_aux();
             o->complete(a, clamp_grid((nseg + 255) / 256, 4096), s);
+            tm.stop_aux(0, L);
         }
-        tm.stop(2, L);
         stats.partition_launches++;
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
         if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
@@ -566,7 +577,7 @@ bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     bqs_status st = ensure_device_state(ctx);
     if (st != BQS_OK) return st;
     const hipStream_t s = ctx->stream;
-    Timer tm{ctx, ctx->timing != 0};
+    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1};
     tm.resolve(ctx->stats);  // drop events a failed call may have left
     bqs_stats stats{};
     stats.tile_keys = a.tile_keys;
@@ -616,11 +627,14 @@ void drop_graph(bqs_ctx* ctx) {
 }
 
 // Most tiles level L can hold: n/T plus two partial tiles per segment; a
-// level has at most min(k * 2^L, cap_seg) segments.
+// level has at most min(k * f^L, cap_seg) segments, f = 2 children per
+// segment for the two-way step and 16 for the multiway step.
 uint64_t tile_bound(const Args& a, int L) {
     const uint64_t T = static_cast<uint64_t>(a.tile_keys);
+    // children per segment: two, or up to sixteen for a multiway level
+    const uint64_t fan = a.ways ? 16 : 2;
     uint64_t segs = static_cast<uint64_t>(a.k);
-    for (int i = 0; i < L && segs < a.cap_seg; ++i) segs *= 2;
+    for (int i = 0; i < L && segs < a.cap_seg; ++i) segs *= fan;
     segs = std::min<uint64_t>(segs, a.cap_seg);
     return std::min<uint64_t>(static_cast<uint64_t>(a.n) / T + 2 * segs + 2, a.cap_tile);
 }
@@ -683,7 +697,7 @@ bqs_status run_graph(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     }
     bqs_status st = ensure_device_state(ctx);
     if (st != BQS_OK) return st;
-    Timer tm{ctx, ctx->timing != 0};
+    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1};
     tm.resolve(ctx->stats);
     bqs_stats stats{};
     stats.tile_keys = a.tile_keys;
@@ -729,7 +743,7 @@ bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     bqs_status st = ensure_device_state(ctx);
     if (st != BQS_OK) return st;
     const hipStream_t s = ctx->stream;
-    Timer tm{ctx, ctx->timing != 0};
+    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1};
     tm.resolve(ctx->stats);
     bqs_stats stats{};
     stats.tile_keys = a.tile_keys;
@@ -776,7 +790,7 @@ bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     bqs_status st = ensure_device_state(ctx);
     if (st != BQS_OK) return st;
     const hipStream_t s = ctx->stream;
-    Timer tm{ctx, ctx->timing != 0};
+    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1};
     tm.resolve(ctx->stats);
     bqs_stats stats{};
     stats.tile_keys = a.tile_keys;
@@ -951,7 +965,10 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             if (value == 1 || value > 64) return BQS_EINVAL;
             ctx->pivot_skew = value;
             break;
-        case BQS_PARAM_TIMING: ctx->timing = value ? 1 : 0; break;
+        case BQS_PARAM_TIMING:
+            if (value > 2) return BQS_EINVAL;
+            ctx->timing = value;
+            break;
         case BQS_PARAM_TILE_EPT:
             if (value != 0 && value != 8 && value != 16 && value != 32) return BQS_EINVAL;
             ctx->ept = value;

@@ -64,6 +64,11 @@ def test_ctx_params_roundtrip(bqs):
         with pytest.raises(bqs.BqsError):
             ctx.set_param("pivot_skew", bad)
     ctx.set_param("pivot_skew", 0)
+    for t in (0, 1, 2):
+        ctx.set_param("timing", t)
+        assert ctx.get_param("timing") == t
+    with pytest.raises(bqs.BqsError):
+        ctx.set_param("timing", 3)
     with pytest.raises(bqs.BqsError):
         ctx.set_param("tile_ept", 12)
     assert bqs.lib.bqs_ctx_set_param(ctx._h, 77, 1) == 1

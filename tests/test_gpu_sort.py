@@ -371,6 +371,25 @@ def test_multiway_segments_and_graph(torch_mod, bqs, oracle):
         assert gctx.stats()["graph_launches"] == (0 if i == 0 else 1)
 
 
+def test_multiway_graph_single_array(torch_mod, bqs, oracle):
+    """Graph replays of multiway levels on one array: a level can hold up to
+    sixteen children per segment, so the captured tile grids must cover
+    them (regression: grids sized for two children left tiles unsorted)."""
+    torch = torch_mod
+    n = 3_000_017
+    ctx = bqs.Context(multiway=1, graph=1)
+    buf = torch.empty(n, dtype=torch.int32, device="cuda")
+    for i, (fam, seed) in enumerate([("uniform", 1), ("uniform", 2), ("few_distinct", 3), ("uniform", 4)]):
+        a = W.I32_FAMILIES[fam](n, seed)
+        note(f"multiway graph single array {i} {fam}")
+        buf.copy_(torch.from_numpy(a))
+        ctx.sort(buf)
+        torch.cuda.synchronize()
+        assert_same_bits(buf.cpu().numpy(), oracle.sort(a))
+        if i:
+            assert ctx.stats()["graph_launches"] == 1
+
+
 def test_multiway_pairs_use_two_way(torch_mod, bqs, oracle):
     """Pairs keep the two-way step; the parameter only changes keys-only sorts."""
     k, v = W.tied_u64_pairs(300_000, 3)
