@@ -526,8 +526,10 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         const uint32_t nchunk = static_cast<uint32_t>(cur.fills >> 32);
         tm.start_aux();
         // plan: one wave per segment (4 per workgroup), one workgroup per fill chunk
+        // (the two-way plan also writes the tile descriptors; the multiway
+        // levels map tiles to segments in a launch of their own)
         (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(std::max<uint64_t>((nseg + 3) / 4, nchunk), 16384), s);
-        if (nseg) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
+        if (nseg && a.ways) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
         tm.stop_aux(0, L);
         for (int cls = 0; cls < kSmallClasses; ++cls) {
             const uint32_t cnt = cur.smalls[cls];
@@ -650,7 +652,7 @@ bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, Args a, bool segmented, int
     for (int L = 0; L < levels; ++L) {
         a.level = L;
         (a.ways ? o->plan_multi : o->plan)(a, 2048, cs);
-        o->map(a, 4096, cs);
+        if (a.ways) o->map(a, 4096, cs);
         for (int cls = 0; cls < kSmallClasses; ++cls)
             if (o->small[cls]) o->small[cls](a, 2048, cs);
         const uint64_t tb = tile_bound(a, L);

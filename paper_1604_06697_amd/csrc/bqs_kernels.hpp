@@ -375,13 +375,15 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
         const bool valid = si < nseg;
         SegDesc* sd = &a.segs[p][valid ? si : 0];
         int64_t lo = 0, hi = 0, m = 0;
-        uint32_t depth = 0;
+        uint32_t depth = 0, t0 = 0, nt = 0;
         PivotPlan pp{0, 0, 0};
         if (valid) {
             lo = sd->lo;
             hi = sd->hi;
             m = hi - lo;
             depth = sd->depth;
+            t0 = sd->t0;
+            nt = sd->nt;
             pp = pivot_plan(a, m, depth);
         }
         const int k = pp.k;
@@ -433,11 +435,26 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
             if (rank == target) s_pick[wv] = mine;
         }
         __syncthreads();
-        if (valid && lane == 0) {
+        if (valid) {
             const R piv = s_pick[wv];
-            sd->pivot = static_cast<uint64_t>(K::ord(piv));
-            sd->pivot_raw = static_cast<uint64_t>(piv);
-            sd->cursor = 0;
+            if (lane == 0) {
+                sd->pivot = static_cast<uint64_t>(K::ord(piv));
+                sd->pivot_raw = static_cast<uint64_t>(piv);
+                sd->cursor = 0;
+            }
+            // the segment's tile descriptors (and cleared look-back words):
+            // the wave that knows the pivot writes them, so no separate map
+            // step has to find each tile's segment
+            TileDesc d;
+            d.lo = lo;
+            d.hi = hi;
+            d.pivot = static_cast<uint64_t>(K::ord(piv));
+            d.t0 = t0;
+            d.si = si;
+            for (uint32_t j = lane; j < nt; j += 64) {
+                a.tile_desc[t0 + j] = d;
+                a.status[t0 + j] = 0;
+            }
         }
         __syncthreads();
     }
@@ -1624,9 +1641,9 @@ __global__ __launch_bounds__(NTH > 256 ? NTH : 256, 6) void k_small(Args a, int 
 // ---------------------------------------------------------------------------
 // Persistent mode: the recursion of every level in one cooperative launch.
 // The resident workgroups drain the level's device lists step by step --
-// (1) pivots, equal runs and small sorts recorded by the previous level,
-// (2) tile descriptors, (3) partition tiles claimed in order with the
-// level's ticket counter, (4) segment completion, which appends the next
+// (1) pivots and tile descriptors, plus the equal runs and small sorts
+// recorded by the previous level, (2) partition tiles claimed in order with
+// the level's ticket counter, (3) segment completion, which appends the next
 // level's lists -- with a grid-wide barrier after each step.  The loop ends
 // on the device, at the first level with no segment left to partition, so
 // the host waits once per sort.  The steps run the same code as the
@@ -1767,7 +1784,8 @@ __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
         const unsigned long long sc = c->lc[p].segs;
         const uint32_t nseg = static_cast<uint32_t>(sc);
         const uint32_t ntile = static_cast<uint32_t>(sc >> 32);
-        // (1) pivots of level L; equal runs and small segments of level L-1
+        // (1) pivots and tile descriptors of level L; equal runs and small
+        // segments of level L-1
         plan_body<DT, V, NT>(a, L, bid, nblk, *reinterpret_cast<PlanLds<DT, NT>*>(s_raw));
         __syncthreads();
         persist_small<DT, V, NT, 1, 64, SP>(a, L, bid, nblk, s_raw);
@@ -1783,10 +1801,7 @@ __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
             if (bid == 0 && tid == 0) atomicOr(&c->error, ERR_OVERFLOW);
             break;
         }
-        // (2) tile descriptors
-        map_tiles(a, L, bid * NT + tid, nblk * NT);
-        if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
-        // (3) partition tiles, claimed in order
+        // (2) partition tiles, claimed in order
         auto& tl = *reinterpret_cast<TileLds<DT, V, NT, EPT>*>(s_raw);
         for (;;) {
             if (tid == 0) {
@@ -1802,7 +1817,7 @@ __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
             __syncthreads();  // the tile's LDS, s_tile and s_desc are free again
         }
         if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
-        // (4) completion: the lists of level L+1
+        // (3) completion: the lists of level L+1
         complete_body<V>(a, L, bid, nblk);
         if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
     }
