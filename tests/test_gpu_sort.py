@@ -563,6 +563,19 @@ def test_stats_account_for_every_key(torch_mod, bqs):
         assert s["partition_ms"] > 0
 
 
+def test_partition_only_timing(torch_mod, bqs, oracle):
+    """Timing mode 2 records events around the partition kernels only: the
+    partition time is there, the other launches are not timed, and the keys
+    are the oracle's."""
+    a = W.uniform_i32(1 << 20, 3)
+    ctx = bqs.Context(timing=2)
+    note("timing mode 2")
+    assert_same_bits(gpu_sort(torch_mod, bqs, a, ctx), oracle.sort(a))
+    s = ctx.stats()
+    assert s["partition_ms"] > 0 and s["small_ms"] == 0 and s["plan_ms"] == 0
+    assert len(ctx.levels()) == s["levels"] and all(ms > 0 for _, ms in ctx.levels())
+
+
 def test_full_size_2p28_uniform_properties(torch_mod, bqs):
     """2^28 int32 keys at the benchmark's configuration: sorted, and the
     same multiset as the input (compared through torch.sort of the input as
