@@ -1461,18 +1461,27 @@ __device__ __forceinline__ void pick(SItem<O, true>& d, const SItem<O, true>& x,
 }
 
 template <class It, class O, int E, int NTH>
-__device__ void merge_sort(It (&v)[E], int t, O* sk, uint32_t* si) {
-    reg_sort<It, O, E>(v);
+__device__ void merge_sort(It (&v)[E], int t, O* sk, uint32_t* si, int m) {
+    // A thread owns outputs [t*E, t*E + E) at every level.  Positions at or
+    // past m (the segment's size) hold padding at every level (padding sorts
+    // after every real item), so a thread whose outputs all lie there has
+    // nothing to do: its items and its LDS slots stay padding.  Whole waves
+    // of a short segment in a large class then skip the merges.
+    const bool idle = t * E >= m;
+    if (!idle) reg_sort<It, O, E>(v);
 #pragma unroll 1
     for (int L = E; L < E * NTH; L <<= 1) {
         __syncthreads();  // the previous level's reads are done
+        if (!idle) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int x = t * E + r;
-            sk[lds_slot<O>(x)] = v[r].k;
-            if constexpr (sizeof(It) > sizeof(O)) si[lds_slot<O>(x)] = v[r].i;
+            for (int r = 0; r < E; ++r) {
+                const int x = t * E + r;
+                sk[lds_slot<O>(x)] = v[r].k;
+                if constexpr (sizeof(It) > sizeof(O)) si[lds_slot<O>(x)] = v[r].i;
+            }
         }
         __syncthreads();
+        if (idle) continue;
         // runs A = [base, base+L) and B = [base+L, base+2L); this thread's
         // outputs are positions [d, d+E) of the merged run
         const int per = (2 * L) / E;  // threads per merged run
@@ -1598,7 +1607,7 @@ __device__ void small_body(const Args& a, int level, int cls, uint32_t bid, uint
             v[r].k = sk[lds_slot<O>(x)];
             if constexpr (HV) v[r].i = si[lds_slot<O>(x)];
         }
-        merge_sort<It, O, E, NTH>(v, t, sk, si);
+        merge_sort<It, O, E, NTH>(v, t, sk, si, m);
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < E; ++r) {
