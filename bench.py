@@ -302,9 +302,17 @@ def serving(torch, requests, seed=11, budget=64 << 30, workers=3):
     def fresh(tr):
         return [serve.Request(r.rid, r.kind, r.n, r.arrival) for r in tr]
 
-    burst = serve.make_trace(max(200, requests // 50), qps=0.0, seed=seed + 1)
-    _, mk, _ = serve.run_service(burst, budget, workers=workers, seed_base=1 << 40)
-    cap = serve.latency_summary(burst, mk)
+    # a warm-up burst (kernel code objects, allocator pools), then the median
+    # of three calibration bursts
+    warm = serve.make_trace(max(50, requests // 200), qps=0.0, seed=seed + 2)
+    serve.run_service(warm, budget, workers=workers, seed_base=1 << 41)
+    caps = []
+    for rep in range(3):
+        burst = serve.make_trace(max(200, requests // 50), qps=0.0, seed=seed + 1)
+        _, mk, _ = serve.run_service(burst, budget, workers=workers, seed_base=(1 << 40) + rep)
+        caps.append((mk, serve.latency_summary(burst, mk)))
+    caps.sort(key=lambda c: c[0])
+    mk, cap = caps[1]
     qps = 0.7 * len(burst) / mk
     trace = serve.make_trace(requests, qps=qps, seed=seed)
     sample = [r.rid for r in trace if r.rid % 100 == 0]
@@ -315,7 +323,8 @@ def serving(torch, requests, seed=11, budget=64 << 30, workers=3):
                     "sizes log-uniform [2^10, 2^24], 50% int32 / 30% float64 / 20% uint64+uint32 pairs, "
                     f"{budget >> 30} GiB HBM budget, {workers} batch workers",
         "qps": round(qps, 1),
-        "saturated": {"requests": cap["requests"], "Gkeys/s": cap["Gkeys/s"]},
+        "saturated": {"requests": cap["requests"], "Gkeys/s": cap["Gkeys/s"],
+                      "bursts_Gkeys/s": sorted(c[1]["Gkeys/s"] for c in caps)},
         "service": dict(serve.latency_summary(trace, mk), batches=svc.batches,
                         peak_budget_GiB=round(svc.budget.peak / 2**30, 2)),
         "correct_sample": ok,
