@@ -136,7 +136,11 @@ typedef enum {
  *               statistics are not kept.  A barrier that waits more than
  *               about a second (the GPU cannot hold the whole grid at once)
  *               ends the launch and the call returns BQS_EHIP.  Results are
- *               identical to LEVELS. */
+ *               identical to LEVELS.  Measured side effect: once a process
+ *               has made a cooperative launch, its later kernels on several
+ *               streams overlap less (the serving loop's capacity dropped
+ *               from 18 to 11 Gkeys/s), so a process that batches work on
+ *               many streams should not mix in this mode. */
 typedef enum { BQS_MODE_LEVELS = 0, BQS_MODE_QUEUE = 1, BQS_MODE_PERSISTENT = 2 } bqs_mode;
 
 /* Graph mode (BQS_PARAM_GRAPH = 1).  The first call with a given set of
