@@ -119,10 +119,6 @@ typedef enum {
 /* Execution modes (BQS_PARAM_MODE).
  *   LEVELS    : one partition launch per recursion level; the host reads the
  *               next level's size between levels (per-level statistics).
- *   QUEUE     : the recursion as a device-resident work queue drained by one
- *               persistent kernel.  Closed: selecting it returns BQS_EINVAL
- *               (its kernel faulted on the device and the cause is not yet
- *               known).
  *   PERSISTENT: every level in one cooperative launch (Quicksort's main
  *               loop, Algorithm 1, run on the device): the workgroups that
  *               fit on the GPU at once drain each level's device-resident
@@ -141,7 +137,7 @@ typedef enum {
  *               streams overlap less (the serving loop's capacity dropped
  *               from 18 to 11 Gkeys/s), so a process that batches work on
  *               many streams should not mix in this mode. */
-typedef enum { BQS_MODE_LEVELS = 0, BQS_MODE_QUEUE = 1, BQS_MODE_PERSISTENT = 2 } bqs_mode;
+typedef enum { BQS_MODE_LEVELS = 0, BQS_MODE_PERSISTENT = 2 } bqs_mode;
 
 /* Graph mode (BQS_PARAM_GRAPH = 1).  The first call with a given set of
  * buffers (keys, vals, offsets, workspace), sizes and parameters sorts with

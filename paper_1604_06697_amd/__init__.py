@@ -14,9 +14,12 @@ The library must be built (``python -m paper_1604_06697_amd.build`` or
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
 import threading
+import weakref
 
 import torch
 
@@ -48,7 +51,7 @@ PARAM_LOOKBACK = 10
 PARAM_MULTIWAY = 11
 PARAM_PIVOT_SKEW = 12
 RECORD_VECTOR, RECORD_RECORD = 1, 2
-MODE_LEVELS, MODE_QUEUE, MODE_PERSISTENT = 0, 1, 2
+MODE_LEVELS, MODE_PERSISTENT = 0, 2
 
 _TORCH_DTYPES = {
     torch.int32: I32,
@@ -170,9 +173,18 @@ def _key_code(t: torch.Tensor, key_type) -> int:
     return code
 
 
+# Contexts still open.  They are closed by an exit hook, which runs before
+# the interpreter (and with it PyTorch and the HIP runtime) is torn down:
+# destroying a context frees pinned host memory, events and a stream, which
+# must not happen after the runtime has shut down.
+_LIVE: "weakref.WeakSet[Context]" = weakref.WeakSet()
+
+
 class Context:
     """One library context: parameters, statistics and a workspace tensor
-    taken from PyTorch's caching allocator (grown on demand)."""
+    taken from PyTorch's caching allocator (grown on demand).  `close()`
+    releases it; contexts still open at interpreter exit are closed by an
+    exit hook."""
 
     def __init__(self, **params):
         h = ctypes.c_void_p()
@@ -180,14 +192,30 @@ class Context:
         self._h = h
         self._ws: torch.Tensor | None = None
         self._lock = threading.Lock()
+        _LIVE.add(self)
         for k, v in params.items():
             self.set_param(k, v)
 
-    def __del__(self):
+    def close(self):
+        """Waits for the context's work and releases it (idempotent)."""
         h = getattr(self, "_h", None)
-        if h is not None and lib is not None:
+        self._h = None
+        if h is not None:
             lib.bqs_ctx_destroy(h)
-            self._h = None
+        self._ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        # at interpreter shutdown the exit hook has already closed every
+        # context; a HIP call from here could run after the runtime is gone
+        if sys.is_finalizing():
+            return
+        self.close()
 
     _NAMES = {
         "small_cutoff": PARAM_SMALL_CUTOFF,
@@ -331,6 +359,12 @@ class Context:
                                                self._h),
                    "bqs_sort_segments_pairs")
         return keys, vals
+
+
+@atexit.register
+def _close_all():
+    for ctx in list(_LIVE):
+        ctx.close()
 
 
 _default: Context | None = None

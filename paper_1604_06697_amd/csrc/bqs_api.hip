@@ -147,62 +147,6 @@ __global__ __launch_bounds__(256) void k_map(Args a) {
     map_tiles(a, a.level, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
-// Clears the queue state (flags, status pool, counters).
-__global__ void k_qclear(Args a) {
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (uint64_t i = i0; i < a.cap_qitem; i += stride) a.qpub[i] = 0u;
-    for (uint64_t i = i0; i < a.cap_qstatus; i += stride) a.qstatus[i] = 0ull;
-    if (i0 == 0) {
-        QCtl* q = a.qctl;
-        q->head = q->tail = q->outstanding = q->status_next = 0;
-        q->segs = 0;
-        q->small_raw = 0;
-        for (int k = 0; k < kSmallClasses; ++k) q->small_cursor[k] = 0;
-        Ctl* c = a.ctl;
-        for (int s = 0; s < 2; ++s) {
-            c->lc[s].segs = 0;
-            c->lc[s].fills = 0;
-            for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
-            c->lc[s].tile_next = 0;
-            c->lc[s].keys = 0;
-        }
-        c->error = 0;
-        c->levels = 0;
-        c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
-        for (int k = 0; k < 8; ++k) c->prof[k] = 0;
-    }
-}
-
-// Packs the small segments of the work-queue run by size class: class c
-// occupies [sum of the counts of classes < c, + count of c) of smalls[0].
-__global__ void k_qbin(Args a) {
-    const Ctl* c = a.ctl;
-    QCtl* q = a.qctl;
-    uint32_t first[kSmallClasses];
-    uint32_t run = 0;
-    for (int k = 0; k < kSmallClasses; ++k) {
-        first[k] = run;
-        run += c->lc[0].smalls[k];
-    }
-    const uint32_t n = q->small_raw < a.cap_small ? q->small_raw : a.cap_small;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const SmallItem s = a.smalls[1][i];
-        const int64_t hi = s.hi & ((int64_t(1) << 62) - 1);
-        const int cls = small_class(hi - s.lo);
-        const uint32_t at = atomicAdd(&q->small_cursor[cls], 1u);
-        a.smalls[0][first[cls] + at] = s;
-    }
-}
-
-void launch_qclear(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_qclear, dim3(1024), dim3(256), 0, s, a);
-}
-
-void launch_qbin(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_qbin, dim3(256), dim3(256), 0, s, a);
-}
-
 // ------------------------------------------------------------- records --
 // The paper's large element types (Section 4, experimental setup), sorted as
 // (key, index) pairs and then gathered.  Vector: ten doubles ordered by the
@@ -260,18 +204,15 @@ void launch_init_segments(const Args& a, hipStream_t s) {
 struct Layout {
     size_t ctl, yk, yv, side, segs[2], smalls[2], fills[2], tile_desc, status, total;
     size_t splitters[2], toff, bcur, bstart;
-    size_t qctl, qsegs, qitems, qpub, qstatus;
     uint64_t cap_seg, cap_tile, cap_small, cap_fill;
-    uint64_t cap_qseg, cap_qitem, cap_qstatus;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-// Workspace layout.  Level mode keeps per-level lists (two slots); work-queue
-// mode keeps whole-sort lists whose capacities allow 16 partition passes
-// worth of segments and tiles (beyond that the run reports BQS_EOVERFLOW).
-static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S, bool queue,
-                          bool multiway) {
+// Workspace layout: the control block, the double buffer (keys, payloads
+// and the side buffer for payloads of pivot-equal keys) and the per-level
+// work lists in two slots.
+static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S, bool multiway) {
     Layout L{};
     const uint64_t un = static_cast<uint64_t>(n);
     const uint64_t uk = static_cast<uint64_t>(k);
@@ -286,37 +227,24 @@ static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T,
     L.yk = take(un * kb);
     L.yv = take(vb ? un * vb : 0);
     L.side = take(vb ? un * vb : 0);
-    if (!queue) {
-        // a two-way level gives each segment two children and one equal run;
-        // a multiway level up to 16 children and 15 equal runs
-        const uint64_t fan = multiway ? 16 : 2;
-        L.cap_seg = per_level_segs;
-        L.cap_tile = un / static_cast<uint64_t>(T) + 2 * L.cap_seg + 2;
-        L.cap_small = fan * L.cap_seg + uk + 2;
-        L.cap_fill = (fan - 1) * L.cap_seg + 1;
-        for (int s = 0; s < 2; ++s) L.segs[s] = take(L.cap_seg * sizeof(SegDesc));
-        for (int s = 0; s < 2; ++s) L.smalls[s] = take(kSmallClasses * L.cap_small * sizeof(SmallItem));
-        for (int s = 0; s < 2; ++s) L.fills[s] = take(L.cap_fill * sizeof(FillItem));
-        L.tile_desc = take(L.cap_tile * sizeof(TileDesc));
-        L.status = take(L.cap_tile * sizeof(unsigned long long));
-        // multiway levels: 16 splitters, 32 bucket cursors and 32 bucket
-        // starts per segment, 32 bucket offsets per tile
-        for (int s = 0; s < 2; ++s) L.splitters[s] = take(L.cap_seg * 16 * sizeof(uint64_t));
-        L.toff = take(L.cap_tile * 32 * sizeof(uint32_t));
-        L.bcur = take(L.cap_seg * 32 * sizeof(uint32_t));
-        L.bstart = take(L.cap_seg * 32 * sizeof(uint32_t));
-    } else {
-        L.cap_qseg = 16 * per_level_segs + uk + 1024;
-        L.cap_qstatus = 16 * (un / static_cast<uint64_t>(T)) + 2 * L.cap_qseg + 4096;
-        L.cap_qitem = L.cap_qstatus + un / kFillChunk + L.cap_qseg + 4096;
-        L.cap_small = 2 * L.cap_qseg + uk + 16;
-        L.qctl = take(sizeof(QCtl));
-        L.qsegs = take(L.cap_qseg * sizeof(SegQ));
-        L.qitems = take(L.cap_qitem * sizeof(QItem));
-        L.qpub = take(L.cap_qitem * sizeof(unsigned int));
-        L.qstatus = take(L.cap_qstatus * sizeof(unsigned long long));
-        for (int s = 0; s < 2; ++s) L.smalls[s] = take(L.cap_small * sizeof(SmallItem));
-    }
+    // a two-way level gives each segment two children and one equal run;
+    // a multiway level up to 16 children and 15 equal runs
+    const uint64_t fan = multiway ? 16 : 2;
+    L.cap_seg = per_level_segs;
+    L.cap_tile = un / static_cast<uint64_t>(T) + 2 * L.cap_seg + 2;
+    L.cap_small = fan * L.cap_seg + uk + 2;
+    L.cap_fill = (fan - 1) * L.cap_seg + 1;
+    for (int s = 0; s < 2; ++s) L.segs[s] = take(L.cap_seg * sizeof(SegDesc));
+    for (int s = 0; s < 2; ++s) L.smalls[s] = take(kSmallClasses * L.cap_small * sizeof(SmallItem));
+    for (int s = 0; s < 2; ++s) L.fills[s] = take(L.cap_fill * sizeof(FillItem));
+    L.tile_desc = take(L.cap_tile * sizeof(TileDesc));
+    L.status = take(L.cap_tile * sizeof(unsigned long long));
+    // multiway levels: 16 splitters, 32 bucket cursors and 32 bucket
+    // starts per segment, 32 bucket offsets per tile
+    for (int s = 0; s < 2; ++s) L.splitters[s] = take(L.cap_seg * 16 * sizeof(uint64_t));
+    L.toff = take(L.cap_tile * 32 * sizeof(uint32_t));
+    L.bcur = take(L.cap_seg * 32 * sizeof(uint32_t));
+    L.bstart = take(L.cap_seg * 32 * sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -355,7 +283,6 @@ struct bqs_ctx {
     hipGraphExec_t gexec = nullptr;
     std::vector<uint64_t> gkey;
     int glevels = 0;
-    int64_t queue_grid = 0;  // resident workgroups of the queue kernel (cached)
     int64_t persist_grid = 0;  // resident workgroups of the persistent kernel (cached per table)
     const void* persist_ops = nullptr;
     bqs_stats stats{};
@@ -508,7 +435,6 @@ void fill_stats(bqs_stats& stats, const Ctl& c) {
     stats.prof_load_cycles = static_cast<double>(c.prof[5]);
 }
 
-bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented);
 bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented);
 void drop_graph(bqs_ctx* ctx);
 
@@ -568,7 +494,7 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
         if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
         tm.resolve(stats);
-        if (ctx->pinned->error) return BQS_EOVERFLOW;
+        if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
         cur = ctx->pinned->lc[(L + 1) & 1];
     }
     return BQS_OK;
@@ -589,13 +515,13 @@ bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     else launch_init_single(a, s);
     if (hipGetLastError() != hipSuccess) return BQS_EHIP;
     if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
-    if (ctx->pinned->error) return (ctx->pinned->error & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
+    if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
     ctx->level_keys.clear();
     ctx->level_ms.clear();
     if ((st = level_loop(ctx, o, a, 0, ctx->pinned->lc[0], tm, stats)) != BQS_OK) return st;
     if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
     tm.resolve(stats);
-    if (ctx->pinned->error) return BQS_EOVERFLOW;
+    if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
     fill_stats(stats, *ctx->pinned);
     ctx->stats = stats;
     return BQS_OK;
@@ -709,7 +635,7 @@ bqs_status run_graph(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     if (hipGraphLaunch(ctx->gexec, ctx->stream) != hipSuccess) return BQS_EHIP;
     if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
     tm.resolve(stats);
-    if (ctx->pinned->error) return (ctx->pinned->error & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
+    if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
     stats.graph_launches = 1;
     // work the graph's levels did not reach: continue host-driven
     const LevelCtr cur = ctx->pinned->lc[ctx->glevels & 1];
@@ -719,7 +645,7 @@ bqs_status run_graph(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
         if ((st = level_loop(ctx, o, a, ctx->glevels, cur, tm, stats)) != BQS_OK) return st;
         if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
         tm.resolve(stats);
-        if (ctx->pinned->error) return BQS_EOVERFLOW;
+        if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
     }
     fill_stats(stats, *ctx->pinned);
     ctx->stats = stats;
@@ -733,56 +659,9 @@ bqs_status run_graph(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
 
 // The entry points' common driver.
 bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
-    if (ctx->mode == BQS_MODE_QUEUE) return run_queue(ctx, o, a, segmented);
     if (ctx->mode == BQS_MODE_PERSISTENT) return run_persist(ctx, o, a, segmented);
     if (ctx->graph) return run_graph(ctx, o, a, segmented);
     return run_levels(ctx, o, a, segmented);
-}
-
-// Work-queue mode: seed, drain with one persistent launch, bin and sort the
-// small segments.  No host synchronisation until the final status read.
-bqs_status run_queue(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
-    bqs_status st = ensure_device_state(ctx);
-    if (st != BQS_OK) return st;
-    const hipStream_t s = ctx->stream;
-    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1};
-    tm.resolve(ctx->stats);
-    bqs_stats stats{};
-    stats.tile_keys = a.tile_keys;
-    stats.small_cutoff = a.small_cut;
-    ctx->level_keys.clear();
-    ctx->level_ms.clear();
-    if (ctx->queue_grid <= 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return BQS_EHIP;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return BQS_EHIP;
-        const int per = o->qblocks_per_cu();
-        if (per <= 0 || cus <= 0) return BQS_EHIP;
-        ctx->queue_grid = static_cast<int64_t>(per) * cus;
-    }
-    const int grid = static_cast<int>(ctx->grid > 0 ? std::min<int64_t>(ctx->grid, ctx->queue_grid) : ctx->queue_grid);
-    tm.start();
-    o->qinit(a, segmented ? static_cast<int>(a.k) : 1, s);
-    tm.stop(0, 0);
-    tm.start();
-    o->qrun(a, grid, s);
-    tm.stop(2, 0);
-    for (int cls = 0; cls < kSmallClasses; ++cls) {
-        if (!o->small[cls]) continue;
-        tm.start();
-        o->small[cls](a, 2048, s);
-        tm.stop(1, 0);
-        stats.small_launches++;
-    }
-    if (hipGetLastError() != hipSuccess) return BQS_EHIP;
-    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
-    tm.resolve(stats);
-    const unsigned err = ctx->pinned->error;
-    if (err) return (err & ERR_OFFSETS) ? BQS_EINVAL : BQS_EOVERFLOW;
-    stats.partition_launches = 1;
-    fill_stats(stats, *ctx->pinned);
-    ctx->stats = stats;
-    return BQS_OK;
 }
 
 // Persistent mode: init, then one cooperative launch of every workgroup the
@@ -819,10 +698,7 @@ bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     if (e != hipSuccess || hipGetLastError() != hipSuccess) return BQS_EHIP;
     if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
     tm.resolve(stats);
-    const unsigned err = ctx->pinned->error;
-    if (err & ERR_OFFSETS) return BQS_EINVAL;
-    if (err & ERR_STALL) return BQS_EHIP;
-    if (err) return BQS_EOVERFLOW;
+    if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
     fill_stats(stats, *ctx->pinned);
     stats.partition_launches = 1;
     ctx->stats = stats;
@@ -833,11 +709,9 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
                    void* vals, Args& a) {
     const size_t kb = key_bytes(dtype);
     const int64_t S = eff_small_cut(ctx, o);
-    const bool queue = ctx->mode == BQS_MODE_QUEUE;
-    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S, queue,
+    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S,
                                  ctx->multiway && o->mscan);
-    if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull ||
-        L.cap_qseg > 0xffffffffull || L.cap_qitem > 0xffffffffull)
+    if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull)
         return BQS_EINVAL;
     if (!ctx->ws || ctx->ws_bytes < L.total) return BQS_EINVAL;
     if (overlaps(keys, static_cast<size_t>(n) * kb, ctx->ws, ctx->ws_bytes)) return BQS_EINVAL;
@@ -882,17 +756,6 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.prof = static_cast<int>(ctx->profile);
     a.claim = ctx->lookback ? 0 : 1;
     a.ways = multiway ? 1 : 0;
-    a.queue = queue ? 1 : 0;
-    if (queue) {
-        a.qctl = reinterpret_cast<QCtl*>(w + L.qctl);
-        a.qsegs = reinterpret_cast<SegQ*>(w + L.qsegs);
-        a.qitems = reinterpret_cast<QItem*>(w + L.qitems);
-        a.qpub = reinterpret_cast<unsigned int*>(w + L.qpub);
-        a.qstatus = reinterpret_cast<unsigned long long*>(w + L.qstatus);
-        a.cap_qseg = static_cast<uint32_t>(L.cap_qseg);
-        a.cap_qitem = static_cast<uint32_t>(L.cap_qitem);
-        a.cap_qstatus = L.cap_qstatus;
-    }
     return BQS_OK;
 }
 
@@ -984,12 +847,8 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
         case BQS_PARAM_LOOKBACK: ctx->lookback = value ? 1 : 0; break;
         case BQS_PARAM_MULTIWAY: ctx->multiway = value ? 1 : 0; break;
         case BQS_PARAM_MODE:
-            // The work-queue kernel took a memory-aperture fault on its first
-            // input with partition tiles (n = 8193 int32) and the cause is not
-            // known; that mode stays closed until it is.
             if (value != BQS_MODE_LEVELS && value != BQS_MODE_PERSISTENT) return BQS_EINVAL;
             ctx->mode = value;
-            ctx->queue_grid = 0;
             drop_graph(ctx);
             break;
         default: return BQS_EINVAL;
@@ -1036,7 +895,7 @@ size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, i
     if (!o) return 0;
     const Layout L = make_layout(n_total, key_bytes(key), static_cast<size_t>(val_bytes),
                                  std::max<int64_t>(k_segments, 1), eff_tile_keys(ctx, o), eff_small_cut(ctx, o),
-                                 ctx && ctx->mode == BQS_MODE_QUEUE, ctx && ctx->multiway && o->mscan);
+                                 ctx && ctx->multiway && o->mscan);
     return L.total;
 }
 

@@ -18,6 +18,7 @@
 #include <cstdint>
 
 #include "bqs.h"
+#include "bqs_status_map.h"
 
 namespace bqs {
 
@@ -83,47 +84,7 @@ struct LevelCtr {
     unsigned long long keys;   // keys in the segments of this list (statistics)
 };
 
-enum : unsigned { ERR_OVERFLOW = 1u, ERR_OFFSETS = 2u, ERR_STALL = 4u };
-
 constexpr int kMaxXcd = 16;  // XCD ids the persistent barrier can index (MI355X has 8)
-
-// ---- work-queue mode --------------------------------------------------------
-// The recursion as a device-resident queue: items are published into a
-// linear array (a flag per slot, set after a release fence) and claimed in
-// order with an atomic counter by the workgroups of one persistent kernel.
-
-enum : uint32_t { QK_TILE = 1, QK_FILL = 2 };
-
-struct QItem {
-    uint32_t kind;  // QK_TILE or QK_FILL
-    uint32_t seg;   // segment index
-    uint32_t j;     // tile or fill work unit within the segment
-    uint32_t pad;
-};
-
-struct SegQ {
-    int64_t lo, hi;
-    uint64_t pivot;      // order key
-    uint64_t pivot_raw;  // stored bits
-    uint64_t st_base;    // first status word of the segment's tiles
-    uint32_t nt;         // tiles
-    uint32_t depth;
-    uint32_t buf;        // buffer holding the keys: 0 = X, 1 = Y
-    uint32_t done;       // tiles finished
-    uint32_t fill_left;  // pairs: fill units still running; the last one spawns the children
-    uint32_t pad;
-    int64_t Lt, Gt;      // totals, written by the segment's finisher
-};
-
-struct QCtl {
-    unsigned long long head;         // next item to claim
-    unsigned long long tail;         // next item slot to reserve
-    unsigned long long outstanding;  // items published and not yet completed
-    unsigned long long status_next;  // status words handed out
-    unsigned int segs;               // segment descriptors handed out
-    unsigned int small_raw;          // small segments in arrival order (binned by class afterwards)
-    unsigned int small_cursor[kSmallClasses];
-};
 
 struct Ctl {
     LevelCtr lc[2];
@@ -175,15 +136,6 @@ struct Args {
     uint32_t* toff;          // per tile: offset of its keys inside each bucket
     uint32_t* bcur;          // per segment: bucket cursors (stride 32)
     uint32_t* bstart;        // per segment: bucket starts from the segment start
-    // work-queue mode
-    int queue;
-    QCtl* qctl;
-    SegQ* qsegs;
-    QItem* qitems;
-    unsigned int* qpub;
-    unsigned long long* qstatus;
-    uint32_t cap_qseg, cap_qitem;
-    uint64_t cap_qstatus;
 };
 
 struct Ops {
@@ -204,10 +156,6 @@ struct Ops {
     void (*mcount)(const Args&, int grid, hipStream_t);
     void (*mscan)(const Args&, int grid, hipStream_t);
     void (*mscatter)(const Args&, int grid, hipStream_t);
-    // work-queue mode: clear + seed the queue, drain it with `grid` workgroups
-    void (*qinit)(const Args&, int grid, hipStream_t);
-    void (*qrun)(const Args&, int grid, hipStream_t);
-    int (*qblocks_per_cu)();
     // persistent mode: every level in one cooperative launch of `grid`
     // resident workgroups; small segments up to persist_small_max keys
     hipError_t (*persist)(const Args&, int grid, hipStream_t);
@@ -252,7 +200,5 @@ const Ops* ops_pairs64(int dtype);
 void launch_init_single(const Args& a, hipStream_t s);
 void launch_init_segments(const Args& a, hipStream_t s);
 void launch_map(const Args& a, int grid, hipStream_t s);
-void launch_qclear(const Args& a, hipStream_t s);
-void launch_qbin(const Args& a, hipStream_t s);
 
 }  // namespace bqs

@@ -470,7 +470,7 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// Partition tile, shared by the level-mode kernel and the work-queue kernel.
+// Partition tile, shared by the level-mode and persistent kernels.
 //
 // One workgroup partitions one tile of T = NT*EPT keys of a segment [lo, hi)
 // around the segment's pivot: keys < pivot go to the left run, keys > pivot
@@ -986,351 +986,6 @@ __global__ __launch_bounds__(256) void k_complete(Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// Work-queue mode: the recursion as a device-resident queue drained by one
-// persistent kernel (Quicksort main loop, Algorithm 1 with an explicit stack,
-// Section 2: here the "stack" holds tiles of every open segment at once).
-//
-// Protocol.  A producer reserves slots with an atomic add on `tail`, writes
-// the items, fences (release, agent scope) and then sets each slot's flag.
-// A consumer claims the next slot with an atomic add on `head`, waits for its
-// flag, fences (acquire) and reads the item.  `outstanding` counts items that
-// are published or running; producers raise it before publishing and an item
-// lowers it only after publishing its own follow-up work, so it reaches zero
-// exactly when the sort is done -- that is when waiting workgroups leave.
-// A segment's tiles each fence and then count themselves done; the last one
-// to finish (its acquire fence makes every tile's output visible) writes the
-// equal run, picks the children's pivots and publishes their tiles.  Every
-// wait is bounded by a wall-clock limit: past it the kernel latches
-// ERR_STALL and every workgroup leaves, so the launch always terminates.
-
-constexpr unsigned long long kSpinTicks = 1ull << 27;  // ~1.3 s of the 100 MHz wall clock
-constexpr int64_t kInlineFill = 16384;                  // equal runs written by the finisher itself
-
-__device__ __forceinline__ unsigned ld_flag(const unsigned int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Pivot of keys src[lo, hi): median of a stratified sample (all NT threads).
-template <int DT, int NT>
-__device__ typename KeyT<DT>::raw pick_pivot(const typename KeyT<DT>::raw* src, int64_t lo, int64_t hi,
-                                             uint32_t depth, const Args& a) {
-    using K = KeyT<DT>;
-    using R = typename K::raw;
-    static_assert(NT >= kMaxSample + 1, "one thread per sample");
-    __shared__ R s_samp[kMaxSample + 1];
-    __shared__ R s_pick;
-    const int tid = threadIdx.x;
-    const int64_t m = hi - lo;
-    int k;
-    if (a.pivot_mode == 3 && depth < static_cast<uint32_t>(a.depth_limit)) {
-        k = 3;
-    } else {
-        // about sqrt(m)/4 samples, odd, within [7, sample_max]; past the
-        // depth limit the largest sample is used
-        int64_t kk = static_cast<int64_t>(sqrt(static_cast<double>(m))) / 4;
-        if (depth >= static_cast<uint32_t>(a.depth_limit)) kk = a.sample_max;
-        if (kk > a.sample_max) kk = a.sample_max;
-        if (kk < 7) kk = 7;
-        if (kk > m) kk = m;
-        k = static_cast<int>(kk) | 1;
-        if (k > m) k -= 2;
-    }
-    __syncthreads();  // s_samp may still be read by a previous call
-    if (tid < k) {
-        int64_t pos;
-        if (k == 3) {
-            pos = tid == 0 ? lo : (tid == 1 ? lo + m / 2 : hi - 1);
-        } else {
-            const int64_t stride = m / k;
-            const uint64_t h = mix64((static_cast<uint64_t>(lo) * 0x9e3779b97f4a7c15ull) ^
-                                     (static_cast<uint64_t>(hi) << 17) ^ (static_cast<uint64_t>(tid) << 40) ^ depth);
-            pos = lo + tid * stride + static_cast<int64_t>(h % static_cast<uint64_t>(stride));
-        }
-        s_samp[tid] = src[pos];
-    }
-    __syncthreads();
-    if (tid < k) {
-        // rank of this sample: smaller samples, plus equal ones of lower index
-        const R mine = s_samp[tid];
-        const auto om = K::ord(mine);
-        int rank = 0;
-        for (int j = 0; j < k; ++j) {
-            const auto oj = K::ord(s_samp[j]);
-            rank += (oj < om) | ((oj == om) & (j < tid));
-        }
-        if (rank == k / 2) s_pick = mine;
-    }
-    __syncthreads();
-    return s_pick;
-}
-
-// Publishes `count` items (kind, seg, 0..count-1).  All NT threads.
-template <int NT>
-__device__ void q_publish(const Args& a, uint32_t kind, uint32_t seg, uint32_t count) {
-    __shared__ unsigned long long s_pos;
-    const int tid = threadIdx.x;
-    QCtl* q = a.qctl;
-    if (tid == 0) {
-        atomicAdd(&q->outstanding, static_cast<unsigned long long>(count));
-        s_pos = atomicAdd(&q->tail, static_cast<unsigned long long>(count));
-    }
-    __syncthreads();
-    const unsigned long long pos = s_pos;
-    if (pos + count > a.cap_qitem) {
-        if (tid == 0) atomicOr(&a.ctl->error, ERR_OVERFLOW);
-        return;
-    }
-    for (uint32_t i = tid; i < count; i += NT) a.qitems[pos + i] = QItem{kind, seg, i, 0u};
-    __threadfence();  // release: items, segment descriptors and the data they describe
-    __syncthreads();
-    for (uint32_t i = tid; i < count; i += NT)
-        __hip_atomic_store(&a.qpub[pos + i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// A child segment [lo, hi) whose keys sit in buffer `buf`: small segments go
-// to the small-sort lists, larger ones get a pivot, status words and tiles.
-template <int DT, class V, int NT, int EPT>
-__device__ void q_spawn(const Args& a, int64_t lo, int64_t hi, uint32_t depth, uint32_t buf) {
-    using K = KeyT<DT>;
-    using R = typename K::raw;
-    constexpr int64_t T = NT * EPT;
-    __shared__ uint32_t s_seg;
-    __shared__ int s_ok;
-    const int tid = threadIdx.x;
-    const int64_t m = hi - lo;
-    if (m <= 0) return;
-    Ctl* c = a.ctl;
-    if (m <= a.small_cut) {
-        if (tid == 0 && !(m == 1 && buf == 0)) {
-            // arrival-order list; binned by size class once the queue drained
-            const uint32_t idx = atomicAdd(&a.qctl->small_raw, 1u);
-            if (idx >= a.cap_small) {
-                atomicOr(&c->error, ERR_OVERFLOW);
-            } else {
-                atomicAdd(&c->lc[0].smalls[small_class(m)], 1u);
-                a.smalls[1][idx] = SmallItem{lo, hi | (static_cast<int64_t>(buf) << 62)};
-            }
-        }
-        return;
-    }
-    const R* src = static_cast<const R*>(buf ? a.y_keys : a.x_keys);
-    const R piv = pick_pivot<DT, NT>(src, lo, hi, depth, a);
-    const uint32_t nt = seg_tiles(lo, hi, T);
-    if (tid == 0) {
-        QCtl* q = a.qctl;
-        const uint32_t si = atomicAdd(&q->segs, 1u);
-        const unsigned long long sb = atomicAdd(&q->status_next, static_cast<unsigned long long>(nt));
-        const bool ok = si < a.cap_qseg && sb + nt <= a.cap_qstatus;
-        if (ok) {
-            SegQ d{};
-            d.lo = lo;
-            d.hi = hi;
-            d.pivot = static_cast<uint64_t>(K::ord(piv));
-            d.pivot_raw = static_cast<uint64_t>(piv);
-            d.st_base = sb;
-            d.nt = nt;
-            d.depth = depth;
-            d.buf = buf;
-            a.qsegs[si] = d;
-            atomicAdd(&c->part_keys, static_cast<unsigned long long>(m));
-            atomicAdd(&c->tiles, static_cast<unsigned long long>(nt));
-        } else {
-            atomicOr(&c->error, ERR_OVERFLOW);
-        }
-        s_seg = si;
-        s_ok = ok;
-    }
-    __syncthreads();
-    if (s_ok) q_publish<NT>(a, QK_TILE, s_seg, nt);
-}
-
-// Writes units [u0, u1) of keys equal to the pivot (and, for pairs, their
-// payloads from the side buffer) into X.  All NT threads.
-template <int DT, class V, int NT>
-__device__ void q_fill(const Args& a, const SegQ& sd, int64_t b, int64_t e) {
-    using R = typename KeyT<DT>::raw;
-    using VS = typename ValStore<V>::type;
-    constexpr bool HV = !std::is_same<V, NoVal>::value;
-    R* xk = static_cast<R*>(a.x_keys) + sd.lo + sd.Lt;
-    const R raw = static_cast<R>(sd.pivot_raw);
-    for (int64_t t = b + threadIdx.x; t < e; t += NT) {
-        xk[t] = raw;
-        if constexpr (HV) static_cast<VS*>(a.x_vals)[sd.lo + sd.Lt + t] = static_cast<const VS*>(a.side)[sd.lo + t];
-    }
-}
-
-template <int DT, class V, int NT, int EPT>
-__device__ void q_children(const Args& a, const SegQ& sd) {
-    q_spawn<DT, V, NT, EPT>(a, sd.lo, sd.lo + sd.Lt, sd.depth + 1, sd.buf ^ 1u);
-    q_spawn<DT, V, NT, EPT>(a, sd.hi - sd.Gt, sd.hi, sd.depth + 1, sd.buf ^ 1u);
-}
-
-// Segment completion by the workgroup of its last finishing tile.
-template <int DT, class V, int NT, int EPT>
-__device__ void q_complete(const Args& a, uint32_t si, int64_t Lt, int64_t Gt) {
-    constexpr bool HV = !std::is_same<V, NoVal>::value;
-    __shared__ SegQ s_sd;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        SegQ* sd = &a.qsegs[si];
-        sd->Lt = Lt;
-        sd->Gt = Gt;
-        s_sd = *sd;
-        s_sd.Lt = Lt;
-        s_sd.Gt = Gt;
-    }
-    __syncthreads();
-    const SegQ sd = s_sd;
-    const int64_t Et = (sd.hi - sd.lo) - Lt - Gt;
-    if (tid == 0 && Et > 0) atomicAdd(&a.ctl->fill_keys, static_cast<unsigned long long>(Et));
-    if (Et <= kInlineFill) {
-        q_fill<DT, V, NT>(a, sd, 0, Et);
-        if constexpr (HV) __threadfence();  // side reads done before children may overwrite it
-        __syncthreads();
-        q_children<DT, V, NT, EPT>(a, sd);
-    } else {
-        const uint32_t nch = static_cast<uint32_t>((Et + kFillChunk - 1) / kFillChunk);
-        if constexpr (HV) {
-            // the children reuse the side buffer: they start after the last fill unit
-            if (tid == 0) a.qsegs[si].fill_left = nch;
-            q_publish<NT>(a, QK_FILL, si, nch);
-        } else {
-            q_publish<NT>(a, QK_FILL, si, nch);
-            q_children<DT, V, NT, EPT>(a, sd);
-        }
-    }
-}
-
-template <int DT, class V, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_queue(Args a) {
-    constexpr bool HV = !std::is_same<V, NoVal>::value;
-    __shared__ TileLds<DT, V, NT, EPT> s_tl;
-    __shared__ QItem s_item;
-    __shared__ int s_exit;
-    __shared__ int s_fin;
-    __shared__ int64_t s_tot[2];
-    __shared__ SegQ s_sd;
-    const int tid = threadIdx.x;
-    QCtl* q = a.qctl;
-    Ctl* c = a.ctl;
-    for (;;) {
-        if (tid == 0) {
-            int ex = 0;
-            const unsigned long long h = atomicAdd(&q->head, 1ull);
-            if (h >= a.cap_qitem) {
-                ex = 1;  // no item can ever be published there
-            } else {
-                const unsigned long long t0 = wall_clock64();
-                for (;;) {
-                    if (ld_flag(&a.qpub[h]) != 0u) break;
-                    if (ld_u64(&q->outstanding) == 0ull || __hip_atomic_load(&c->error, __ATOMIC_RELAXED,
-                                                                            __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                        ex = 1;
-                        break;
-                    }
-                    if (wall_clock64() - t0 > kSpinTicks) {
-                        atomicOr(&c->error, ERR_STALL);
-                        ex = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                if (!ex) {
-                    __threadfence();  // acquire: the item and what it describes
-                    s_item = a.qitems[h];
-                    s_sd = a.qsegs[s_item.seg];
-                }
-            }
-            s_exit = ex;
-        }
-        __syncthreads();
-        if (s_exit) return;
-        __threadfence();  // every wave: acquire before touching the segment's data
-        const QItem it = s_item;
-        const SegQ sd = s_sd;
-        if (it.kind == QK_TILE) {
-            TileIO io;
-            io.error = &c->error;
-            io.src = sd.buf ? a.y_keys : a.x_keys;
-            io.dst = sd.buf ? a.x_keys : a.y_keys;
-            io.vsrc = sd.buf ? a.y_vals : a.x_vals;
-            io.vdst = sd.buf ? a.x_vals : a.y_vals;
-            io.side = a.side;
-            io.status = a.qstatus + sd.st_base;
-            io.cursor = nullptr;
-            io.lo = sd.lo;
-            io.hi = sd.hi;
-            io.pivot = sd.pivot;
-            io.j = it.j;
-            const TileOut r = tile_partition<DT, V, NT, EPT>(io, nullptr, s_tl);
-            __threadfence();  // release this tile's output
-            __syncthreads();
-            if (tid == 0) {
-                if (!r.ok) atomicOr(&c->error, ERR_OVERFLOW);
-                const uint32_t old = atomicAdd(&a.qsegs[it.seg].done, 1u);
-                const bool fin = old + 1 == sd.nt;
-                if (fin) {
-                    // totals: the inclusive status word of the segment's last tile
-                    const uint64_t st = r.last ? st_pack(kStInc, r.Lx + r.nlt, r.Gx + r.ngt)
-                                               : ld_status(&a.qstatus[sd.st_base + sd.nt - 1]);
-                    s_tot[0] = static_cast<int64_t>((st >> 31) & kM31);
-                    s_tot[1] = static_cast<int64_t>(st & kM31);
-                }
-                s_fin = fin;
-            }
-            __syncthreads();
-            if (s_fin) {
-                __threadfence();  // acquire: every tile's output
-                q_complete<DT, V, NT, EPT>(a, it.seg, s_tot[0], s_tot[1]);
-            }
-        } else {
-            const int64_t Et = (sd.hi - sd.lo) - sd.Lt - sd.Gt;
-            const int64_t b = static_cast<int64_t>(it.j) * kFillChunk;
-            const int64_t e = b + kFillChunk < Et ? b + kFillChunk : Et;
-            q_fill<DT, V, NT>(a, sd, b, e);
-            if constexpr (HV) {
-                __threadfence();
-                __syncthreads();
-                if (tid == 0) s_fin = atomicSub(&a.qsegs[it.seg].fill_left, 1u) == 1u;
-                __syncthreads();
-                if (s_fin) {
-                    __threadfence();
-                    q_children<DT, V, NT, EPT>(a, sd);
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0) atomicSub(&q->outstanding, 1ull);
-    }
-}
-
-// Seeds the queue: one workgroup per input segment (the whole array for a
-// single sort), validating segment offsets.
-template <int DT, class V, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_qseed(Args a) {
-    const int64_t i = blockIdx.x;
-    int64_t lo = 0, hi = a.n;
-    if (a.offsets) {
-        if (i >= a.k) return;
-        lo = a.offsets[i];
-        hi = a.offsets[i + 1];
-        const bool bad = lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) || (i == a.k - 1 && hi != a.n) ||
-                         hi - lo >= (int64_t(1) << 31);
-        if (bad) {
-            if (threadIdx.x == 0) atomicOr(&a.ctl->error, ERR_OFFSETS);
-            return;
-        }
-    } else if (i > 0) {
-        return;
-    }
-    q_spawn<DT, V, NT, EPT>(a, lo, hi, 0, 0);
-}
-
-// ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
 // Small-segment sort (the paper's Insertionsort stage, Section 2).
 //
 // A group of NTH threads (one wave, or a 256-thread workgroup) sorts one
@@ -1557,14 +1212,8 @@ __device__ void small_body(const Args& a, int level, int cls, uint32_t bid, uint
     const uint32_t nsm = c->lc[p].smalls[cls];
     R* xk = static_cast<R*>(a.x_keys);
     VS* xv = static_cast<VS*>(a.x_vals);
-    // level mode: one region of cap_small items per class; work-queue mode:
-    // the classes are packed back to back (binned after the queue drained)
-    size_t first = static_cast<size_t>(cls) * a.cap_small;
-    if (a.queue) {
-        first = 0;
-        for (int k = 0; k < cls; ++k) first += c->lc[0].smalls[k];
-    }
-    const SmallItem* items = a.smalls[p] + first;
+    // one region of cap_small items per class
+    const SmallItem* items = a.smalls[p] + static_cast<size_t>(cls) * a.cap_small;
     O* sk = s_k + grp * PS;
     uint32_t* si = HV ? s_i + grp * PS : s_i;
     VS* sv = HV ? s_v + grp * P : s_v;
@@ -1576,17 +1225,13 @@ __device__ void small_body(const Args& a, int level, int cls, uint32_t bid, uint
         const bool have = it < nsm;
         int64_t lo = 0;
         int m = 0;
-        int par = p;
         if (have) {
             const SmallItem s = items[it];
-            // work-queue mode keeps the item's buffer in bit 62 of hi
-            const int64_t hi = s.hi & ((int64_t(1) << 62) - 1);
-            if (a.queue) par = static_cast<int>((static_cast<uint64_t>(s.hi) >> 62) & 1u);
             lo = s.lo;
-            m = static_cast<int>(hi - s.lo);
+            m = static_cast<int>(s.hi - s.lo);
         }
-        const R* src = static_cast<const R*>(par ? a.y_keys : a.x_keys);
-        const VS* vsrc = static_cast<const VS*>(par ? a.y_vals : a.x_vals);
+        const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
+        const VS* vsrc = static_cast<const VS*>(p ? a.y_vals : a.x_vals);
         // striped (coalesced) load into LDS, padding with the largest key
 #pragma unroll
         for (int r = 0; r < E; ++r) {
@@ -1657,6 +1302,8 @@ __global__ __launch_bounds__(NTH > 256 ? NTH : 256, 6) void k_small(Args a, int 
 // on the device, at the first level with no segment left to partition, so
 // the host waits once per sort.  The steps run the same code as the
 // level-mode kernels.
+
+constexpr unsigned long long kSpinTicks = 1ull << 27;  // ~1.3 s of the 100 MHz wall clock
 
 // Waits (one thread) until the barrier generation reaches `want`; 0 when
 // the wait ran out or another workgroup latched ERR_STALL.
@@ -1912,21 +1559,6 @@ struct Launch {
     static void complete(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_complete<V>), dim3(grid), dim3(256), 0, s, a);
     }
-    // work-queue mode: clear, seed one workgroup per input segment
-    static void qinit(const Args& a, int grid, hipStream_t s) {
-        launch_qclear(a, s);
-        hipLaunchKernelGGL((k_qseed<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
-    }
-    // drain the queue with `grid` resident workgroups, then bin the small segments
-    static void qrun(const Args& a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_queue<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
-        launch_qbin(a, s);
-    }
-    static int qblocks_per_cu() {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_queue<DT, V, NT, EPT>, NT, 0) != hipSuccess) return 0;
-        return nb;
-    }
     static void map(const Args& a, int grid, hipStream_t s) { launch_map(a, grid, s); }
     // persistent mode: small segments up to 4096 keys (the classes whose
     // groups fit a 256-thread workgroup)
@@ -1965,9 +1597,6 @@ struct Launch {
             MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::c(),
             MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::sc(),
             MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::sa(),
-            &qinit,
-            &qrun,
-            &qblocks_per_cu,
             &persist,
             &persist_blocks_per_cu,
             kPersistSmall,

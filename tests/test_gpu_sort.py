@@ -261,6 +261,10 @@ def test_segments_pairs_match_oracle(torch_mod, bqs, oracle):
         torch.cuda.synchronize()
         ko = from_dev(tk, keys.dtype)
         vo = tv.cpu().numpy().view(np.uint32).astype(np.int64)
+        # the payloads are a permutation of the indexes: none lost, none
+        # duplicated (a payload copied twice among equal keys would keep the
+        # key check below green)
+        assert np.array_equal(np.sort(vo), np.arange(n))
         for i in range(len(sizes)):
             lo, hi = offsets[i], offsets[i + 1]
             assert_same_bits(ko[lo:hi], oracle.sort(keys[lo:hi]))
