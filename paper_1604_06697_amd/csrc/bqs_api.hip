@@ -457,13 +457,11 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(std::max<uint64_t>((nseg + 3) / 4, nchunk), 16384), s);
         if (nseg && a.ways) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
         tm.stop_aux(0, L);
-        for (int cls = 0; cls < kSmallClasses; ++cls) {
-            const uint32_t cnt = cur.smalls[cls];
-            if (!cnt) continue;
-            if (!o->small[cls]) return BQS_EOVERFLOW;  // cannot happen: classes follow small_cut
-            const uint32_t per = static_cast<uint32_t>(o->small_per_block[cls]);
+        uint32_t nsmall = 0;
+        for (int cls = 0; cls < kSmallClasses; ++cls) nsmall += cur.smalls[cls];
+        if (nsmall) {
             tm.start_aux();
-            o->small[cls](a, clamp_grid((cnt + per - 1) / per, 16384), s);
+            o->small(a, clamp_grid(nsmall, 16384), s);
             tm.stop_aux(1, L);
             stats.small_launches++;
         }
@@ -579,8 +577,7 @@ bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, Args a, bool segmented, int
         a.level = L;
         (a.ways ? o->plan_multi : o->plan)(a, 2048, cs);
         if (a.ways) o->map(a, 4096, cs);
-        for (int cls = 0; cls < kSmallClasses; ++cls)
-            if (o->small[cls]) o->small[cls](a, 2048, cs);
+        o->small(a, 2048, cs);
         const uint64_t tb = tile_bound(a, L);
         if (tb > 0x7fffffffull) {
             hipGraph_t g = nullptr;

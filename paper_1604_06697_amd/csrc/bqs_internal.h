@@ -144,8 +144,8 @@ struct Ops {
     int small_default;  // default cutoff (measured best for the tile size)
     void (*plan)(const Args&, int grid, hipStream_t);
     void (*map)(const Args&, int grid, hipStream_t);
-    void (*small[kSmallClasses])(const Args&, int grid, hipStream_t);  // nullptr beyond small_max
-    int small_per_block[kSmallClasses];  // segments one workgroup sorts at once
+    // every small segment of the level (all size classes), one per workgroup
+    void (*small)(const Args&, int grid, hipStream_t);
     void (*tile)(const Args&, int grid, hipStream_t);
     // segment completion after a partition launch: children and equal runs
     // of every segment of the level
@@ -170,8 +170,10 @@ struct Ops {
 __device__ inline void map_tiles(const Args& a, int level, uint32_t gtid, uint32_t gstride) {
     const int p = level & 1;
     const unsigned long long sc = a.ctl->lc[p].segs;
-    const uint32_t nseg = static_cast<uint32_t>(sc);
-    const uint32_t ntile = static_cast<uint32_t>(sc >> 32);
+    // counts past the capacities mean an overflow was latched: only the
+    // entries that were written are read
+    const uint32_t nseg = static_cast<uint32_t>(sc) < a.cap_seg ? static_cast<uint32_t>(sc) : a.cap_seg;
+    const uint32_t ntile = static_cast<uint32_t>(sc >> 32) < a.cap_tile ? static_cast<uint32_t>(sc >> 32) : a.cap_tile;
     const SegDesc* segs = a.segs[p];
     for (uint32_t t = gtid; t < ntile; t += gstride) {
         uint32_t lo_i = 0, hi_i = nseg;

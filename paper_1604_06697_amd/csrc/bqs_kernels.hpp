@@ -252,7 +252,9 @@ __device__ void run_fills(const Args& a, int p, uint32_t bid, uint32_t nblk) {
     const Ctl* c = a.ctl;
     const int tid = threadIdx.x;
     const unsigned long long fc = c->lc[p].fills;
-    const uint32_t nfill = static_cast<uint32_t>(fc);
+    uint32_t nfill = static_cast<uint32_t>(fc);
+    if (nfill > a.cap_fill) nfill = a.cap_fill;  // an overflow was latched
+    if (nfill == 0) return;
     const uint32_t nchunk = static_cast<uint32_t>(fc >> 32);
     R* xk = static_cast<R*>(a.x_keys);
     for (uint32_t ch = bid; ch < nchunk; ch += nblk) {
@@ -364,8 +366,9 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
     Ctl* c = a.ctl;
     const int p = level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
     reset_next_slot(c, q, nseg, bid);
+    if (nseg > a.cap_seg) nseg = a.cap_seg;  // an overflow was latched
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
     R* ws = lds.samp[wv];
 
@@ -789,7 +792,8 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     Ctl* c = a.ctl;
     const int p = a.level & 1;
     const int tid = threadIdx.x;
-    const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
+    uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
+    if (ntiles > a.cap_tile) ntiles = a.cap_tile;  // an overflow was latched
     // a launch may cover more workgroups than the level has tiles (a grid
     // fixed in advance); the surplus leaves before taking a ticket
     if (blockIdx.x >= ntiles || (c->error & ERR_OFFSETS)) return;
@@ -842,7 +846,8 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
     const int p = level & 1, q = p ^ 1;
     const int lane = lane_id();
     const bool cursor = !HV && a.claim != 0;
-    const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    if (nseg > a.cap_seg) nseg = a.cap_seg;  // an overflow was latched
     const int64_t T = a.tile_keys;
     const int64_t S = a.small_cut;
     // statistics of this thread's appends: equal keys, and keys / tiles the
@@ -986,10 +991,11 @@ __global__ __launch_bounds__(256) void k_complete(Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// Small-segment sort (the paper's Insertionsort stage, Section 2).
+// Comparison sort of one small segment, the fallback of the bucket sort
+// below for segments whose keys crowd into few buckets.
 //
-// A group of NTH threads (one wave, or a 256-thread workgroup) sorts one
-// segment of at most E*NTH keys: thread t holds items t*E .. t*E+E-1, sorts
+// A group of NTH threads sorts one segment of at most E*NTH keys: thread t
+// holds items t*E .. t*E+E-1, sorts
 // them with a bitonic network in registers (every merge of two sorted halves
 // starts with the mirror step, item x against x ^ (2^k - 1), after which all
 // compare-exchanges put the smaller item at the lower index), and the group
@@ -1169,127 +1175,341 @@ __device__ void merge_sort(It (&v)[E], int t, O* sk, uint32_t* si, int m) {
     }
 }
 
-// The small sort of one size class: a workgroup of max(NTH, 256) threads
-// holds max(NTH, 256)/NTH groups, each group sorts one segment of at most
-// E*NTH keys.
-template <int DT, class V, int E, int NTH>
+// LDS of the comparison sort (merge_sort) of one segment of at most E*NT
+// keys, the fallback of the bucket sort below: keys (padded layout), the
+// keys' indexes in the segment (pairs) and the staged payloads (pairs).
+template <int DT, class V, int E, int NT>
 struct SmallLds {
     using O = decltype(KeyT<DT>::ord(typename KeyT<DT>::raw()));
     static constexpr bool HV = !std::is_same<V, NoVal>::value;
-    static constexpr int WG = NTH > 256 ? NTH : 256;  // workgroup size
-    static constexpr int G = WG / NTH;                 // groups per workgroup
-    static constexpr int P = E * NTH;                  // items per group
-    static constexpr int PS = P + P / 16;              // padded LDS items per group (covers both pad rules)
-    O k[G * PS];
-    uint32_t i[HV ? G * PS : 1];
-    typename ValStore<V>::type v[HV ? G * P : 1];
-    unsigned long long done[G];  // keys sorted by each group (statistics)
+    static constexpr int P = E * NT;       // items
+    static constexpr int PS = P + P / 16;  // padded LDS items (covers both pad rules)
+    O k[PS];
+    uint32_t i[HV ? PS : 1];
+    typename ValStore<V>::type v[HV ? P : 1];
 };
 
-// The small sort of class `cls` as workgroup `bid` of `nblk`.
-template <int DT, class V, int E, int NTH>
-__device__ void small_body(const Args& a, int level, int cls, uint32_t bid, uint32_t nblk,
-                           SmallLds<DT, V, E, NTH>& lds) {
+// The comparison sort of one segment whose keys (order keys, padding ~0 at
+// positions >= m) sit in registers in striped order, item r of thread t at
+// position r*NT + t; pairs have staged their payloads in lds.v by position.
+// Writes the sorted segment (and payloads) to dst[0, m), dv[0, m).
+template <int DT, class V, int E, int NT>
+__device__ void compare_sort_segment(typename SmallLds<DT, V, E, NT>::O (&key)[E], int m,
+                                     SmallLds<DT, V, E, NT>& lds, typename KeyT<DT>::raw* dst,
+                                     typename ValStore<V>::type* dv) {
     using K = KeyT<DT>;
-    using R = typename K::raw;
-    using SL = SmallLds<DT, V, E, NTH>;
+    using SL = SmallLds<DT, V, E, NT>;
     using O = typename SL::O;
-    using VS = typename ValStore<V>::type;
     constexpr bool HV = SL::HV;
     using It = SItem<O, HV>;
-    constexpr int G = SL::G;
-    constexpr int P = SL::P;
-    constexpr int PS = SL::PS;
-    O* s_k = lds.k;
-    uint32_t* s_i = lds.i;
-    VS* s_v = lds.v;
-
-    Ctl* c = a.ctl;
-    const int p = level & 1;
-    const int tid = threadIdx.x;
-    const int grp = tid / NTH;
-    const int t = tid % NTH;
-    const uint32_t nsm = c->lc[p].smalls[cls];
-    R* xk = static_cast<R*>(a.x_keys);
-    VS* xv = static_cast<VS*>(a.x_vals);
-    // one region of cap_small items per class
-    const SmallItem* items = a.smalls[p] + static_cast<size_t>(cls) * a.cap_small;
-    O* sk = s_k + grp * PS;
-    uint32_t* si = HV ? s_i + grp * PS : s_i;
-    VS* sv = HV ? s_v + grp * P : s_v;
-    unsigned long long* s_done = lds.done;
-    unsigned long long my_keys = 0;
-
-    for (uint32_t base = bid * G; base < nsm; base += nblk * G) {
-        const uint32_t it = base + grp;
-        const bool have = it < nsm;
-        int64_t lo = 0;
-        int m = 0;
-        if (have) {
-            const SmallItem s = items[it];
-            lo = s.lo;
-            m = static_cast<int>(s.hi - s.lo);
-        }
-        const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
-        const VS* vsrc = static_cast<const VS*>(p ? a.y_vals : a.x_vals);
-        // striped (coalesced) load into LDS, padding with the largest key
+    O* sk = lds.k;
+    uint32_t* si = lds.i;
+    const int t = threadIdx.x;
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int x = r * NTH + t;
-            O key = static_cast<O>(~O(0));
-            if (x < m) {
-                key = K::ord(src[lo + x]);
-                if constexpr (HV) sv[x] = vsrc[lo + x];
-            }
-            sk[lds_slot<O>(x)] = key;
-            if constexpr (HV) si[lds_slot<O>(x)] = static_cast<uint32_t>(x);
-        }
-        __syncthreads();
-        It v[E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int x = t * E + r;
-            v[r].k = sk[lds_slot<O>(x)];
-            if constexpr (HV) v[r].i = si[lds_slot<O>(x)];
-        }
-        merge_sort<It, O, E, NTH>(v, t, sk, si, m);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int x = t * E + r;
-            sk[lds_slot<O>(x)] = v[r].k;
-            if constexpr (HV) si[lds_slot<O>(x)] = v[r].i;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int x = r * NTH + t;
-            if (x < m) {
-                xk[lo + x] = K::inv(sk[lds_slot<O>(x)]);
-                if constexpr (HV) xv[lo + x] = sv[si[lds_slot<O>(x)]];
-            }
-        }
-        my_keys += static_cast<unsigned long long>(m);
-        __syncthreads();
+    for (int r = 0; r < E; ++r) {
+        const int x = r * NT + t;
+        sk[lds_slot<O>(x)] = key[r];
+        if constexpr (HV) si[lds_slot<O>(x)] = static_cast<uint32_t>(x);
     }
-    // one statistics atomic per workgroup
-    if (t == 0) s_done[grp] = my_keys;
     __syncthreads();
-    if (tid == 0) {
-        unsigned long long sum = 0;
-        for (int g = 0; g < G; ++g) sum += s_done[g];
-        if (sum) atomicAdd(&c->small_keys, sum);
+    It v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = t * E + r;
+        v[r].k = sk[lds_slot<O>(x)];
+        if constexpr (HV) v[r].i = si[lds_slot<O>(x)];
+    }
+    merge_sort<It, O, E, NT>(v, t, sk, si, m);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = t * E + r;
+        sk[lds_slot<O>(x)] = v[r].k;
+        if constexpr (HV) si[lds_slot<O>(x)] = v[r].i;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = r * NT + t;
+        if (x < m) {
+            dst[x] = K::inv(sk[lds_slot<O>(x)]);
+            if constexpr (HV) dv[x] = lds.v[si[lds_slot<O>(x)]];
+        }
     }
 }
 
-// One launch sorts the segments of one size class.  Registers are capped for
-// six waves per SIMD (80 VGPRs, no spills for keys): the merges wait on LDS,
-// and more resident waves hide it (2^28 int32 keys: 2.8 instead of 3.2 ms).
-template <int DT, class V, int E, int NTH>
-__global__ __launch_bounds__(NTH > 256 ? NTH : 256, 6) void k_small(Args a, int cls) {
-    __shared__ SmallLds<DT, V, E, NTH> s_lds;
+// ---------------------------------------------------------------------------
+// Small-segment sort (the paper's Insertionsort stage, Section 2, and its
+// outlook on a better recursion stopper, Section 5).
+//
+// A segment that reaches the small sort is the key range between two
+// pivots, so its keys are confined to [mn, mx] and spread over few bits.
+// One workgroup of NT threads sorts one segment of m <= E*NT keys in LDS
+// with a bucket sort on the order keys:
+//   1. keys are loaded (coalesced, striped) into registers; mn and mx are
+//      reduced across the workgroup;
+//   2. bucket b(x) = (x - mn) >> s, with s chosen so that there are at most
+//      NB = 2^ceil(log2 m) buckets (about one key per bucket);
+//   3. bucket sizes are counted with LDS atomics (two 16-bit counters per
+//      word), turned into bucket starts by a workgroup scan, and every key is
+//      scattered to its bucket by an atomic increment of the bucket's cursor;
+//   4. if s = 0 every bucket holds one key value, so the keys are sorted
+//      (keys only); otherwise, and for pairs, every key's final rank is its
+//      bucket start plus the keys of its bucket that precede it -- smaller,
+//      or equal with a smaller tie-break (position for keys, the index in
+//      the segment for pairs, which makes the payload order deterministic:
+//      equal keys keep their input order).
+// A segment with a bucket of more than kBucketCap keys (skewed or heavily
+// duplicated keys) is sorted by the comparison sort instead (merge_sort).
+// The keys are exactly the segment's keys in ascending order either way.
+
+constexpr int kBucketCap = 32;
+
+template <int DT, class V, int NT, int SMAX>
+struct BucketLds {
+    static constexpr int E = SMAX / NT;
+    using SL = SmallLds<DT, V, E, NT>;
+    using O = typename SL::O;
+    SL s;                          // bucket arrays (s.k keys, s.i indexes) or the fallback's LDS
+    uint32_t hist[SMAX / 2];       // bucket counters, then cursors: 16 bits each, two per word
+    O red[2][NT / 64];             // per-wave min and max
+    uint32_t wsum[NT / 64];        // per-wave scan totals
+    uint32_t wmax[NT / 64];        // per-wave largest bucket
+    unsigned long long done;
+};
+
+template <class O>
+__device__ __forceinline__ O wave_min(O v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        O o;
+        if constexpr (sizeof(O) == 8) o = shfl_xor64(v, d);
+        else o = static_cast<O>(__shfl_xor(static_cast<int>(v), d, 64));
+        v = o < v ? o : v;
+    }
+    return v;
+}
+template <class O>
+__device__ __forceinline__ O wave_max(O v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        O o;
+        if constexpr (sizeof(O) == 8) o = shfl_xor64(v, d);
+        else o = static_cast<O>(__shfl_xor(static_cast<int>(v), d, 64));
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t half16(const uint32_t* h, uint32_t b) {
+    return (h[b >> 1] >> ((b & 1u) << 4)) & 0xffffu;
+}
+
+template <class O>
+__device__ __forceinline__ int bit_width(O x) {
+    if constexpr (sizeof(O) == 8) return x ? 64 - __clzll(static_cast<long long>(x)) : 0;
+    else return x ? 32 - __clz(static_cast<int>(x)) : 0;
+}
+
+// Sorts one segment [lo, lo + m) of buffer `src` (payloads `vsrc`) into the
+// caller's arrays at lo (all NT threads of the workgroup).
+template <int DT, class V, int NT, int SMAX>
+__device__ void bucket_sort_segment(const Args& a, int p, int64_t lo, int m, BucketLds<DT, V, NT, SMAX>& L) {
+    using K = KeyT<DT>;
+    using R = typename K::raw;
+    using BL = BucketLds<DT, V, NT, SMAX>;
+    using O = typename BL::O;
+    using VS = typename ValStore<V>::type;
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    constexpr int E = BL::E;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys) + lo;
+    const VS* vsrc = static_cast<const VS*>(p ? a.y_vals : a.x_vals) + lo;
+    R* xk = static_cast<R*>(a.x_keys) + lo;
+    VS* xv = static_cast<VS*>(a.x_vals) + lo;
+    O* B = L.s.k;
+    uint32_t* Bi = L.s.i;
+    VS* sv = L.s.v;
+    uint32_t* h = L.hist;
+
+    // 1. load; the key range
+    O key[E];
+    O mn = static_cast<O>(~O(0)), mx = 0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = r * NT + tid;
+        key[r] = static_cast<O>(~O(0));
+        if (x < m) {
+            key[r] = K::ord(src[x]);
+            if constexpr (HV) sv[x] = vsrc[x];
+            mn = key[r] < mn ? key[r] : mn;
+            mx = key[r] > mx ? key[r] : mx;
+        }
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (lane == 0) {
+        L.red[0][wv] = mn;
+        L.red[1][wv] = mx;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        mn = L.red[0][w] < mn ? L.red[0][w] : mn;
+        mx = L.red[1][w] > mx ? L.red[1][w] : mx;
+    }
+    const O range = mx - mn;
+    // buckets: NB = 2^hb >= m, shift s so that (range >> s) < NB
+    const int hb = m > 1 ? 32 - __clz(m - 1) : 1;
+    const int bits = bit_width(range);
+    const int s = bits > hb ? bits - hb : 0;
+    const uint32_t nbw = ((1u << hb) + 1u) >> 1;  // words of 16-bit counters
+    if (range == 0) {
+        // one key value: the segment is sorted as it stands
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = r * NT + tid;
+            if (x < m) {
+                xk[x] = K::inv(key[r]);
+                if constexpr (HV) xv[x] = sv[x];
+            }
+        }
+        return;
+    }
+    // 2. bucket sizes
+    for (uint32_t w = tid; w < nbw; w += NT) h[w] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = r * NT + tid;
+        if (x < m) {
+            const uint32_t b = static_cast<uint32_t>((key[r] - mn) >> s);
+            atomicAdd(&h[b >> 1], 1u << ((b & 1u) << 4));
+        }
+    }
+    __syncthreads();
+    // 3. bucket starts: each thread scans a run of consecutive words
+    const uint32_t per = (nbw + NT - 1) / NT;
+    const uint32_t w0 = tid * per;
+    uint32_t sum = 0, big = 0;
+    for (uint32_t w = w0; w < w0 + per && w < nbw; ++w) {
+        const uint32_t c = h[w];
+        const uint32_t c0 = c & 0xffffu, c1 = c >> 16;
+        sum += c0 + c1;
+        big = c0 > big ? c0 : big;
+        big = c1 > big ? c1 : big;
+    }
+    const uint32_t inc = static_cast<uint32_t>(wave_inclusive_sum(static_cast<uint64_t>(sum), opaque(lane)));
+    const uint32_t wbig = wave_max(big);
+    if (lane == 63) L.wsum[wv] = inc;
+    if (lane == 0) L.wmax[wv] = wbig;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    uint32_t maxc = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        run += w < wv ? L.wsum[w] : 0u;
+        maxc = L.wmax[w] > maxc ? L.wmax[w] : maxc;
+    }
+    const bool rank_step = s > 0 || HV;
+    if (rank_step && maxc > static_cast<uint32_t>(kBucketCap)) {
+        // a crowded bucket: sort this segment by comparisons instead
+        compare_sort_segment<DT, V, E, NT>(key, m, L.s, xk, xv);
+        return;
+    }
+    for (uint32_t w = w0; w < w0 + per && w < nbw; ++w) {
+        const uint32_t c = h[w];
+        const uint32_t s0 = run, s1 = run + (c & 0xffffu);
+        run = s1 + (c >> 16);
+        h[w] = s0 | (s1 << 16);
+    }
+    __syncthreads();
+    // 4. scatter into the buckets; afterwards each counter holds its bucket's end
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = r * NT + tid;
+        if (x < m) {
+            const uint32_t b = static_cast<uint32_t>((key[r] - mn) >> s);
+            const uint32_t sh = (b & 1u) << 4;
+            const uint32_t pos = (atomicAdd(&h[b >> 1], 1u << sh) >> sh) & 0xffffu;
+            B[pos] = key[r];
+            if constexpr (HV) Bi[pos] = static_cast<uint32_t>(x);
+        }
+    }
+    __syncthreads();
+    if (!rank_step) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = r * NT + tid;
+            if (x < m) xk[x] = K::inv(B[x]);
+        }
+        return;
+    }
+    // 5. final rank inside the bucket
+#pragma unroll 4
+    for (int r = 0; r < E; ++r) {
+        const int q = r * NT + tid;
+        if (q < m) {
+            const O o = B[q];
+            const uint32_t b = static_cast<uint32_t>((o - mn) >> s);
+            const int e = static_cast<int>(half16(h, b));
+            const int st = b ? static_cast<int>(half16(h, b - 1)) : 0;
+            const uint32_t tie = HV ? Bi[q] : static_cast<uint32_t>(q);
+            int rank = st;
+            for (int j = st; j < e; ++j) {
+                const O o2 = B[j];
+                const uint32_t t2 = HV ? Bi[j] : static_cast<uint32_t>(j);
+                rank += static_cast<int>((o2 < o) | ((o2 == o) & (t2 < tie)));
+            }
+            xk[rank] = K::inv(o);
+            if constexpr (HV) xv[rank] = sv[tie];
+        }
+    }
+}
+
+// The small sort of level `level` as workgroup `bid` of `nblk`: every
+// segment recorded for the level's small lists (all size classes, largest
+// class first, so that the long sorts start early), one per workgroup.
+template <int DT, class V, int NT, int SMAX>
+__device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
+                               BucketLds<DT, V, NT, SMAX>& L) {
+    Ctl* c = a.ctl;
+    const int p = level & 1;
+    uint32_t cnt[kSmallClasses];
+    uint32_t total = 0;
+#pragma unroll
+    for (int k = 0; k < kSmallClasses; ++k) {
+        // a count past the capacity means an overflow was latched; only the
+        // items that were written are read
+        cnt[k] = c->lc[p].smalls[k] < a.cap_small ? c->lc[p].smalls[k] : a.cap_small;
+        total += cnt[k];
+    }
+    unsigned long long my_keys = 0;
+    for (uint32_t it = bid; it < total; it += nblk) {
+        uint32_t r = it;
+        int cls = kSmallClasses - 1;
+        while (r >= cnt[cls]) {
+            r -= cnt[cls];
+            --cls;
+        }
+        const SmallItem s = a.smalls[p][static_cast<size_t>(cls) * a.cap_small + r];
+        const int m = static_cast<int>(s.hi - s.lo);
+        bucket_sort_segment<DT, V, NT, SMAX>(a, p, s.lo, m, L);
+        my_keys += static_cast<unsigned long long>(m);
+        __syncthreads();  // LDS is reused by the next segment
+    }
+    if (threadIdx.x == 0 && my_keys) atomicAdd(&c->small_keys, my_keys);
+}
+
+// One launch sorts every small segment of a level.  512-thread workgroups
+// are capped at 80 VGPRs, so that three of them fit a CU as their LDS does
+// (six waves per SIMD to hide the LDS latency).
+template <int DT, class V, int NT, int SMAX>
+__global__ __launch_bounds__(NT, NT >= 512 ? 6 : 3) void k_small(Args a) {
+    __shared__ BucketLds<DT, V, NT, SMAX> s_lds;
     if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
-    small_body<DT, V, E, NTH>(a, a.level, cls, blockIdx.x, gridDim.x, s_lds);
+    small_all_body<DT, V, NT, SMAX>(a, a.level, blockIdx.x, gridDim.x, s_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1386,26 +1606,9 @@ __device__ inline bool grid_sync_xcd(Ctl* c, uint32_t xcd, uint32_t my_n, uint32
 template <int DT, class V, int NT, int EPT, int SP>
 struct PersistLds {
     static constexpr size_t mx(size_t x, size_t y) { return x > y ? x : y; }
-    template <int E, int NTH>
-    static constexpr size_t small() {
-        return (NTH <= NT && E * NTH <= SP) ? sizeof(SmallLds<DT, V, E, NTH>) : 0;
-    }
     static constexpr size_t bytes =
-        mx(mx(sizeof(TileLds<DT, V, NT, EPT>), sizeof(PlanLds<DT, NT>)),
-           mx(mx(mx(small<1, 64>(), small<2, 64>()), mx(small<4, 64>(), small<8, 64>())),
-              mx(small<16, 64>(), mx(small<8, 256>(), small<16, 256>()))));
+        mx(mx(sizeof(TileLds<DT, V, NT, EPT>), sizeof(PlanLds<DT, NT>)), sizeof(BucketLds<DT, V, NT, SP>));
 };
-
-template <int DT, class V, int NT, int E, int NTH, int SP>
-__device__ __forceinline__ void persist_small(const Args& a, int level, uint32_t bid, uint32_t nblk,
-                                              unsigned char* raw) {
-    if constexpr (NTH <= NT && E * NTH <= SP) {
-        const int cls = small_class(static_cast<int64_t>(E) * NTH);
-        if (a.ctl->lc[level & 1].smalls[cls] == 0) return;
-        small_body<DT, V, E, NTH>(a, level, cls, bid, nblk, *reinterpret_cast<SmallLds<DT, V, E, NTH>*>(raw));
-        __syncthreads();
-    }
-}
 
 template <int DT, class V, int NT, int EPT, int SP>
 __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
@@ -1439,18 +1642,14 @@ __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
         const int p = L & 1;
         const unsigned long long sc = c->lc[p].segs;
         const uint32_t nseg = static_cast<uint32_t>(sc);
-        const uint32_t ntile = static_cast<uint32_t>(sc >> 32);
+        uint32_t ntile = static_cast<uint32_t>(sc >> 32);
+        if (ntile > a.cap_tile) ntile = a.cap_tile;  // an overflow was latched
         // (1) pivots and tile descriptors of level L; equal runs and small
         // segments of level L-1
         plan_body<DT, V, NT>(a, L, bid, nblk, *reinterpret_cast<PlanLds<DT, NT>*>(s_raw));
         __syncthreads();
-        persist_small<DT, V, NT, 1, 64, SP>(a, L, bid, nblk, s_raw);
-        persist_small<DT, V, NT, 2, 64, SP>(a, L, bid, nblk, s_raw);
-        persist_small<DT, V, NT, 4, 64, SP>(a, L, bid, nblk, s_raw);
-        persist_small<DT, V, NT, 8, 64, SP>(a, L, bid, nblk, s_raw);
-        persist_small<DT, V, NT, 16, 64, SP>(a, L, bid, nblk, s_raw);
-        persist_small<DT, V, NT, 8, 256, SP>(a, L, bid, nblk, s_raw);
-        persist_small<DT, V, NT, 16, 256, SP>(a, L, bid, nblk, s_raw);
+        small_all_body<DT, V, NT, SP>(a, L, bid, nblk, *reinterpret_cast<BucketLds<DT, V, NT, SP>*>(s_raw));
+        __syncthreads();
         if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
         if (nseg == 0) break;
         if (L >= level_cap) {
@@ -1529,24 +1728,6 @@ struct MultiFns<DT, NT, EPT, false> {
     static constexpr Fn sa() { return nullptr; }
 };
 
-template <int DT, class V, int E, int NTH>
-struct SmallLaunch {
-    static void run(const Args& a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_small<DT, V, E, NTH>), dim3(grid), dim3(NTH > 256 ? NTH : 256), 0, s, a,
-                           small_class(static_cast<int64_t>(E) * NTH));
-    }
-};
-
-// function pointer of a small-sort class, or nullptr without instantiating it
-template <int DT, class V, int E, int NTH, bool ON>
-struct SmallFn {
-    static constexpr void (*get())(const Args&, int, hipStream_t) { return &SmallLaunch<DT, V, E, NTH>::run; }
-};
-template <int DT, class V, int E, int NTH>
-struct SmallFn<DT, V, E, NTH, false> {
-    static constexpr void (*get())(const Args&, int, hipStream_t) { return nullptr; }
-};
-
 template <int DT, class V, int NT, int EPT, int SMAX>
 struct Launch {
     static constexpr int kPlanThreads = 256;
@@ -1558,6 +1739,12 @@ struct Launch {
     }
     static void complete(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_complete<V>), dim3(grid), dim3(256), 0, s, a);
+    }
+    // small sort: 16 keys per thread (8 for pairs of 2048 keys), at least
+    // 256 threads
+    static constexpr int kSmallThreads = SMAX / 16 < 256 ? 256 : SMAX / 16;
+    static void small(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_small<DT, V, kSmallThreads, SMAX>), dim3(grid), dim3(kSmallThreads), 0, s, a);
     }
     static void map(const Args& a, int grid, hipStream_t s) { launch_map(a, grid, s); }
     // persistent mode: small segments up to 4096 keys (the classes whose
@@ -1584,13 +1771,7 @@ struct Launch {
             SMAX,
             &plan,
             &map,
-            {&SmallLaunch<DT, V, 1, 64>::run, &SmallLaunch<DT, V, 2, 64>::run,
-             &SmallLaunch<DT, V, 4, 64>::run, &SmallLaunch<DT, V, 8, 64>::run,
-             SmallFn<DT, V, 16, 64, (SMAX >= 1024)>::get(),
-             SmallFn<DT, V, 8, 256, (SMAX >= 2048)>::get(),
-             SmallFn<DT, V, 16, 256, (SMAX >= 4096)>::get(),
-             SmallFn<DT, V, 16, 512, (SMAX >= 8192)>::get()},
-            {4, 4, 4, 4, 4, 1, 1, 1},
+            &small,
             &tile,
             &complete,
             MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::p(),

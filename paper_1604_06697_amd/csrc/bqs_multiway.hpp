@@ -69,8 +69,9 @@ __global__ __launch_bounds__(NT) void k_plan_multi(Args a) {
     if (c->error & ERR_OFFSETS) return;
     const int p = a.level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
     reset_next_slot(c, q, nseg, blockIdx.x);
+    if (nseg > a.cap_seg) nseg = a.cap_seg;  // an overflow was latched
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
     R* ws = s_samp[wv];
     R* so = s_sorted[wv];
@@ -154,7 +155,8 @@ __global__ __launch_bounds__(NT) void k_mcount(Args a) {
     __shared__ uint16_t s_c[kBStride][NT];
     const Ctl* c = a.ctl;
     const int p = a.level & 1;
-    const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
+    uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
+    if (ntiles > a.cap_tile) ntiles = a.cap_tile;  // an overflow was latched
     const uint32_t tile = blockIdx.x;
     if (tile >= ntiles || (c->error & ERR_OFFSETS)) return;
     const int tid = threadIdx.x;
@@ -206,7 +208,8 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
     if (c->error & ERR_OFFSETS) return;
     const int p = a.level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    if (nseg > a.cap_seg) nseg = a.cap_seg;  // an overflow was latched
     const int64_t T = a.tile_keys;
     const int64_t S = a.small_cut;
     unsigned long long fill_keys = 0, next_keys = 0, next_tiles = 0;
@@ -334,7 +337,8 @@ __global__ __launch_bounds__(NT) void k_mscatter(Args a) {
     __shared__ uint32_t s_cnt[kBStride], s_start[kBStride], s_off[kBStride];
     const Ctl* c = a.ctl;
     const int p = a.level & 1;
-    const uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
+    uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
+    if (ntiles > a.cap_tile) ntiles = a.cap_tile;  // an overflow was latched
     const uint32_t tile = blockIdx.x;
     if (tile >= ntiles || (c->error & ERR_OFFSETS)) return;
     const int tid = threadIdx.x, lane = tid & 63;
