@@ -16,13 +16,18 @@
  *     owned by the caller.  The library never allocates or frees device
  *     memory; it only owns host-side state inside a context.
  *   - Calls enqueue work on the context's HIP stream (default: the null
- *     stream).  The current implementation waits on that stream between
- *     recursion levels, so a call returns after the sort has finished on
- *     the device.
+ *     stream) and return without waiting for it (default mode,
+ *     BQS_MODE_ASYNC; BQS_MODE_LEVELS instead waits between recursion
+ *     levels and returns when the sort is done).  Results are valid once
+ *     the stream has passed the call, as for any kernel on that stream; the
+ *     caller keeps keys, payloads, offsets and the workspace alive and
+ *     unmodified until then.
  *   - Argument errors are reported at once and nothing is enqueued.
  *     Device-detected errors (a work list overflowing its capacity, a
- *     malformed offsets array) are latched in the context and returned by
- *     the call that detects them and by bqs_ctx_sync_status().
+ *     malformed offsets array, a NaN key in check mode, a device-side wait
+ *     that gave up) are latched in the context when the call has completed
+ *     and are returned by bqs_ctx_sync_status() (and, in BQS_MODE_LEVELS,
+ *     by the call itself).
  *   - Keys are 1-D and contiguous.  Integer keys use their usual order;
  *     float keys use IEEE-754 totalOrder restricted to non-NaN values, so
  *     -0.0 sorts before +0.0.  NaN keys violate the precondition (their
@@ -57,7 +62,7 @@ typedef enum {
     BQS_EDTYPE = 2,     /* unsupported key dtype or payload width                          */
     BQS_ENOMEM = 3,     /* host-side allocation inside the context failed                  */
     BQS_EHIP = 4,       /* a HIP runtime call failed                                        */
-    BQS_ENAN = 5,       /* reserved: NaN detected (not checked by the current kernels)      */
+    BQS_ENAN = 5,       /* a floating-point key is NaN (only with BQS_PARAM_CHECK_NAN = 1)   */
     BQS_EOVERFLOW = 6   /* a device work list or the level cap was exceeded                 */
 } bqs_status;
 
@@ -90,10 +95,21 @@ typedef enum {
     BQS_PARAM_GRID = 6,         /* workgroups of the persistent kernel (0 = all that can be
                                    resident at once)                                            */
     BQS_PARAM_PROFILE = 7,      /* 1: count cycles and look-back rounds inside partition tiles */
-    BQS_PARAM_MODE = 8,         /* BQS_MODE_LEVELS (default) or BQS_MODE_PERSISTENT              */
+    BQS_PARAM_MODE = 8,         /* BQS_MODE_ASYNC (default), BQS_MODE_LEVELS or
+                                   BQS_MODE_PERSISTENT                                          */
     BQS_PARAM_GRAPH = 9,        /* 1: capture the launches of a call into a HIP graph and replay
                                    it for later calls with the same buffers, sizes and parameters
-                                   (see "Graph mode" below)                                     */
+                                   (BQS_MODE_ASYNC only; see "Graph mode" below)               */
+    BQS_PARAM_ENQUEUE_LEVELS = 14, /* BQS_MODE_ASYNC: recursion levels a call enqueues before its
+                                   single-workgroup tail launch (0, the default: as many as the
+                                   last completed call of the same shape needed plus one, or an
+                                   estimate).  The result is the same for any value; small
+                                   values leave more of the recursion to the tail              */
+    BQS_PARAM_CHECK_NAN = 13,   /* 1: float keys are checked for NaN (one extra read of the keys)
+                                   before the sort; a NaN is reported as BQS_ENAN and the keys
+                                   are then in an unspecified order.  The sort's precondition
+                                   (a totally ordered key set, Introduction) excludes NaN; 0
+                                   (default) does not check                                     */
     BQS_PARAM_LOOKBACK = 10,    /* how a partition tile claims its output ranges.  0 (default):
                                    keys-only sorts move the segment's two cursors with one atomic
                                    add per tile (the paper's cursors l and r, Algorithm 3), so
@@ -117,49 +133,59 @@ typedef enum {
 } bqs_param;
 
 /* Execution modes (BQS_PARAM_MODE).
- *   LEVELS    : one partition launch per recursion level; the host reads the
- *               next level's size between levels (per-level statistics).
+ *   ASYNC     : (default) a call enqueues every launch of the sort and
+ *               returns.  Each recursion level is one partition launch whose
+ *               grid covers the most tiles the level can hold; the kernels
+ *               read the level's actual counts on the device.  The call
+ *               enqueues as many levels as the last call of the same shape
+ *               needed (plus one), or an estimate for a new shape, then one
+ *               single-workgroup launch that finishes any recursion left
+ *               over, so every input is sorted whatever its depth.  The
+ *               context's statistics and latched status are updated when
+ *               the call has completed on the device.
+ *   LEVELS    : host-driven: the host reads the next level's size between
+ *               levels and sizes every launch exactly; the call returns when
+ *               the sort is done, with its status.
  *   PERSISTENT: every level in one cooperative launch (Quicksort's main
  *               loop, Algorithm 1, run on the device): the workgroups that
  *               fit on the GPU at once drain each level's device-resident
  *               lists -- pivots, equal runs and small segments, tile
  *               descriptors, partition tiles, segment completion -- with a
  *               grid-wide barrier between steps, and the loop ends on the
- *               device when no segment is left to partition.  The host waits
- *               once per call.  The small-sort cutoff is clamped to 4096
+ *               device when no segment is left to partition.  Asynchronous
+ *               like ASYNC.  The small-sort cutoff is clamped to 4096
  *               keys.  BQS_PARAM_GRAPH does not apply (one launch already);
  *               BQS_PARAM_MULTIWAY = 1 returns BQS_EINVAL; per-level
  *               statistics are not kept.  A barrier that waits more than
  *               about a second (the GPU cannot hold the whole grid at once)
- *               ends the launch and the call returns BQS_EHIP.  Results are
- *               identical to LEVELS.  Measured side effect: once a process
- *               has made a cooperative launch, its later kernels on several
- *               streams overlap less (the serving loop's capacity dropped
- *               from 18 to 11 Gkeys/s), so a process that batches work on
- *               many streams should not mix in this mode. */
-typedef enum { BQS_MODE_LEVELS = 0, BQS_MODE_PERSISTENT = 2 } bqs_mode;
+ *               ends the launch and BQS_EHIP is latched.  Results are
+ *               identical to the other modes.  Measured side effect: once a
+ *               process has made a cooperative launch, its later kernels on
+ *               several streams overlap less (the serving loop's capacity
+ *               dropped from 18 to 11 Gkeys/s), so a process that batches
+ *               work on many streams should not mix in this mode. */
+typedef enum { BQS_MODE_ASYNC = 0, BQS_MODE_LEVELS = 1, BQS_MODE_PERSISTENT = 2 } bqs_mode;
 
-/* Graph mode (BQS_PARAM_GRAPH = 1).  The first call with a given set of
- * buffers (keys, vals, offsets, workspace), sizes and parameters sorts with
- * the host-driven level loop and then captures that call's launches (one
- * level more than it needed) into a HIP graph held by the context.  Later
- * calls with the same set replay the graph with one hipGraphLaunch and one
- * status read; if an input needs more levels than the graph holds, the
- * host-driven loop finishes it.  Results are identical to the default mode.
- * The graph reads the buffers' contents at replay time, so callers refill
- * the same buffers between calls.  Per-level statistics (bqs_ctx_get_level)
- * and kernel timings are not kept for replayed levels.  Changing any
+/* Graph mode (BQS_PARAM_GRAPH = 1, BQS_MODE_ASYNC).  The first call with a
+ * given set of buffers (keys, vals, offsets, workspace), sizes and
+ * parameters captures the call's launch sequence into a HIP graph held by
+ * the context and launches it; later calls with the same set replay it with
+ * one hipGraphLaunch.  When a completed call shows that the shape needs a
+ * different depth than the graph holds, the next call captures it again.
+ * Results are identical to the default mode.  The graph reads the buffers'
+ * contents at replay time, so callers refill the same buffers between
+ * calls.  Kernel timings are not kept for replayed calls.  Changing any
  * parameter drops the graph.  The graph is recorded on a stream the context
  * owns (default priority) and replayed on the context's stream. */
 
 typedef struct {
-    int64_t levels;             /* partition passes executed by the last call                  */
+    int64_t levels;             /* levels that partitioned at least one segment               */
     int64_t partitioned_keys;   /* sum of segment sizes over all partition passes              */
     int64_t small_sorted_keys;  /* keys finished by the in-LDS small sort                       */
     int64_t filled_keys;        /* keys equal to a pivot, written by the fill step             */
     int64_t tiles;              /* partition tiles processed                                    */
     double partition_ms;        /* summed partition-kernel time (BQS_PARAM_TIMING only)         */
-    int64_t partition_launches;
+    int64_t partition_launches; /* partition launches enqueued (levels, plus spare levels)     */
     double small_ms;            /* summed small-sort kernel time (BQS_PARAM_TIMING = 1 only)    */
     int64_t small_launches;
     double plan_ms;             /* summed pivot, fill, map and completion kernel time          
@@ -198,14 +224,16 @@ bqs_status bqs_ctx_set_workspace(bqs_ctx* ctx, void* dev_ptr, size_t bytes);
 bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value);
 int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param);
 
-/* Statistics of the most recent successful call on this context. */
-bqs_status bqs_ctx_get_stats(const bqs_ctx* ctx, bqs_stats* out);
+/* Statistics of the most recent call on this context; waits until the
+ * calls it has enqueued have completed on the device. */
+bqs_status bqs_ctx_get_stats(bqs_ctx* ctx, bqs_stats* out);
 
-/* Per-level statistics of the most recent call: keys partitioned by level
- * `level` (0-based) and, with BQS_PARAM_TIMING, that level's partition
- * kernel time in ms.  Either output pointer may be NULL.  Returns
- * BQS_EINVAL for a level the call did not run. */
-bqs_status bqs_ctx_get_level(const bqs_ctx* ctx, int level, int64_t* keys, double* partition_ms);
+/* Per-level statistics of the most recent call (waits like
+ * bqs_ctx_get_stats): keys partitioned by level `level` (0-based; levels
+ * past 127 are summed into level 127) and, with BQS_PARAM_TIMING, that
+ * level's partition kernel time in ms.  Either output pointer may be NULL.
+ * Returns BQS_EINVAL for a level the call did not run. */
+bqs_status bqs_ctx_get_level(bqs_ctx* ctx, int level, int64_t* keys, double* partition_ms);
 
 /* Workspace needed to sort n_total keys of `key` type with `val_bytes`-byte
  * payloads (0 for keys only) split into k_segments segments (1 for a single
@@ -222,17 +250,24 @@ size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, i
  * 2^31 keys. */
 bqs_status bqs_sort(void* keys, int64_t n, bqs_dtype dtype, bqs_ctx* ctx);
 
-/* Sorts (keys[i], vals[i]) records by key: the payload moves with its key.
- * vals: device pointer to n payloads of val_bytes (4 or 8) bytes each;
- * keys and vals must not overlap each other or the workspace. */
+/* Sorts (keys[i], vals[i]) records by key: the payload moves with its key
+ * (the paper's records compared by a key field, Section 4, experimental
+ * setup; the partition moves whole elements, Algorithm 3).  vals: device
+ * pointer to n payloads of val_bytes (4 or 8) bytes each; keys and vals
+ * must not overlap each other or the workspace.  Errors as for bqs_sort;
+ * val_bytes other than 4 or 8 -> BQS_EDTYPE. */
 bqs_status bqs_sort_pairs(void* keys, void* vals, int64_t n, bqs_dtype key, int32_t val_bytes,
                           bqs_ctx* ctx);
 
 /* Sorts k independent segments keys[offsets[i] .. offsets[i+1]) in one
- * batched launch sequence.  offsets: device pointer to k+1 int64 values,
- * offsets[0] = 0, non-decreasing, offsets[k] = n_total (the caller passes
- * n_total so no device read-back is needed to size the work).  A malformed
- * offsets array is detected on the device and reported as BQS_EINVAL. */
+ * batched launch sequence: the problem statement (Introduction) applied to
+ * each segment, the segments entering the recursion as level 0's list
+ * (Algorithm 1's stack seeded with k ranges).  offsets: device pointer to
+ * k+1 int64 values, offsets[0] = 0, non-decreasing, offsets[k] = n_total
+ * (the caller passes n_total so no device read-back is needed to size the
+ * work); each segment holds fewer than 2^31 keys.  A malformed offsets
+ * array is detected on the device; nothing is sorted and BQS_EINVAL is
+ * latched. */
 bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int64_t n_total,
                              bqs_dtype dtype, bqs_ctx* ctx);
 
@@ -259,7 +294,10 @@ typedef enum { BQS_RECORD_VECTOR = 1, BQS_RECORD_RECORD = 2 } bqs_record;
 size_t bqs_records_workspace_bytes(const bqs_ctx* ctx, int64_t n, int kind);
 bqs_status bqs_sort_records(const void* in, void* out, int64_t n, int kind, bqs_ctx* ctx);
 
-/* Synchronises the context's stream and returns the latched device status. */
+/* Waits until every call enqueued on this context has completed (and
+ * synchronises the context's stream), then returns the first error latched
+ * since the previous bqs_ctx_sync_status() -- a device-detected error of a
+ * call, or an error an asynchronous call returned -- and clears it. */
 bqs_status bqs_ctx_sync_status(bqs_ctx* ctx);
 
 /* Static, human-readable name of a status code. */

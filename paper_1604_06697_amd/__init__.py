@@ -8,6 +8,11 @@ the stream.  The three entry points mirror the C ABI in include/bqs.h:
     sort_pairs(keys, vals)     -> records sorted by key, payload follows key
     sort_segments(keys, offs)  -> every segment keys[offs[i]:offs[i+1]] sorted
 
+Calls are asynchronous, like any kernel on PyTorch's current stream: they
+return once the sort is enqueued.  ``Context.synchronize()`` waits for the
+context's calls and raises ``BqsError`` for an error the device detected
+(a malformed offsets array, a NaN key in check mode, ...).
+
 The library must be built (``python -m paper_1604_06697_amd.build`` or
 ``__graft_entry__.build()``); importing fails loudly when it is missing.
 """
@@ -50,8 +55,10 @@ PARAM_GRAPH = 9
 PARAM_LOOKBACK = 10
 PARAM_MULTIWAY = 11
 PARAM_PIVOT_SKEW = 12
+PARAM_CHECK_NAN = 13
+PARAM_ENQUEUE_LEVELS = 14
 RECORD_VECTOR, RECORD_RECORD = 1, 2
-MODE_LEVELS, MODE_PERSISTENT = 0, 2
+MODE_ASYNC, MODE_LEVELS, MODE_PERSISTENT = 0, 1, 2
 
 _TORCH_DTYPES = {
     torch.int32: I32,
@@ -230,6 +237,8 @@ class Context:
         "lookback": PARAM_LOOKBACK,
         "multiway": PARAM_MULTIWAY,
         "pivot_skew": PARAM_PIVOT_SKEW,
+        "check_nan": PARAM_CHECK_NAN,
+        "enqueue_levels": PARAM_ENQUEUE_LEVELS,
     }
 
     def set_param(self, name: str, value: int):
@@ -237,6 +246,11 @@ class Context:
 
     def get_param(self, name: str) -> int:
         return int(lib.bqs_ctx_get_param(self._h, self._NAMES[name]))
+
+    def synchronize(self):
+        """Waits for every call enqueued on this context; raises BqsError for
+        the first error the device latched since the last synchronize()."""
+        _check(lib.bqs_ctx_sync_status(self._h), "bqs_ctx_sync_status")
 
     def stats(self) -> dict:
         s = Stats()
@@ -375,6 +389,10 @@ def default_context() -> Context:
     if _default is None:
         _default = Context()
     return _default
+
+
+def synchronize(ctx: Context | None = None):
+    (ctx or default_context()).synchronize()
 
 
 def sort(keys: torch.Tensor, ctx: Context | None = None, key_type=None) -> torch.Tensor:

@@ -1,20 +1,32 @@
 // Host runtime behind include/bqs.h: argument checks, workspace layout,
-// kernel selection and the level loop that drives the partition passes.
+// kernel selection and the drivers of the recursion levels.
 //
 // The Quicksort main loop of the paper (Algorithm 1 with an explicit stack,
-// Section 2) becomes a breadth-first loop over recursion levels: all
+// Section 2) becomes a breadth-first sequence of recursion levels: all
 // segments of one level are partitioned by one launch, their children form
 // the next level's list on the device.  Segments of at most small_cut keys
 // leave the loop and are sorted in LDS; runs of keys equal to a pivot leave
 // it as well (the pivot is excluded from the recursion, Section 2).
+//
+// Default (asynchronous) mode: a call enqueues the levels with grids sized
+// from device-side counts -- each kernel reads its level's counts from the
+// control block and surplus workgroups leave at once -- for as many levels
+// as the input is expected to need, then one single-workgroup launch that
+// finishes whatever recursion is left, then a copy of the control block's
+// counters to pinned host memory and an event.  Nothing waits: the call
+// returns once the work is enqueued, and the counters are read when the
+// event has passed (statistics, latched errors, the depth the next call of
+// the same shape enqueues).
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstddef>
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -25,27 +37,39 @@ namespace bqs {
 
 // ---------------------------------------------------------------- set-up --
 
-__global__ void k_init_single(Args a) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    Ctl* c = a.ctl;
-    for (int s = 0; s < 2; ++s) {
-        c->lc[s].segs = 0;
-        c->lc[s].fills = 0;
-        for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
-        c->lc[s].tile_next = 0;
-        c->lc[s].pad = 0;
-        c->lc[s].keys = 0;
-    }
-    c->error = 0;
-    c->levels = 0;
-    c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
-    for (int i = 0; i < 8; ++i) c->prof[i] = 0;
-    c->bar_arrive = 0;
-    c->bar_gen = 0;
-    for (int x = 0; x < kMaxXcd; ++x) {
+// Clears the control block (workgroup of 64 threads).
+__device__ void clear_ctl(Ctl* c) {
+    const int t = threadIdx.x;
+    for (int i = t; i < kLevelStats; i += 64) c->level_keys[i] = 0;
+    for (int x = t; x < kMaxXcd; x += 64) {
         c->xcd_arrive[x][0] = 0;
         c->xcd_n[x] = 0;
     }
+    if (t == 0) {
+        for (int s = 0; s < 2; ++s) {
+            c->lc[s].segs = 0;
+            c->lc[s].fills = 0;
+            for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
+            c->lc[s].tile_next = 0;
+            c->lc[s].pad = 0;
+            c->lc[s].keys = 0;
+        }
+        c->error = 0;
+        c->levels = 0;
+        c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
+        for (int i = 0; i < 8; ++i) c->prof[i] = 0;
+        c->bar_arrive = 0;
+        c->bar_gen = 0;
+    }
+}
+
+// Single array: the whole array is level 0's only segment (or one small
+// segment).
+__global__ __launch_bounds__(64) void k_init_single(Args a) {
+    Ctl* c = a.ctl;
+    clear_ctl(c);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const int64_t n = a.n;
     if (n > a.small_cut) {
         const int64_t T = a.tile_keys;
@@ -59,6 +83,7 @@ __global__ void k_init_single(Args a) {
         c->lc[0].segs = (static_cast<unsigned long long>(nt) << 32) | 1ull;
         c->part_keys = static_cast<unsigned long long>(n);
         c->lc[0].keys = static_cast<unsigned long long>(n);
+        c->level_keys[0] = static_cast<unsigned long long>(n);
         c->tiles = nt;
     } else if (n >= 2) {
         const int cls = small_class(n);
@@ -67,28 +92,7 @@ __global__ void k_init_single(Args a) {
     }
 }
 
-__global__ void k_zero_ctl(Args a) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    Ctl* c = a.ctl;
-    for (int s = 0; s < 2; ++s) {
-        c->lc[s].segs = 0;
-        c->lc[s].fills = 0;
-        for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
-        c->lc[s].tile_next = 0;
-        c->lc[s].pad = 0;
-        c->lc[s].keys = 0;
-    }
-    c->error = 0;
-    c->levels = 0;
-    c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
-    for (int i = 0; i < 8; ++i) c->prof[i] = 0;
-    c->bar_arrive = 0;
-    c->bar_gen = 0;
-    for (int x = 0; x < kMaxXcd; ++x) {
-        c->xcd_arrive[x][0] = 0;
-        c->xcd_n[x] = 0;
-    }
-}
+__global__ __launch_bounds__(64) void k_zero_ctl(Args a) { clear_ctl(a.ctl); }
 
 // One thread per segment: validate the offsets, then route the segment to
 // the level-0 partition list or straight to the small sort.
@@ -135,6 +139,7 @@ __global__ __launch_bounds__(256) void k_init_segments(Args a) {
     if (threadIdx.x == 0 && s_keys) {
         atomicAdd(&c->part_keys, s_keys);
         atomicAdd(&c->lc[0].keys, s_keys);
+        atomicAdd(&c->level_keys[0], s_keys);
         atomicAdd(&c->tiles, s_tiles);
     }
 }
@@ -145,6 +150,24 @@ __global__ __launch_bounds__(256) void k_init_segments(Args a) {
 __global__ __launch_bounds__(256) void k_map(Args a) {
     if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
     map_tiles(a, a.level, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+// Check mode: latches ERR_NAN if any floating-point key is a NaN (exponent
+// all ones, fraction not zero).  `wide`: 8-byte keys.  Runs after the init
+// kernel has cleared the error word and before any level, and only reads.
+__global__ __launch_bounds__(256) void k_check_nan(const void* keys, int64_t n, int wide, Ctl* c) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    bool nan = false;
+    if (wide) {
+        const uint64_t* k = static_cast<const uint64_t*>(keys);
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+            nan |= (k[i] & 0x7fffffffffffffffull) > 0x7ff0000000000000ull;
+    } else {
+        const uint32_t* k = static_cast<const uint32_t*>(keys);
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+            nan |= (k[i] & 0x7fffffffu) > 0x7f800000u;
+    }
+    if (__ballot(nan) && (threadIdx.x & 63) == 0) atomicOr(&c->error, ERR_NAN);
 }
 
 // ------------------------------------------------------------- records --
@@ -273,11 +296,13 @@ struct bqs_ctx {
     int64_t ept = 0;
     int64_t grid = 0;
     int64_t profile = 0;
-    int64_t mode = BQS_MODE_LEVELS;
+    int64_t mode = BQS_MODE_ASYNC;
     int64_t graph = 0;
-    int64_t lookback = 0;  // 1: keys-only tiles also claim by decoupled look-back
-    int64_t multiway = 0;  // 1: keys-only levels split around up to 15 splitters
-    // graph mode: the captured launch sequence and the call it belongs to
+    int64_t lookback = 0;   // 1: keys-only tiles also claim by decoupled look-back
+    int64_t multiway = 0;   // 1: keys-only levels split around up to 15 splitters
+    int64_t check_nan = 0;  // 1: floating-point keys are checked for NaN first
+    int64_t enqueue_levels = 0;  // > 0: levels enqueued before the tail launch
+    // graph mode: the captured launch sequence and the call shape it belongs to
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph_obj = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -285,20 +310,37 @@ struct bqs_ctx {
     int glevels = 0;
     int64_t persist_grid = 0;  // resident workgroups of the persistent kernel (cached per table)
     const void* persist_ops = nullptr;
+    // results of the most recent call that has completed
     bqs_stats stats{};
-    bqs_status latched = BQS_OK;
+    std::vector<int64_t> level_keys;
+    std::vector<double> level_ms;
+    bqs_status latched = BQS_OK;  // first device-detected error since the last bqs_ctx_sync_status
+    // host-driven mode: control block read back between levels
     bqs::Ctl* pinned = nullptr;
-    // timing: event pairs recorded around launches, resolved at the next
-    // host synchronisation so that timing adds no wait of its own
+    // calls in flight: the copy of their control block, the event that
+    // follows it, and what the host knows of the call
+    struct Done {
+        bqs::Ctl* slot;
+        hipEvent_t ev;
+        uint64_t call;
+        std::vector<uint64_t> shape;
+        bqs_stats host;  // fields the host sets (tile size, cutoff, launches)
+    };
+    std::deque<Done> inflight;
+    std::vector<bqs::Ctl*> free_slots;
+    uint64_t calls = 0;
+    // levels that calls of a given shape partitioned (from completed calls)
+    std::map<std::vector<uint64_t>, int> seen_levels;
+    // timing: event pairs recorded around launches, resolved when their call
+    // has completed
     std::vector<hipEvent_t> ev_pool;
     struct Pending {
         hipEvent_t a, b;
-        int kind;   // 0 plan, 1 small, 2 partition
+        int kind;  // 0 plan, 1 small, 2 partition
         int level;
+        uint64_t call;
     };
     std::vector<Pending> pending;
-    std::vector<int64_t> level_keys;
-    std::vector<double> level_ms;
 };
 
 using namespace bqs;
@@ -342,24 +384,9 @@ bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
 
 bqs_status hip_ok(hipError_t e) { return e == hipSuccess ? BQS_OK : BQS_EHIP; }
 
-bqs_status ensure_device_state(bqs_ctx* ctx) {
-    if (!ctx->pinned) {
-        void* p = nullptr;
-        if (hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return BQS_EHIP;
-        ctx->pinned = static_cast<Ctl*>(p);
-    }
-    return BQS_OK;
-}
-
-// Copies the device control block to pinned host memory and waits.
-bqs_status read_ctl(bqs_ctx* ctx, const Ctl* dev) {
-    // the host reads the counters and the status; the barrier lines of the
-    // persistent mode (the last ~5 KB) stay on the device
-    if (hipMemcpyAsync(ctx->pinned, dev, offsetof(Ctl, bar_arrive), hipMemcpyDeviceToHost, ctx->stream) !=
-        hipSuccess)
-        return BQS_EHIP;
-    return hip_ok(hipStreamSynchronize(ctx->stream));
-}
+// Bytes of the control block the host reads: counters, status and per-level
+// statistics; the barrier lines of the persistent mode stay on the device.
+constexpr size_t kCtlHostBytes = offsetof(Ctl, bar_arrive);
 
 hipEvent_t take_event(bqs_ctx* ctx) {
     if (!ctx->ev_pool.empty()) {
@@ -372,12 +399,14 @@ hipEvent_t take_event(bqs_ctx* ctx) {
     return e;
 }
 
+// Event pairs around launches of call `call`.
 struct Timer {
     bqs_ctx* ctx;
     bool on;           // partition passes are timed
-    bool all = false;  // every other launch too
+    bool all;          // every other launch too
+    uint64_t call;
+    hipStream_t s;
     hipEvent_t a = nullptr;
-    // other launches (plan, small sorts, completion): timed with all only
     void start_aux() {
         if (all) start();
     }
@@ -387,38 +416,49 @@ struct Timer {
     void start() {
         if (!on) return;
         a = take_event(ctx);
-        if (a) hipEventRecord(a, ctx->stream);
+        if (a && hipEventRecord(a, s) != hipSuccess) {
+            ctx->ev_pool.push_back(a);
+            a = nullptr;
+        }
     }
     void stop(int kind, int level) {
         if (!on || !a) return;
         hipEvent_t b = take_event(ctx);
-        if (!b) return;
-        hipEventRecord(b, ctx->stream);
-        ctx->pending.push_back({a, b, kind, level});
-        a = nullptr;
-    }
-    // after a stream synchronisation: all recorded events are complete
-    void resolve(bqs_stats& st) {
-        for (auto& p : ctx->pending) {
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, p.a, p.b);
-            if (p.kind == 0) st.plan_ms += ms;
-            else if (p.kind == 1) st.small_ms += ms;
-            else {
-                st.partition_ms += ms;
-                if (static_cast<size_t>(p.level) < ctx->level_ms.size()) ctx->level_ms[p.level] += ms;
-            }
-            ctx->ev_pool.push_back(p.a);
-            ctx->ev_pool.push_back(p.b);
+        if (!b || hipEventRecord(b, s) != hipSuccess) {
+            ctx->ev_pool.push_back(a);
+            if (b) ctx->ev_pool.push_back(b);
+            a = nullptr;
+            return;
         }
-        ctx->pending.clear();
+        ctx->pending.push_back({a, b, kind, level, call});
+        a = nullptr;
     }
 };
 
-int clamp_grid(uint64_t want, int64_t cap) {
-    if (want < 1) want = 1;
-    if (want > static_cast<uint64_t>(cap)) want = static_cast<uint64_t>(cap);
-    return static_cast<int>(want);
+// Adds the timings of call `call` (all of its events have completed) to
+// `st` and the per-level times.
+void resolve_events(bqs_ctx* ctx, uint64_t call, bqs_stats& st, std::vector<double>& level_ms) {
+    std::vector<bqs_ctx::Pending> keep;
+    for (auto& p : ctx->pending) {
+        if (p.call != call) {
+            keep.push_back(p);
+            continue;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) ms = 0.f;
+        if (p.kind == 0) st.plan_ms += ms;
+        else if (p.kind == 1) st.small_ms += ms;
+        else {
+            st.partition_ms += ms;
+            if (p.level >= 0) {
+                if (level_ms.size() <= static_cast<size_t>(p.level)) level_ms.resize(p.level + 1, 0.0);
+                level_ms[p.level] += ms;
+            }
+        }
+        ctx->ev_pool.push_back(p.a);
+        ctx->ev_pool.push_back(p.b);
+    }
+    ctx->pending.swap(keep);
 }
 
 void fill_stats(bqs_stats& stats, const Ctl& c) {
@@ -435,25 +475,305 @@ void fill_stats(bqs_stats& stats, const Ctl& c) {
     stats.prof_load_cycles = static_cast<double>(c.prof[5]);
 }
 
-bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented);
-void drop_graph(bqs_ctx* ctx);
+void latch(bqs_ctx* ctx, bqs_status st) {
+    if (st != BQS_OK && ctx->latched == BQS_OK) ctx->latched = st;
+}
 
-// Levels L0, L0+1, ... driven from the host: each level's counts are read
-// back before its launches are sized.  `cur` holds the lists of level L0.
-bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur, Timer& tm,
-                      bqs_stats& stats) {
+// Folds in the calls that have completed, oldest first (all of them, waiting
+// as needed, with `wait`): latched error, statistics, per-level figures and
+// the depth each call shape needed.
+void harvest(bqs_ctx* ctx, bool wait) {
+    while (!ctx->inflight.empty()) {
+        bqs_ctx::Done& d = ctx->inflight.front();
+        if (wait) {
+            if (hipEventSynchronize(d.ev) != hipSuccess) latch(ctx, BQS_EHIP);
+        } else {
+            const hipError_t q = hipEventQuery(d.ev);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) latch(ctx, BQS_EHIP);
+        }
+        const Ctl& c = *d.slot;
+        latch(ctx, status_of_device_error(c.error));
+        bqs_stats st = d.host;
+        fill_stats(st, c);
+        std::vector<double> lms;
+        resolve_events(ctx, d.call, st, lms);
+        const int nl = static_cast<int>(std::min<int64_t>(st.levels, kLevelStats));
+        ctx->level_keys.assign(c.level_keys, c.level_keys + nl);
+        lms.resize(nl, 0.0);
+        ctx->level_ms = lms;
+        ctx->stats = st;
+        if (!c.error) ctx->seen_levels[d.shape] = static_cast<int>(c.levels);
+        ctx->free_slots.push_back(d.slot);
+        ctx->ev_pool.push_back(d.ev);
+        ctx->inflight.pop_front();
+    }
+}
+
+// Records the end of an enqueued call: its control block is copied to a
+// pinned slot, then an event.
+bqs_status record_completion(bqs_ctx* ctx, const Args& a, hipStream_t s, uint64_t call,
+                             const std::vector<uint64_t>& shape, const bqs_stats& host) {
+    harvest(ctx, false);
+    if (ctx->inflight.size() >= 64) harvest(ctx, true);  // bounds the pinned slots a context holds
+    Ctl* slot = nullptr;
+    if (!ctx->free_slots.empty()) {
+        slot = ctx->free_slots.back();
+        ctx->free_slots.pop_back();
+    } else {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return BQS_EHIP;
+        slot = static_cast<Ctl*>(p);
+    }
+    hipEvent_t ev = take_event(ctx);
+    if (!ev || hipMemcpyAsync(slot, a.ctl, kCtlHostBytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(ev, s) != hipSuccess) {
+        ctx->free_slots.push_back(slot);
+        if (ev) ctx->ev_pool.push_back(ev);
+        return BQS_EHIP;
+    }
+    ctx->inflight.push_back({slot, ev, call, shape, host});
+    return BQS_OK;
+}
+
+int clamp_grid(uint64_t want, int64_t cap) {
+    if (want < 1) want = 1;
+    if (want > static_cast<uint64_t>(cap)) want = static_cast<uint64_t>(cap);
+    return static_cast<int>(want);
+}
+
+// The shape of a call: what its launch sequence depends on.
+std::vector<uint64_t> call_shape(const Ops* o, const Args& a, bool segmented) {
+    auto u = [](const void* p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); };
+    return {u(o), static_cast<uint64_t>(a.n), static_cast<uint64_t>(a.k), static_cast<uint64_t>(a.small_cut),
+            static_cast<uint64_t>(a.sample_max), static_cast<uint64_t>(a.pivot_mode),
+            static_cast<uint64_t>(a.pivot_skew), static_cast<uint64_t>(a.tile_keys), static_cast<uint64_t>(a.prof),
+            static_cast<uint64_t>(a.claim), static_cast<uint64_t>(a.ways), segmented ? 1ull : 0ull};
+}
+
+// Graph key: the shape plus the buffers the launches were captured with.
+std::vector<uint64_t> graph_key(const Ops* o, const Args& a, bool segmented, bool check) {
+    auto u = [](const void* p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); };
+    std::vector<uint64_t> k = call_shape(o, a, segmented);
+    for (uint64_t v : {u(a.ctl), u(a.x_keys), u(a.x_vals), u(a.y_keys), u(a.offsets), uint64_t(check ? 1 : 0)})
+        k.push_back(v);
+    return k;
+}
+
+int level_cap(const Args& a) { return 4 * a.depth_limit + 64; }
+
+// Levels a call enqueues before its tail launch: the levels that the last
+// completed call of the same shape partitioned, plus its final level and
+// one spare; for a new shape, an estimate from the largest possible segment
+// (about log2(n / small_cut) halvings with sampled pivots, or a quarter as
+// many sixteen-way splits) with some spare levels.
+int levels_to_enqueue(const bqs_ctx* ctx, const Args& a, const std::vector<uint64_t>& shape) {
+    int L;
+    const auto it = ctx->seen_levels.find(shape);
+    if (ctx->enqueue_levels > 0) {
+        L = static_cast<int>(std::min<int64_t>(ctx->enqueue_levels, 1 << 20));
+    } else if (it != ctx->seen_levels.end()) {
+        L = it->second + 2;
+    } else if (a.n <= a.small_cut) {
+        L = 1;
+    } else {
+        const double r = std::log2(static_cast<double>(a.n) / static_cast<double>(a.small_cut));
+        L = a.ways ? static_cast<int>(std::ceil(r / 4.0)) + 3 : static_cast<int>(std::ceil(r)) + 5;
+    }
+    return std::max(1, std::min(L, level_cap(a)));
+}
+
+// Most segments level L can hold: k at level 0, times the fan-out per level
+// (two children, or up to sixteen for a multiway level), at most cap_seg.
+uint64_t seg_bound(const Args& a, int L) {
+    const uint64_t fan = a.ways ? 16 : 2;
+    uint64_t segs = static_cast<uint64_t>(std::max<int64_t>(a.k, 1));
+    for (int i = 0; i < L && segs < a.cap_seg; ++i) segs *= fan;
+    return std::min<uint64_t>(segs, a.cap_seg);
+}
+
+// Most tiles level L can hold: n/T plus two partial tiles per segment.
+uint64_t tile_bound(const Args& a, int L) {
+    const uint64_t T = static_cast<uint64_t>(a.tile_keys);
+    return std::min<uint64_t>(static_cast<uint64_t>(a.n) / T + 2 * seg_bound(a, L) + 2, a.cap_tile);
+}
+
+// Enqueues init, the optional NaN check, `levels` recursion levels with
+// grids that cover the most work each level can hold (the kernels read the
+// actual counts on the device), and the tail launch.  `tm` may be null (no
+// timing, e.g. under graph capture).
+bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int dtype, int levels,
+                          hipStream_t s, Timer* tm) {
+    if (segmented) launch_init_segments(a, s);
+    else launch_init_single(a, s);
+    if (check && (dtype == BQS_F32 || dtype == BQS_F64))
+        hipLaunchKernelGGL(k_check_nan, dim3(clamp_grid((a.n + 255) / 256, 2048)), dim3(256), 0, s, a.x_keys, a.n,
+                           dtype == BQS_F64 ? 1 : 0, a.ctl);
+    const uint64_t n = static_cast<uint64_t>(a.n);
+    for (int L = 0; L < levels; ++L) {
+        a.level = L;
+        const uint64_t sb = seg_bound(a, L);
+        const uint64_t sb_prev = L ? seg_bound(a, L - 1) : 0;
+        // equal runs written at level L: at most one chunk per kFillChunk
+        // keys plus one per run (the previous level's segments)
+        const uint64_t fill_units = L ? n / kFillChunk + sb_prev * (a.ways ? 15 : 1) : 0;
+        // small segments sorted at level L: the inputs (level 0) or the
+        // previous level's children
+        const uint64_t small_items = L ? sb_prev * (a.ways ? 16 : 2) : std::max<uint64_t>(a.k, 1);
+        if (tm) tm->start_aux();
+        (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(std::max<uint64_t>((sb + 3) / 4, fill_units), 2048), s);
+        if (a.ways) o->map(a, clamp_grid((tile_bound(a, L) + 255) / 256, 4096), s);
+        if (tm) tm->stop_aux(0, L);
+        if (tm) tm->start_aux();
+        o->small(a, clamp_grid(small_items, 2048), s);
+        if (tm) tm->stop_aux(1, L);
+        const uint64_t tb = tile_bound(a, L);
+        if (tb > 0x7fffffffull) return BQS_EINVAL;
+        const int tg = clamp_grid(tb, 0x7fffffff);
+        if (tm) tm->start();
+        if (a.ways) {
+            o->mcount(a, tg, s);
+            o->mscan(a, clamp_grid((sb + 3) / 4, 1024), s);
+            o->mscatter(a, tg, s);
+            if (tm) tm->stop(2, L);
+        } else {
+            o->tile(a, tg, s);
+            if (tm) tm->stop(2, L);
+            if (tm) tm->start_aux();
+            o->complete(a, clamp_grid((sb + 255) / 256, 1024), s);
+            if (tm) tm->stop_aux(0, L);
+        }
+    }
+    // whatever recursion is left: one workgroup, two-way levels with the
+    // two-way tile (segments listed by multiway levels are re-tiled first)
+    Args t = a;
+    t.level = levels;
+    t.ways = 0;
+    t.tile_keys = o->tile_keys;
+    t.retile = a.tile_keys != o->tile_keys ? 1 : 0;
+    if (tm) tm->start_aux();
+    o->tail(t, s);
+    if (tm) tm->stop_aux(0, levels);
+    return hipGetLastError() == hipSuccess ? BQS_OK : BQS_EHIP;
+}
+
+void drop_graph(bqs_ctx* ctx) {
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph_obj) (void)hipGraphDestroy(ctx->graph_obj);
+    ctx->gexec = nullptr;
+    ctx->graph_obj = nullptr;
+    ctx->gkey.clear();
+    ctx->glevels = 0;
+}
+
+bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, const Args& a, bool segmented, int dtype, int levels) {
+    drop_graph(ctx);
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return BQS_EHIP;
+    const hipStream_t cs = ctx->cap_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return BQS_EHIP;
+    const bqs_status st = enqueue_levels(o, a, segmented, ctx->check_nan != 0, dtype, levels, cs, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st != BQS_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != BQS_OK ? st : BQS_EHIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return BQS_EHIP;
+    }
+    ctx->graph_obj = g;
+    ctx->gexec = ex;
+    ctx->glevels = levels;
+    return BQS_OK;
+}
+
+// Asynchronous sort (default mode, also graph mode): enqueue and return.
+bqs_status run_async(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int dtype) {
     const hipStream_t s = ctx->stream;
-    bqs_status st = BQS_OK;
-    const int64_t level_cap = 4 * static_cast<int64_t>(a.depth_limit) + 64;
-    for (int L = L0;; ++L) {
+    harvest(ctx, false);
+    const uint64_t call = ++ctx->calls;
+    const std::vector<uint64_t> shape = call_shape(o, a, segmented);
+    const int levels = levels_to_enqueue(ctx, a, shape);
+    bqs_stats host{};
+    host.tile_keys = a.tile_keys;
+    host.small_cutoff = a.small_cut;
+    bqs_status st;
+    if (ctx->graph) {
+        const std::vector<uint64_t> key = graph_key(o, a, segmented, ctx->check_nan != 0);
+        // (re)capture for a new shape, or when the depth the graph holds is
+        // short of or far past what the shape needs
+        if (!ctx->gexec || key != ctx->gkey || ctx->glevels < levels || ctx->glevels > levels + 4) {
+            if ((st = capture_graph(ctx, o, a, segmented, dtype, levels)) != BQS_OK) return st;
+            ctx->gkey = key;
+        }
+        if (hipGraphLaunch(ctx->gexec, s) != hipSuccess) return BQS_EHIP;
+        host.graph_launches = 1;
+        host.partition_launches = ctx->glevels;
+        host.small_launches = ctx->glevels;
+    } else {
+        Timer tm{ctx, ctx->timing != 0, ctx->timing == 1, call, s};
+        if ((st = enqueue_levels(o, a, segmented, ctx->check_nan != 0, dtype, levels, s, &tm)) != BQS_OK) return st;
+        host.partition_launches = levels;
+        host.small_launches = levels;
+    }
+    return record_completion(ctx, a, s, call, shape, host);
+}
+
+// ------------------------------------------------------ host-driven mode --
+
+bqs_status ensure_pinned(bqs_ctx* ctx) {
+    if (!ctx->pinned) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return BQS_EHIP;
+        ctx->pinned = static_cast<Ctl*>(p);
+    }
+    return BQS_OK;
+}
+
+// Copies the device control block to pinned host memory and waits.
+bqs_status read_ctl(bqs_ctx* ctx, const Ctl* dev) {
+    if (hipMemcpyAsync(ctx->pinned, dev, kCtlHostBytes, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+        return BQS_EHIP;
+    return hip_ok(hipStreamSynchronize(ctx->stream));
+}
+
+// Levels driven from the host (BQS_MODE_LEVELS): each level's counts are
+// read back before its launches are sized, so every launch covers exactly
+// its level's work and the call returns when the sort has finished.
+bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int dtype) {
+    harvest(ctx, true);
+    bqs_status st = ensure_pinned(ctx);
+    if (st != BQS_OK) return st;
+    const hipStream_t s = ctx->stream;
+    const uint64_t call = ++ctx->calls;
+    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1, call, s};
+    bqs_stats stats{};
+    stats.tile_keys = a.tile_keys;
+    stats.small_cutoff = a.small_cut;
+    std::vector<int64_t> lkeys;
+
+    if (segmented) launch_init_segments(a, s);
+    else launch_init_single(a, s);
+    if (ctx->check_nan && (dtype == BQS_F32 || dtype == BQS_F64))
+        hipLaunchKernelGGL(k_check_nan, dim3(clamp_grid((a.n + 255) / 256, 2048)), dim3(256), 0, s, a.x_keys, a.n,
+                           dtype == BQS_F64 ? 1 : 0, a.ctl);
+    if (hipGetLastError() != hipSuccess) return BQS_EHIP;
+    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
+    if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
+    LevelCtr cur = ctx->pinned->lc[0];
+    const int cap = level_cap(a);
+    for (int L = 0;; ++L) {
         a.level = L;
         const uint32_t nseg = static_cast<uint32_t>(cur.segs);
         const uint32_t ntile = static_cast<uint32_t>(cur.segs >> 32);
         const uint32_t nchunk = static_cast<uint32_t>(cur.fills >> 32);
         tm.start_aux();
-        // plan: one wave per segment (4 per workgroup), one workgroup per fill chunk
-        // (the two-way plan also writes the tile descriptors; the multiway
-        // levels map tiles to segments in a launch of their own)
+        // plan: one wave per segment (4 per workgroup), one workgroup per
+        // fill chunk (the two-way plan also writes the tile descriptors; the
+        // multiway levels map tiles to segments in a launch of their own)
         (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(std::max<uint64_t>((nseg + 3) / 4, nchunk), 16384), s);
         if (nseg && a.ways) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
         tm.stop_aux(0, L);
@@ -467,15 +787,9 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         }
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
         if (nseg == 0) break;
-        if (L >= level_cap) return BQS_EOVERFLOW;
-        if (ctx->level_keys.size() <= static_cast<size_t>(L)) {
-            ctx->level_keys.resize(L + 1, 0);
-            ctx->level_ms.resize(L + 1, 0.0);
-        }
-        ctx->level_keys[L] = static_cast<int64_t>(cur.keys);
+        if (L >= cap) return BQS_EOVERFLOW;
+        lkeys.push_back(static_cast<int64_t>(cur.keys));
         tm.start();
-        // one workgroup per tile (tiles are still claimed in order through the
-        // level's ticket counter, which the look-back relies on)
         if (a.ways) {
             o->mcount(a, static_cast<int>(ntile), s);
             o->mscan(a, clamp_grid((nseg + 3) / 4, 4096), s);
@@ -491,190 +805,28 @@ bqs_status level_loop(bqs_ctx* ctx, const Ops* o, Args& a, int L0, LevelCtr cur,
         stats.partition_launches++;
         if (hipGetLastError() != hipSuccess) return BQS_EHIP;
         if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
-        tm.resolve(stats);
         if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
         cur = ctx->pinned->lc[(L + 1) & 1];
     }
-    return BQS_OK;
-}
-
-// Host-driven sort: init, then the level loop.
-bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
-    bqs_status st = ensure_device_state(ctx);
-    if (st != BQS_OK) return st;
-    const hipStream_t s = ctx->stream;
-    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1};
-    tm.resolve(ctx->stats);  // drop events a failed call may have left
-    bqs_stats stats{};
-    stats.tile_keys = a.tile_keys;
-    stats.small_cutoff = a.small_cut;
-
-    if (segmented) launch_init_segments(a, s);
-    else launch_init_single(a, s);
-    if (hipGetLastError() != hipSuccess) return BQS_EHIP;
     if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
     if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
-    ctx->level_keys.clear();
-    ctx->level_ms.clear();
-    if ((st = level_loop(ctx, o, a, 0, ctx->pinned->lc[0], tm, stats)) != BQS_OK) return st;
-    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
-    tm.resolve(stats);
-    if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
+    std::vector<double> lms;
+    resolve_events(ctx, call, stats, lms);
     fill_stats(stats, *ctx->pinned);
+    lms.resize(lkeys.size(), 0.0);
+    ctx->level_keys = lkeys;
+    ctx->level_ms = lms;
     ctx->stats = stats;
     return BQS_OK;
 }
 
-// ------------------------------------------------------------ graph mode --
-// The launches of a whole sort, captured once into a HIP graph and replayed.
-// A graph cannot read counts back, so every launch has a grid fixed at
-// capture time that covers the most work its level can hold, and the kernels
-// take the actual counts from the device (surplus workgroups leave at once).
-// The graph holds as many levels as the first, host-driven call of the same
-// shape needed; if a later input needs more, the host-driven loop takes over
-// at the first level the graph does not hold.
-
-std::vector<uint64_t> graph_key(const Ops* o, const Args& a, bool segmented) {
-    auto u = [](const void* p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); };
-    return {u(o), u(a.ctl), u(a.x_keys), u(a.x_vals), u(a.y_keys), u(a.offsets), static_cast<uint64_t>(a.n),
-            static_cast<uint64_t>(a.k), static_cast<uint64_t>(a.small_cut), static_cast<uint64_t>(a.sample_max),
-            static_cast<uint64_t>(a.pivot_mode), static_cast<uint64_t>(a.pivot_skew), static_cast<uint64_t>(a.depth_limit),
-            static_cast<uint64_t>(a.prof), static_cast<uint64_t>(a.claim), static_cast<uint64_t>(a.ways),
-            segmented ? 1ull : 0ull};
-}
-
-void drop_graph(bqs_ctx* ctx) {
-    if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
-    if (ctx->graph_obj) hipGraphDestroy(ctx->graph_obj);
-    ctx->gexec = nullptr;
-    ctx->graph_obj = nullptr;
-    ctx->gkey.clear();
-    ctx->glevels = 0;
-}
-
-// Most tiles level L can hold: n/T plus two partial tiles per segment; a
-// level has at most min(k * f^L, cap_seg) segments, f = 2 children per
-// segment for the two-way step and 16 for the multiway step.
-uint64_t tile_bound(const Args& a, int L) {
-    const uint64_t T = static_cast<uint64_t>(a.tile_keys);
-    // children per segment: two, or up to sixteen for a multiway level
-    const uint64_t fan = a.ways ? 16 : 2;
-    uint64_t segs = static_cast<uint64_t>(a.k);
-    for (int i = 0; i < L && segs < a.cap_seg; ++i) segs *= fan;
-    segs = std::min<uint64_t>(segs, a.cap_seg);
-    return std::min<uint64_t>(static_cast<uint64_t>(a.n) / T + 2 * segs + 2, a.cap_tile);
-}
-
-bqs_status capture_graph(bqs_ctx* ctx, const Ops* o, Args a, bool segmented, int levels) {
-    drop_graph(ctx);
-    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
-        return BQS_EHIP;
-    const hipStream_t cs = ctx->cap_stream;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return BQS_EHIP;
-    if (segmented) launch_init_segments(a, cs);
-    else launch_init_single(a, cs);
-    for (int L = 0; L < levels; ++L) {
-        a.level = L;
-        (a.ways ? o->plan_multi : o->plan)(a, 2048, cs);
-        if (a.ways) o->map(a, 4096, cs);
-        o->small(a, 2048, cs);
-        const uint64_t tb = tile_bound(a, L);
-        if (tb > 0x7fffffffull) {
-            hipGraph_t g = nullptr;
-            hipStreamEndCapture(cs, &g);
-            if (g) hipGraphDestroy(g);
-            return BQS_EINVAL;
-        }
-        const int tg = static_cast<int>(std::max<uint64_t>(tb, 1));
-        if (a.ways) {
-            o->mcount(a, tg, cs);
-            o->mscan(a, 1024, cs);
-            o->mscatter(a, tg, cs);
-        } else {
-            o->tile(a, tg, cs);
-            o->complete(a, 1024, cs);
-        }
-    }
-    hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return BQS_EHIP;
-    hipGraphExec_t ex = nullptr;
-    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(g);
-        return BQS_EHIP;
-    }
-    ctx->graph_obj = g;
-    ctx->gexec = ex;
-    ctx->glevels = levels;
-    return BQS_OK;
-}
-
-bqs_status run_graph(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
-    const std::vector<uint64_t> key = graph_key(o, a, segmented);
-    if (!ctx->gexec || key != ctx->gkey) {
-        // first call of this shape: sort host-driven, then capture as many
-        // levels as it took (the last one has no segments left to partition)
-        bqs_status st = run_levels(ctx, o, a, segmented);
-        if (st != BQS_OK) return st;
-        const int levels = static_cast<int>(ctx->stats.levels) + 1;
-        if ((st = capture_graph(ctx, o, a, segmented, levels)) != BQS_OK) return st;
-        ctx->gkey = key;
-        return BQS_OK;
-    }
-    bqs_status st = ensure_device_state(ctx);
-    if (st != BQS_OK) return st;
-    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1};
-    tm.resolve(ctx->stats);
-    bqs_stats stats{};
-    stats.tile_keys = a.tile_keys;
-    stats.small_cutoff = a.small_cut;
-    ctx->level_keys.clear();
-    ctx->level_ms.clear();
-    if (hipGraphLaunch(ctx->gexec, ctx->stream) != hipSuccess) return BQS_EHIP;
-    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
-    tm.resolve(stats);
-    if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
-    stats.graph_launches = 1;
-    // work the graph's levels did not reach: continue host-driven
-    const LevelCtr cur = ctx->pinned->lc[ctx->glevels & 1];
-    bool more = cur.segs != 0 || cur.fills != 0;
-    for (int c = 0; c < kSmallClasses; ++c) more = more || cur.smalls[c] != 0;
-    if (more) {
-        if ((st = level_loop(ctx, o, a, ctx->glevels, cur, tm, stats)) != BQS_OK) return st;
-        if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
-        tm.resolve(stats);
-        if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
-    }
-    fill_stats(stats, *ctx->pinned);
-    ctx->stats = stats;
-    if (more) {
-        // hold the deeper recursion from now on
-        if ((st = capture_graph(ctx, o, a, segmented, static_cast<int>(stats.levels) + 1)) != BQS_OK) return st;
-        ctx->gkey = key;
-    }
-    return BQS_OK;
-}
-
-// The entry points' common driver.
-bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
-    if (ctx->mode == BQS_MODE_PERSISTENT) return run_persist(ctx, o, a, segmented);
-    if (ctx->graph) return run_graph(ctx, o, a, segmented);
-    return run_levels(ctx, o, a, segmented);
-}
-
-// Persistent mode: init, then one cooperative launch of every workgroup the
-// GPU holds at once, which runs all levels; one host wait for the status.
-bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
+// ------------------------------------------------------ persistent mode --
+// Init, then one cooperative launch of every workgroup the GPU holds at
+// once, which runs all levels; asynchronous like the default mode.
+bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int dtype) {
     if (a.ways) return BQS_EINVAL;  // the multiway step has no persistent form
-    bqs_status st = ensure_device_state(ctx);
-    if (st != BQS_OK) return st;
+    harvest(ctx, false);
     const hipStream_t s = ctx->stream;
-    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1};
-    tm.resolve(ctx->stats);
-    bqs_stats stats{};
-    stats.tile_keys = a.tile_keys;
-    stats.small_cutoff = a.small_cut;
-    ctx->level_keys.clear();
-    ctx->level_ms.clear();
     if (ctx->persist_grid <= 0 || ctx->persist_ops != o) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess) return BQS_EHIP;
@@ -686,20 +838,32 @@ bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented) {
     }
     const int grid = static_cast<int>(ctx->grid > 0 ? std::min<int64_t>(ctx->grid, ctx->persist_grid)
                                                     : ctx->persist_grid);
+    const uint64_t call = ++ctx->calls;
+    Timer tm{ctx, ctx->timing != 0, ctx->timing == 1, call, s};
     a.prof = 0;
+    a.level = 0;
+    a.retile = 0;
     if (segmented) launch_init_segments(a, s);
     else launch_init_single(a, s);
+    if (ctx->check_nan && (dtype == BQS_F32 || dtype == BQS_F64))
+        hipLaunchKernelGGL(k_check_nan, dim3(clamp_grid((a.n + 255) / 256, 2048)), dim3(256), 0, s, a.x_keys, a.n,
+                           dtype == BQS_F64 ? 1 : 0, a.ctl);
     tm.start();
     const hipError_t e = o->persist(a, grid, s);
-    tm.stop(2, 0);
+    tm.stop(2, -1);
     if (e != hipSuccess || hipGetLastError() != hipSuccess) return BQS_EHIP;
-    if ((st = read_ctl(ctx, a.ctl)) != BQS_OK) return st;
-    tm.resolve(stats);
-    if (ctx->pinned->error) return status_of_device_error(ctx->pinned->error);
-    fill_stats(stats, *ctx->pinned);
-    stats.partition_launches = 1;
-    ctx->stats = stats;
-    return BQS_OK;
+    bqs_stats host{};
+    host.tile_keys = a.tile_keys;
+    host.small_cutoff = a.small_cut;
+    host.partition_launches = 1;
+    return record_completion(ctx, a, s, call, call_shape(o, a, segmented), host);
+}
+
+// The entry points' common driver.
+bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int dtype) {
+    if (ctx->mode == BQS_MODE_PERSISTENT) return run_persist(ctx, o, a, segmented, dtype);
+    if (ctx->mode == BQS_MODE_LEVELS) return run_levels(ctx, o, a, segmented, dtype);
+    return run_async(ctx, o, a, segmented, dtype);
 }
 
 bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int64_t k, void* keys,
@@ -770,7 +934,7 @@ size_t record_head(int64_t n, const RecordKind& rk) {
     return align_up(static_cast<size_t>(n) * key_bytes(rk.key_dtype)) + align_up(static_cast<size_t>(n) * 4);
 }
 bqs_status finish(bqs_ctx* ctx, bqs_status st) {
-    if (st != BQS_OK) ctx->latched = st;
+    latch(ctx, st);
     return st;
 }
 
@@ -786,15 +950,17 @@ bqs_status bqs_ctx_create(bqs_ctx** out) {
 
 void bqs_ctx_destroy(bqs_ctx* ctx) {
     if (!ctx) return;
+    harvest(ctx, true);  // the calls still in flight finish first
     drop_graph(ctx);
-    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-    if (ctx->pinned) hipHostFree(ctx->pinned);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (Ctl* p : ctx->free_slots) (void)hipHostFree(p);
     for (auto& p : ctx->pending) {
         ctx->ev_pool.push_back(p.a);
         ctx->ev_pool.push_back(p.b);
     }
     for (hipEvent_t e : ctx->ev_pool)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -843,8 +1009,14 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             break;
         case BQS_PARAM_LOOKBACK: ctx->lookback = value ? 1 : 0; break;
         case BQS_PARAM_MULTIWAY: ctx->multiway = value ? 1 : 0; break;
+        case BQS_PARAM_CHECK_NAN: ctx->check_nan = value ? 1 : 0; break;
+        case BQS_PARAM_ENQUEUE_LEVELS:
+            ctx->enqueue_levels = value;
+            drop_graph(ctx);
+            break;
         case BQS_PARAM_MODE:
-            if (value != BQS_MODE_LEVELS && value != BQS_MODE_PERSISTENT) return BQS_EINVAL;
+            if (value != BQS_MODE_ASYNC && value != BQS_MODE_LEVELS && value != BQS_MODE_PERSISTENT)
+                return BQS_EINVAL;
             ctx->mode = value;
             drop_graph(ctx);
             break;
@@ -868,18 +1040,23 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_GRAPH: return ctx->graph;
         case BQS_PARAM_LOOKBACK: return ctx->lookback;
         case BQS_PARAM_MULTIWAY: return ctx->multiway;
+        case BQS_PARAM_CHECK_NAN: return ctx->check_nan;
+        case BQS_PARAM_ENQUEUE_LEVELS: return ctx->enqueue_levels;
         default: return -1;
     }
 }
 
-bqs_status bqs_ctx_get_stats(const bqs_ctx* ctx, bqs_stats* out) {
+bqs_status bqs_ctx_get_stats(bqs_ctx* ctx, bqs_stats* out) {
     if (!ctx || !out) return BQS_EINVAL;
+    harvest(ctx, true);
     *out = ctx->stats;
     return BQS_OK;
 }
 
-bqs_status bqs_ctx_get_level(const bqs_ctx* ctx, int level, int64_t* keys, double* partition_ms) {
-    if (!ctx || level < 0 || static_cast<size_t>(level) >= ctx->level_keys.size()) return BQS_EINVAL;
+bqs_status bqs_ctx_get_level(bqs_ctx* ctx, int level, int64_t* keys, double* partition_ms) {
+    if (!ctx) return BQS_EINVAL;
+    harvest(ctx, true);
+    if (level < 0 || static_cast<size_t>(level) >= ctx->level_keys.size()) return BQS_EINVAL;
     if (keys) *keys = ctx->level_keys[level];
     if (partition_ms) *partition_ms = ctx->level_ms[level];
     return BQS_OK;
@@ -900,15 +1077,12 @@ bqs_status bqs_sort(void* keys, int64_t n, bqs_dtype dtype, bqs_ctx* ctx) {
     if (!ctx || n < 0 || (n > 0 && !keys)) return BQS_EINVAL;
     const Ops* o = select_ops(ctx, dtype, 0);
     if (!o) return BQS_EDTYPE;
-    if (n <= 1) {
-        ctx->stats = bqs_stats{};
-        return BQS_OK;
-    }
+    if (n <= 1) return BQS_OK;
     if (n >= (int64_t(1) << 31)) return BQS_EINVAL;
     Args a;
     bqs_status st = prepare(ctx, o, n, dtype, 0, 1, keys, nullptr, a);
     if (st != BQS_OK) return st;
-    return finish(ctx, run_sort(ctx, o, a, false));
+    return finish(ctx, run_sort(ctx, o, a, false, dtype));
 }
 
 bqs_status bqs_sort_pairs(void* keys, void* vals, int64_t n, bqs_dtype key, int32_t val_bytes,
@@ -917,15 +1091,12 @@ bqs_status bqs_sort_pairs(void* keys, void* vals, int64_t n, bqs_dtype key, int3
     if (val_bytes != 4 && val_bytes != 8) return BQS_EDTYPE;
     const Ops* o = select_ops(ctx, key, val_bytes);
     if (!o) return BQS_EDTYPE;
-    if (n <= 1) {
-        ctx->stats = bqs_stats{};
-        return BQS_OK;
-    }
+    if (n <= 1) return BQS_OK;
     if (n >= (int64_t(1) << 31)) return BQS_EINVAL;
     Args a;
     bqs_status st = prepare(ctx, o, n, key, val_bytes, 1, keys, vals, a);
     if (st != BQS_OK) return st;
-    return finish(ctx, run_sort(ctx, o, a, false));
+    return finish(ctx, run_sort(ctx, o, a, false, key));
 }
 
 bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int64_t n_total,
@@ -933,15 +1104,12 @@ bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int6
     if (!ctx || k < 0 || n_total < 0 || (n_total > 0 && !keys) || (k > 0 && !offsets)) return BQS_EINVAL;
     const Ops* o = select_ops(ctx, dtype, 0);
     if (!o) return BQS_EDTYPE;
-    if (k == 0 || n_total <= 1) {
-        ctx->stats = bqs_stats{};
-        return BQS_OK;
-    }
+    if (k == 0 || n_total <= 1) return BQS_OK;
     Args a;
     bqs_status st = prepare(ctx, o, n_total, dtype, 0, k, keys, nullptr, a);
     if (st != BQS_OK) return st;
     a.offsets = offsets;
-    return finish(ctx, run_sort(ctx, o, a, true));
+    return finish(ctx, run_sort(ctx, o, a, true, dtype));
 }
 
 bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offsets, int64_t k,
@@ -951,15 +1119,12 @@ bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offset
     if (val_bytes != 4 && val_bytes != 8) return BQS_EDTYPE;
     const Ops* o = select_ops(ctx, key, val_bytes);
     if (!o) return BQS_EDTYPE;
-    if (k == 0 || n_total <= 1) {
-        ctx->stats = bqs_stats{};
-        return BQS_OK;
-    }
+    if (k == 0 || n_total <= 1) return BQS_OK;
     Args a;
     bqs_status st = prepare(ctx, o, n_total, key, val_bytes, k, keys, vals, a);
     if (st != BQS_OK) return st;
     a.offsets = offsets;
-    return finish(ctx, run_sort(ctx, o, a, true));
+    return finish(ctx, run_sort(ctx, o, a, true, key));
 }
 
 // ------------------------------------------------------------- records --
@@ -980,7 +1145,6 @@ bqs_status bqs_sort_records(const void* in, void* out, int64_t n, int kind, bqs_
     if (overlaps(in, n * rec, out, n * rec) || overlaps(in, n * rec, ctx->ws, ctx->ws_bytes) ||
         overlaps(out, n * rec, ctx->ws, ctx->ws_bytes))
         return BQS_EINVAL;
-    ctx->stats = bqs_stats{};
     if (n == 0) return BQS_OK;
     const size_t head = record_head(n, rk);
     if (!ctx->ws || ctx->ws_bytes < bqs_records_workspace_bytes(ctx, n, kind)) return BQS_EINVAL;
@@ -1009,7 +1173,7 @@ bqs_status bqs_sort_records(const void* in, void* out, int64_t n, int kind, bqs_
         ctx->graph = 0;
         Args a;
         st = prepare(ctx, o, n, rk.key_dtype, 4, 1, keys, idx, a);
-        if (st == BQS_OK) st = run_sort(ctx, o, a, false);
+        if (st == BQS_OK) st = run_sort(ctx, o, a, false, rk.key_dtype);
         ctx->ws = ws0;
         ctx->ws_bytes = wb0;
         ctx->graph = graph0;
@@ -1025,8 +1189,11 @@ bqs_status bqs_sort_records(const void* in, void* out, int64_t n, int kind, bqs_
 
 bqs_status bqs_ctx_sync_status(bqs_ctx* ctx) {
     if (!ctx) return BQS_EINVAL;
-    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return BQS_EHIP;
-    return ctx->latched;
+    harvest(ctx, true);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) latch(ctx, BQS_EHIP);
+    const bqs_status st = ctx->latched;
+    ctx->latched = BQS_OK;
+    return st;
 }
 
 const char* bqs_status_str(bqs_status s) {
@@ -1042,6 +1209,6 @@ const char* bqs_status_str(bqs_status s) {
     }
 }
 
-int bqs_version(void) { return 100; }
+int bqs_version(void) { return 200; }
 
 }  // extern "C"

@@ -85,6 +85,9 @@ struct LevelCtr {
 };
 
 constexpr int kMaxXcd = 16;  // XCD ids the persistent barrier can index (MI355X has 8)
+constexpr int kLevelStats = 128;  // levels with their own statistics slot (deeper ones share the last)
+
+__host__ __device__ inline int level_slot(int level) { return level < kLevelStats ? level : kLevelStats - 1; }
 
 struct Ctl {
     LevelCtr lc[2];
@@ -97,6 +100,7 @@ struct Ctl {
     // profile counters (only with Args::prof): tiles, look-back rounds,
     // look-back polls, look-back cycles, tile cycles, load+count cycles
     unsigned long long prof[8];
+    unsigned long long level_keys[kLevelStats];  // keys partitioned per level (statistics)
     // persistent mode: grid barrier.  Global arrivals (one per XCD) and the
     // generation that waiting workgroups poll, each on a line of its own;
     // arrivals per XCD (one line each); resident workgroups per XCD.
@@ -132,6 +136,7 @@ struct Args {
     int prof;
     int claim;  // 1: keys-only tiles claim their ranges with the segment's cursor
     int ways;   // 1: multiway partition levels (keys only)
+    int retile; // 1: the first level's segments were tiled for another tile size (tail kernel)
     uint64_t* splitters[2];  // per slot: 16 order keys per segment
     uint32_t* toff;          // per tile: offset of its keys inside each bucket
     uint32_t* bcur;          // per segment: bucket cursors (stride 32)
@@ -159,6 +164,9 @@ struct Ops {
     // persistent mode: every level in one cooperative launch of `grid`
     // resident workgroups; small segments up to persist_small_max keys
     hipError_t (*persist)(const Args&, int grid, hipStream_t);
+    // the levels from a.level on, by one workgroup (an ordinary launch): the
+    // rest of a sort whose enqueued levels did not reach the end
+    void (*tail)(const Args&, hipStream_t);
     int (*persist_blocks_per_cu)();
     int persist_small_max;
     int multi_tile_keys;  // keys per tile of the multiway levels (0 without them)

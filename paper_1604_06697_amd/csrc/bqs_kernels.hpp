@@ -979,6 +979,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
         if (next_keys) {
             atomicAdd(&c->part_keys, next_keys);
             atomicAdd(&c->lc[q].keys, next_keys);
+            atomicAdd(&c->level_keys[level_slot(level + 1)], next_keys);
         }
         if (next_tiles) atomicAdd(&c->tiles, next_tiles);
     }
@@ -1601,6 +1602,45 @@ __device__ inline bool grid_sync_xcd(Ctl* c, uint32_t xcd, uint32_t my_n, uint32
     return *s_ok != 0;
 }
 
+// Gives the segments of level slot p the tiles of the tile size a.tile_keys
+// (first tile and tile count; the level's tile total).  Run by a single
+// workgroup of NT threads: the tail kernel, whose first level may have been
+// listed by multiway levels with their own tile size.
+template <int NT>
+__device__ void retile_level(const Args& a, int p) {
+    __shared__ uint32_t s_w[NT / 64];
+    Ctl* c = a.ctl;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    if (nseg > a.cap_seg) nseg = a.cap_seg;
+    const int64_t T = a.tile_keys;
+    uint64_t base = 0;
+    for (uint32_t b = 0; b < nseg; b += NT) {
+        const uint32_t i = b + tid;
+        const uint32_t nt = i < nseg ? seg_tiles(a.segs[p][i].lo, a.segs[p][i].hi, T) : 0u;
+        const uint32_t inc = static_cast<uint32_t>(wave_inclusive_sum(static_cast<uint64_t>(nt), opaque(lane)));
+        if (lane == 63) s_w[wv] = inc;
+        __syncthreads();
+        uint64_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+            before += w < wv ? s_w[w] : 0u;
+            total += s_w[w];
+        }
+        if (i < nseg) {
+            a.segs[p][i].t0 = static_cast<uint32_t>(base + before + inc - nt);
+            a.segs[p][i].nt = nt;
+        }
+        base += total;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (base > a.cap_tile) atomicOr(&c->error, ERR_OVERFLOW);
+        c->lc[p].segs = (static_cast<unsigned long long>(base < a.cap_tile ? base : a.cap_tile) << 32) | nseg;
+    }
+    __syncthreads();
+}
+
 // LDS of the persistent kernel: one region that each step views as its own
 // layout (steps are separated by barriers).
 template <int DT, class V, int NT, int EPT, int SP>
@@ -1638,8 +1678,12 @@ __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
     }
     __syncthreads();
     const uint32_t my_n = s_xn[0], nxcd = s_xn[1];
-    for (int L = 0;; ++L) {
+    for (int L = a.level;; ++L) {
         const int p = L & 1;
+        if (L == a.level && a.retile) {
+            retile_level<NT>(a, p);
+            if (!grid_sync_xcd(c, xcd, my_n, nxcd, gen, &s_ok)) return;
+        }
         const unsigned long long sc = c->lc[p].segs;
         const uint32_t nseg = static_cast<uint32_t>(sc);
         uint32_t ntile = static_cast<uint32_t>(sc >> 32);
@@ -1755,6 +1799,11 @@ struct Launch {
         return hipLaunchCooperativeKernel(k_persist<DT, V, NT, EPT, kPersistSmall>, dim3(grid), dim3(NT), args, 0,
                                           s);
     }
+    // the tail: the persistent kernel's loop on one workgroup, small segments
+    // up to the full cutoff
+    static void tail(const Args& a, hipStream_t s) {
+        hipLaunchKernelGGL((k_persist<DT, V, NT, EPT, SMAX>), dim3(1), dim3(NT), 0, s, a);
+    }
     static int persist_blocks_per_cu() {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<DT, V, NT, EPT, kPersistSmall>, NT, 0) !=
@@ -1779,6 +1828,7 @@ struct Launch {
             MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::sc(),
             MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::sa(),
             &persist,
+            &tail,
             &persist_blocks_per_cu,
             kPersistSmall,
             MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::tile()};

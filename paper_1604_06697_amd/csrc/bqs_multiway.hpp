@@ -317,6 +317,7 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
         if (k) {
             atomicAdd(&c->part_keys, k);
             atomicAdd(&c->lc[q].keys, k);
+            atomicAdd(&c->level_keys[level_slot(a.level + 1)], k);
         }
         if (t) atomicAdd(&c->tiles, t);
     }

@@ -232,6 +232,7 @@ class SortService:
             else:
                 ctx.sort_segments(keys, off)
             stream.synchronize()
+            ctx.synchronize()  # raises for an error the device latched
         t = self.now()
         for i, r in enumerate(batch):
             lo, hi = int(offsets[i]), int(offsets[i + 1])
@@ -319,6 +320,7 @@ def run_one_per_launch(trace, seed_base: int = 0, keep_inputs=()):
         else:
             ctx.sort(keys)
         torch.cuda.current_stream().synchronize()
+        ctx.synchronize()
         r.done = clock() - t0
         if r.rid in keep:
             r.out_keys, r.out_vals = keys, vals

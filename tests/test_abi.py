@@ -64,6 +64,9 @@ def test_ctx_params_roundtrip(bqs):
         with pytest.raises(bqs.BqsError):
             ctx.set_param("pivot_skew", bad)
     ctx.set_param("pivot_skew", 0)
+    assert ctx.get_param("check_nan") == 0
+    ctx.set_param("check_nan", 1)
+    assert ctx.get_param("check_nan") == 1
     for t in (0, 1, 2):
         ctx.set_param("timing", t)
         assert ctx.get_param("timing") == t
@@ -72,9 +75,8 @@ def test_ctx_params_roundtrip(bqs):
     with pytest.raises(bqs.BqsError):
         ctx.set_param("tile_ept", 12)
     assert bqs.lib.bqs_ctx_set_param(ctx._h, 77, 1) == 1
-    # 1 is no mode (the work-queue kernel of an earlier build was removed)
-    with pytest.raises(bqs.BqsError):
-        ctx.set_param("mode", 1)
+    assert ctx.get_param("mode") == bqs.MODE_ASYNC  # the default: calls only enqueue
+    ctx.set_param("mode", bqs.MODE_LEVELS)
     assert ctx.get_param("mode") == bqs.MODE_LEVELS
     ctx.set_param("mode", bqs.MODE_PERSISTENT)
     assert ctx.get_param("mode") == bqs.MODE_PERSISTENT

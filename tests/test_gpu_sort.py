@@ -53,8 +53,9 @@ def from_dev(t, dtype):
 
 def gpu_sort(torch, bqs, a, ctx=None):
     t = to_dev(torch, a)
-    (ctx or bqs.default_context()).sort(t, key_type=_KT[a.dtype])
-    torch.cuda.synchronize()
+    c = ctx or bqs.default_context()
+    c.sort(t, key_type=_KT[a.dtype])
+    c.synchronize()  # waits, and raises for a device-detected error
     return from_dev(t, a.dtype)
 
 
@@ -161,8 +162,9 @@ def check_pairs(keys_in, ko, vo, expect_keys):
 def gpu_pairs(torch, bqs, k, v, ctx=None):
     tk = to_dev(torch, k)
     tv = to_dev(torch, v)
-    (ctx or bqs.default_context()).sort_pairs(tk, tv, key_type=_KT[k.dtype])
-    torch.cuda.synchronize()
+    c = ctx or bqs.default_context()
+    c.sort_pairs(tk, tv, key_type=_KT[k.dtype])
+    c.synchronize()
     return from_dev(tk, k.dtype), from_dev(tv, v.dtype)
 
 
@@ -206,8 +208,9 @@ def test_pairs_deterministic(torch_mod, bqs):
 def gpu_segments(torch, bqs, keys, offsets, ctx=None):
     t = to_dev(torch, keys)
     o = torch.from_numpy(offsets).cuda()
-    (ctx or bqs.default_context()).sort_segments(t, o, key_type=_KT[keys.dtype])
-    torch.cuda.synchronize()
+    c = ctx or bqs.default_context()
+    c.sort_segments(t, o, key_type=_KT[keys.dtype])
+    c.synchronize()
     return from_dev(t, keys.dtype)
 
 
@@ -372,7 +375,7 @@ def test_multiway_segments_and_graph(torch_mod, bqs, oracle):
         gctx.sort_segments(buf, off)
         torch.cuda.synchronize()
         assert_same_bits(buf.cpu().numpy(), oracle.sort_segments(a, offsets))
-        assert gctx.stats()["graph_launches"] == (0 if i == 0 else 1)
+        assert gctx.stats()["graph_launches"] == 1  # the first call captures and launches
 
 
 def test_multiway_graph_single_array(torch_mod, bqs, oracle):
@@ -430,7 +433,7 @@ def test_graph_replays_match_oracle(torch_mod, bqs, oracle):
         assert float(junk) == float(junk)
         assert_same_bits(buf.cpu().numpy(), oracle.sort_segments(a, offsets))
         s = ctx.stats()
-        assert s["graph_launches"] == (0 if i == 0 else 1)
+        assert s["graph_launches"] == 1
         assert s["small_sorted_keys"] + s["filled_keys"] <= n
 
 
@@ -446,7 +449,7 @@ def test_graph_single_array_and_pairs(torch_mod, bqs, oracle):
         ctx.sort(buf)
         torch.cuda.synchronize()
         assert_same_bits(buf.cpu().numpy(), oracle.sort(a))
-        assert ctx.stats()["graph_launches"] == (0 if r == 0 else 1)
+        assert ctx.stats()["graph_launches"] == 1
     m = 300_000
     kb = torch.empty(m, dtype=torch.int64, device="cuda")
     vb = torch.empty(m, dtype=torch.int32, device="cuda")
@@ -475,8 +478,9 @@ def test_graph_bad_offsets_on_replay(torch_mod, bqs):
     torch.cuda.synchronize()
     off.copy_(torch.tensor([0, 60_000, 40_000, 100_000], dtype=torch.int64))
     note("graph replay with malformed offsets")
+    ctx.sort_segments(buf, off)  # enqueued; the device finds the offsets malformed
     with pytest.raises(bqs.BqsError) as e:
-        ctx.sort_segments(buf, off)
+        ctx.synchronize()
     assert e.value.status == 1
 
 
@@ -558,7 +562,8 @@ def test_stats_account_for_every_key(torch_mod, bqs):
         # except single keys already in place
         done = s["small_sorted_keys"] + s["filled_keys"]
         assert 0.99 * a.size <= done <= a.size
-        assert s["levels"] == s["partition_launches"] >= 1
+        # the call enqueues its levels plus spare ones (empty launches)
+        assert s["partition_launches"] > s["levels"] >= 1
         assert s["graph_launches"] == 0
         # per-level partitioned keys add up to the total; level 0 holds every key
         per_level = [k for k, _ in ctx.levels()]
