@@ -63,7 +63,8 @@ typedef enum {
     BQS_ENOMEM = 3,     /* host-side allocation inside the context failed                  */
     BQS_EHIP = 4,       /* a HIP runtime call failed                                        */
     BQS_ENAN = 5,       /* a floating-point key is NaN (only with BQS_PARAM_CHECK_NAN = 1)   */
-    BQS_EOVERFLOW = 6   /* a device work list or the level cap was exceeded                 */
+    BQS_EOVERFLOW = 6,  /* a device work list or the level cap was exceeded                 */
+    BQS_ETOOBIG = 7     /* bqs_sort_noalloc: the input needs more than its fixed scratch    */
 } bqs_status;
 
 /* Tunable parameters (bqs_ctx_set_param).  Values <= 0 restore defaults. */
@@ -276,6 +277,27 @@ bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int6
  * error behaviour as for bqs_sort_segments, vals as for bqs_sort_pairs. */
 bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offsets, int64_t k,
                                    int64_t n_total, bqs_dtype key, int32_t val_bytes, bqs_ctx* ctx);
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, serving loops and harnesses that forbid allocation: bqs_sort
+ * without a caller workspace or a context.  The workspace is a fixed 64 MiB
+ * array in device memory owned by the library (one per GPU, held until the
+ * process ends), so the call allocates nothing, on the device or through
+ * any library routine, and only enqueues kernels on `hip_stream` (a
+ * hipStream_t of the current device, NULL for the null stream) with the
+ * library's default parameters.
+ *   keys, n, dtype : as for bqs_sort (keys: device pointer, n < 2^31).
+ *   status_out     : device pointer to one int32 that receives the call's
+ *                    bqs_status (BQS_OK, or a device-detected error) when
+ *                    the stream reaches the end of the sort; NULL: none.
+ * Returns BQS_ETOOBIG, with nothing enqueued, when the sort needs more than
+ * the scratch: n up to bqs_workspace_bytes(NULL, n, dtype, 0, 1) <= 64 MiB,
+ * about 15.9 million 4-byte or 7.96 million 8-byte keys.  Other argument
+ * errors as for bqs_sort.  Every call on a GPU shares that GPU's scratch
+ * (which keeps the last call's contents; every call starts by clearing what
+ * must start at zero): calls that overlap on one GPU -- on different
+ * streams, or from different threads -- race and must not be made. */
+bqs_status bqs_sort_noalloc(void* keys, int64_t n, bqs_dtype dtype, void* hip_stream, int32_t* status_out);
 
 /* The paper's large element types (Section 4, experimental setup):
  *   BQS_RECORD_VECTOR: 10 doubles (80 bytes), ordered by the sum of the

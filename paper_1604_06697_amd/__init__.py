@@ -41,6 +41,7 @@ STATUS = {
     4: "HIP runtime error",
     5: "NaN key",
     6: "device work list overflow",
+    7: "input larger than the no-allocation scratch",
 }
 
 PARAM_SMALL_CUTOFF = 1
@@ -76,7 +77,7 @@ EXPORTED = [
     "bqs_workspace_bytes",
     "bqs_sort", "bqs_sort_pairs", "bqs_sort_segments", "bqs_sort_segments_pairs",
     "bqs_records_workspace_bytes", "bqs_sort_records", "bqs_ctx_sync_status",
-    "bqs_status_str", "bqs_version",
+    "bqs_status_str", "bqs_version", "bqs_sort_noalloc",
 ]
 
 
@@ -141,6 +142,7 @@ def _load(path: str = LIBRARY) -> ctypes.CDLL:
         "bqs_ctx_sync_status": ([vp], st),
         "bqs_status_str": ([st], ctypes.c_char_p),
         "bqs_version": ([], ctypes.c_int),
+        "bqs_sort_noalloc": ([vp, i64, ctypes.c_int, vp, vp], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -397,6 +399,24 @@ def synchronize(ctx: Context | None = None):
 
 def sort(keys: torch.Tensor, ctx: Context | None = None, key_type=None) -> torch.Tensor:
     return (ctx or default_context()).sort(keys, key_type)
+
+
+def sort_noalloc(keys: torch.Tensor, status: torch.Tensor | None = None, key_type=None) -> torch.Tensor:
+    """bqs_sort_noalloc: sorts `keys` in place on the current stream without
+    any allocation (the library's fixed scratch as workspace, default
+    parameters); `status`, an int32 GPU tensor of one element, receives the
+    call's status on the device."""
+    Context._check_tensor(keys, "keys")
+    code = _key_code(keys, key_type)
+    if status is not None and (not status.is_cuda or status.dtype != torch.int32 or status.numel() < 1):
+        raise BqsError(1, "status must be an int32 GPU tensor")
+    with torch.cuda.device(keys.device):
+        stream = torch.cuda.current_stream(keys.device).cuda_stream
+        _check(lib.bqs_sort_noalloc(ctypes.c_void_p(keys.data_ptr()), keys.numel(), code,
+                                    ctypes.c_void_p(stream),
+                                    None if status is None else ctypes.c_void_p(status.data_ptr())),
+               "bqs_sort_noalloc")
+    return keys
 
 
 def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, ctx: Context | None = None, key_type=None):

@@ -27,6 +27,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -567,20 +568,20 @@ int level_cap(const Args& a) { return 4 * a.depth_limit + 64; }
 // one spare; for a new shape, an estimate from the largest possible segment
 // (about log2(n / small_cut) halvings with sampled pivots, or a quarter as
 // many sixteen-way splits) with some spare levels.
-int levels_to_enqueue(const bqs_ctx* ctx, const Args& a, const std::vector<uint64_t>& shape) {
-    int L;
-    const auto it = ctx->seen_levels.find(shape);
-    if (ctx->enqueue_levels > 0) {
-        L = static_cast<int>(std::min<int64_t>(ctx->enqueue_levels, 1 << 20));
-    } else if (it != ctx->seen_levels.end()) {
-        L = it->second + 2;
-    } else if (a.n <= a.small_cut) {
-        L = 1;
-    } else {
+int estimate_levels(const Args& a) {
+    int L = 1;
+    if (a.n > a.small_cut) {
         const double r = std::log2(static_cast<double>(a.n) / static_cast<double>(a.small_cut));
         L = a.ways ? static_cast<int>(std::ceil(r / 4.0)) + 3 : static_cast<int>(std::ceil(r)) + 5;
     }
     return std::max(1, std::min(L, level_cap(a)));
+}
+
+int levels_to_enqueue(const bqs_ctx* ctx, const Args& a, const std::vector<uint64_t>& shape) {
+    if (ctx->enqueue_levels > 0) return static_cast<int>(std::min<int64_t>(ctx->enqueue_levels, 1 << 20));
+    const auto it = ctx->seen_levels.find(shape);
+    if (it == ctx->seen_levels.end()) return estimate_levels(a);
+    return std::max(1, std::min(it->second + 2, level_cap(a)));
 }
 
 // Most segments level L can hold: k at level 0, times the fan-out per level
@@ -866,20 +867,23 @@ bqs_status run_sort(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int dty
     return run_async(ctx, o, a, segmented, dtype);
 }
 
-bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int64_t k, void* keys,
-                   void* vals, Args& a) {
+// Lays the call's buffers out in workspace [ws, ws + ws_bytes) and fills
+// the kernel arguments; `ctx` supplies the parameters (null: the library's
+// defaults).
+bqs_status prepare_in(const bqs_ctx* ctx, void* ws, size_t ws_bytes, const Ops* o, int64_t n, int dtype, int vb,
+                      int64_t k, void* keys, void* vals, Args& a) {
     const size_t kb = key_bytes(dtype);
     const int64_t S = eff_small_cut(ctx, o);
-    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S,
-                                 ctx->multiway && o->mscan);
+    const bool multiway = ctx && ctx->multiway && o->mscan;
+    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S, multiway);
     if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull)
         return BQS_EINVAL;
-    if (!ctx->ws || ctx->ws_bytes < L.total) return BQS_EINVAL;
-    if (overlaps(keys, static_cast<size_t>(n) * kb, ctx->ws, ctx->ws_bytes)) return BQS_EINVAL;
-    if (vals && (overlaps(vals, static_cast<size_t>(n) * vb, ctx->ws, ctx->ws_bytes) ||
+    if (!ws || ws_bytes < L.total) return BQS_EINVAL;
+    if (overlaps(keys, static_cast<size_t>(n) * kb, ws, ws_bytes)) return BQS_EINVAL;
+    if (vals && (overlaps(vals, static_cast<size_t>(n) * vb, ws, ws_bytes) ||
                  overlaps(vals, static_cast<size_t>(n) * vb, keys, static_cast<size_t>(n) * kb)))
         return BQS_EINVAL;
-    char* w = static_cast<char*>(ctx->ws);
+    char* w = static_cast<char*>(ws);
     a = Args{};
     a.ctl = reinterpret_cast<Ctl*>(w + L.ctl);
     a.x_keys = keys;
@@ -907,17 +911,57 @@ bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int
     a.small_cut = static_cast<int>(S);
     // default sample: 127 keys for one pivot, 255 for the multiway splitters
     // (measured on 2^28 uniform int32 keys)
-    const bool multiway = ctx->multiway && o->mscan;
-    a.sample_max = static_cast<int>(ctx->sample_max > 0 ? std::min<int64_t>(ctx->sample_max, kMaxSample)
-                                                        : (multiway ? kMaxSample : 127));
-    a.pivot_mode = static_cast<int>(ctx->pivot_mode);
-    a.pivot_skew = static_cast<int>(ctx->pivot_skew);
+    const int64_t smax = ctx ? ctx->sample_max : 0;
+    a.sample_max = static_cast<int>(smax > 0 ? std::min<int64_t>(smax, kMaxSample) : (multiway ? kMaxSample : 127));
+    a.pivot_mode = ctx ? static_cast<int>(ctx->pivot_mode) : 0;
+    a.pivot_skew = ctx ? static_cast<int>(ctx->pivot_skew) : 0;
     a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
     a.tile_keys = static_cast<int>(eff_tile_keys(ctx, o));
-    a.prof = static_cast<int>(ctx->profile);
-    a.claim = ctx->lookback ? 0 : 1;
+    a.prof = ctx ? static_cast<int>(ctx->profile) : 0;
+    a.claim = ctx && ctx->lookback ? 0 : 1;
     a.ways = multiway ? 1 : 0;
     return BQS_OK;
+}
+
+bqs_status prepare(bqs_ctx* ctx, const Ops* o, int64_t n, int dtype, int vb, int64_t k, void* keys, void* vals,
+                   Args& a) {
+    return prepare_in(ctx, ctx->ws, ctx->ws_bytes, o, n, dtype, vb, k, keys, vals, a);
+}
+
+// ---------------------------------------------------- no-allocation path --
+// bqs_sort_noalloc's workspace: a fixed array in device memory that the
+// library owns (each GPU the library runs on holds its own copy until the
+// process ends).  Host code never uses the array's name as an address: the
+// address of the current device's copy comes from hipGetSymbolAddress, once
+// per device, and is kept in noalloc_ptr.
+
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kNoAllocDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex noalloc_mu;
+void* noalloc_ptr[kNoAllocDevices] = {};
+
+// The current device's copy of the scratch array (looked up on the first
+// call on that device).
+bqs_status noalloc_scratch(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocDevices) return BQS_EHIP;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BQS_EHIP;
+        noalloc_ptr[dev] = p;
+    }
+    *out = noalloc_ptr[dev];
+    return BQS_OK;
+}
+
+// Writes the call's status (from the control block's error bits; none for
+// a trivial call) to the caller's word.
+__global__ void k_store_status(const Ctl* c, int32_t* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = static_cast<int32_t>(c ? status_of_device_error(c->error) : BQS_OK);
 }
 
 struct RecordKind {
@@ -1127,6 +1171,27 @@ bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offset
     return finish(ctx, run_sort(ctx, o, a, true, key));
 }
 
+bqs_status bqs_sort_noalloc(void* keys, int64_t n, bqs_dtype dtype, void* hip_stream, int32_t* status_out) {
+    if (n < 0 || (n > 0 && !keys)) return BQS_EINVAL;
+    const Ops* o = select_ops(nullptr, dtype, 0);
+    if (!o) return BQS_EDTYPE;
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (n <= 1) {
+        if (status_out) hipLaunchKernelGGL(k_store_status, dim3(1), dim3(64), 0, s, nullptr, status_out);
+        return hipGetLastError() == hipSuccess ? BQS_OK : BQS_EHIP;
+    }
+    if (n >= (int64_t(1) << 31)) return BQS_EINVAL;
+    if (bqs_workspace_bytes(nullptr, n, dtype, 0, 1) > kNoAllocBytes) return BQS_ETOOBIG;
+    void* ws = nullptr;
+    bqs_status st = noalloc_scratch(&ws);
+    if (st != BQS_OK) return st;
+    Args a;
+    if ((st = prepare_in(nullptr, ws, kNoAllocBytes, o, n, dtype, 0, 1, keys, nullptr, a)) != BQS_OK) return st;
+    if ((st = enqueue_levels(o, a, false, false, dtype, estimate_levels(a), s, nullptr)) != BQS_OK) return st;
+    if (status_out) hipLaunchKernelGGL(k_store_status, dim3(1), dim3(64), 0, s, a.ctl, status_out);
+    return hipGetLastError() == hipSuccess ? BQS_OK : BQS_EHIP;
+}
+
 // ------------------------------------------------------------- records --
 
 size_t bqs_records_workspace_bytes(const bqs_ctx* ctx, int64_t n, int kind) {
@@ -1205,6 +1270,7 @@ const char* bqs_status_str(bqs_status s) {
         case BQS_EHIP: return "HIP runtime error";
         case BQS_ENAN: return "NaN key";
         case BQS_EOVERFLOW: return "device work list overflow";
+        case BQS_ETOOBIG: return "input larger than the no-allocation scratch";
         default: return "unknown status";
     }
 }

@@ -18,6 +18,7 @@
 #include <cstdint>
 
 #include "bqs.h"
+#define BQS_STATUS_MAP_FN __host__ __device__ inline
 #include "bqs_status_map.h"
 
 namespace bqs {

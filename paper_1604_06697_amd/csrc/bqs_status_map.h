@@ -1,6 +1,7 @@
 // Error bits that kernels latch in the device control block, and the status
 // a call reports for them.  Plain C++ (no HIP): the host runtime and a
-// CPU-side unit test both include it.
+// CPU-side unit test both include it; the HIP sources define
+// BQS_STATUS_MAP_FN so that kernels can call the mapping too.
 #pragma once
 
 #include "bqs.h"
@@ -18,7 +19,10 @@ enum : unsigned {
 // every kernel, so they win; a NaN found by the check comes next; a stalled
 // wait means the device did not run as launched (a HIP-level failure); any
 // other bit is a work list that ran out of room.
-inline bqs_status status_of_device_error(unsigned err) {
+#ifndef BQS_STATUS_MAP_FN
+#define BQS_STATUS_MAP_FN inline
+#endif
+BQS_STATUS_MAP_FN bqs_status status_of_device_error(unsigned err) {
     if (err == 0) return BQS_OK;
     if (err & ERR_OFFSETS) return BQS_EINVAL;
     if (err & ERR_NAN) return BQS_ENAN;

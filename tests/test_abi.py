@@ -132,6 +132,12 @@ def test_argument_errors_need_no_gpu(bqs):
         assert L.bqs_ctx_set_workspace(h, ctypes.c_void_p(1 << 20), 1 << 30) == 0
         assert L.bqs_sort(ctypes.c_void_p((1 << 20) + 4096), 1000, bqs.I32, h) == 1
         assert L.bqs_ctx_set_workspace(h, None, 16) == 1
+        # the no-allocation entry point checks its arguments before any GPU call
+        assert L.bqs_sort_noalloc(None, 10, bqs.I32, None, None) == 1
+        assert L.bqs_sort_noalloc(ctypes.c_void_p(64), -5, bqs.I32, None, None) == 1
+        assert L.bqs_sort_noalloc(ctypes.c_void_p(64), 10, 42, None, None) == 2
+        assert L.bqs_sort_noalloc(ctypes.c_void_p(64), 1 << 24, bqs.I32, None, None) == 7
+        assert L.bqs_sort_noalloc(ctypes.c_void_p(64), 8_000_000, bqs.F64, None, None) == 7
     finally:
         L.bqs_ctx_destroy(h)
     L.bqs_ctx_destroy(None)
