@@ -201,6 +201,11 @@ typedef struct {
     double prof_tile_cycles;        /* tile start to tile end                                      */
     double prof_load_cycles;        /* tile start to all keys loaded and counted                   */
     int64_t graph_launches;         /* 1 if the call replayed a captured graph                     */
+    /* BQS_PARAM_PROFILE only: small segments sorted, and the shader-clock cycles of each phase of
+       the small sort, summed over segments: key load and range, bucket counts, bucket starts,
+       scatter into buckets, order inside buckets and store */
+    int64_t prof_small_segments;
+    double prof_small_cycles[5];
 } bqs_stats;
 
 typedef struct bqs_ctx bqs_ctx; /* opaque, host-side */

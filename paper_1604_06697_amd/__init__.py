@@ -29,7 +29,8 @@ import weakref
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIBRARY = os.path.join(_HERE, "libbqs.so")
+# the in-tree build; BQS_LIBRARY names another build of the same library
+LIBRARY = os.environ.get("BQS_LIBRARY") or os.path.join(_HERE, "libbqs.so")
 
 I32, U32, I64, U64, F32, F64 = 1, 2, 3, 4, 5, 6
 
@@ -108,10 +109,16 @@ class Stats(ctypes.Structure):
         ("prof_tile_cycles", ctypes.c_double),
         ("prof_load_cycles", ctypes.c_double),
         ("graph_launches", ctypes.c_int64),
+        ("prof_small_segments", ctypes.c_int64),
+        ("prof_small_cycles", ctypes.c_double * 5),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
 
 def _load(path: str = LIBRARY) -> ctypes.CDLL:
@@ -219,10 +226,11 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the exit hook has already closed every
         # context; a HIP call from here could run after the runtime is gone
-        if sys.is_finalizing():
+        # (module globals may already be gone too, hence the bound default)
+        if getattr(self, "_h", None) is None or _finalizing():
             return
         self.close()
 

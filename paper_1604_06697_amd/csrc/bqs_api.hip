@@ -59,6 +59,7 @@ __device__ void clear_ctl(Ctl* c) {
         c->levels = 0;
         c->part_keys = c->small_keys = c->fill_keys = c->tiles = 0;
         for (int i = 0; i < 8; ++i) c->prof[i] = 0;
+        for (int i = 0; i < 8; ++i) c->sprof[i] = 0;
         c->bar_arrive = 0;
         c->bar_gen = 0;
     }
@@ -474,6 +475,8 @@ void fill_stats(bqs_stats& stats, const Ctl& c) {
     stats.prof_lookback_cycles = static_cast<double>(c.prof[3]);
     stats.prof_tile_cycles = static_cast<double>(c.prof[4]);
     stats.prof_load_cycles = static_cast<double>(c.prof[5]);
+    stats.prof_small_segments = static_cast<int64_t>(c.sprof[0]);
+    for (int i = 0; i < 5; ++i) stats.prof_small_cycles[i] = static_cast<double>(c.sprof[1 + i]);
 }
 
 void latch(bqs_ctx* ctx, bqs_status st) {

@@ -101,6 +101,10 @@ struct Ctl {
     // profile counters (only with Args::prof): tiles, look-back rounds,
     // look-back polls, look-back cycles, tile cycles, load+count cycles
     unsigned long long prof[8];
+    // small-sort profile (only with Args::prof): segments, then cycles of
+    // thread 0 per phase summed over segments (load and key range, bucket
+    // counts, bucket starts, scatter, in-bucket order and store)
+    unsigned long long sprof[8];
     unsigned long long level_keys[kLevelStats];  // keys partitioned per level (statistics)
     // persistent mode: grid barrier.  Global arrivals (one per XCD) and the
     // generation that waiting workgroups poll, each on a line of its own;

@@ -110,6 +110,12 @@ __device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
     return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
 }
 
+__device__ __forceinline__ uint64_t shfl_down64(uint64_t v, int d) {
+    const int lo = __shfl_down(static_cast<int>(static_cast<uint32_t>(v)), d, 64);
+    const int hi = __shfl_down(static_cast<int>(static_cast<uint32_t>(v >> 32)), d, 64);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d) {
     const int lo = __shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), d, 64);
     const int hi = __shfl_xor(static_cast<int>(static_cast<uint32_t>(v >> 32)), d, 64);
@@ -1190,14 +1196,16 @@ struct SmallLds {
     typename ValStore<V>::type v[HV ? P : 1];
 };
 
-// The comparison sort of one segment whose keys (order keys, padding ~0 at
-// positions >= m) sit in registers in striped order, item r of thread t at
-// position r*NT + t; pairs have staged their payloads in lds.v by position.
-// Writes the sorted segment (and payloads) to dst[0, m), dv[0, m).
+// The comparison sort of one segment of m keys read from src[0, m) (pairs
+// have staged their payloads in lds.v by position).  Writes the sorted
+// segment (and payloads) to dst[0, m), dv[0, m).  Not inlined: the bucket
+// sort calls it only for crowded segments, and its registers then do not
+// weigh on the bucket sort's.
 template <int DT, class V, int E, int NT>
-__device__ void compare_sort_segment(typename SmallLds<DT, V, E, NT>::O (&key)[E], int m,
-                                     SmallLds<DT, V, E, NT>& lds, typename KeyT<DT>::raw* dst,
-                                     typename ValStore<V>::type* dv) {
+__device__ __attribute__((noinline)) void compare_sort_segment(const typename KeyT<DT>::raw* src, int m,
+                                                              SmallLds<DT, V, E, NT>& lds,
+                                                              typename KeyT<DT>::raw* dst,
+                                                              typename ValStore<V>::type* dv) {
     using K = KeyT<DT>;
     using SL = SmallLds<DT, V, E, NT>;
     using O = typename SL::O;
@@ -1206,10 +1214,12 @@ __device__ void compare_sort_segment(typename SmallLds<DT, V, E, NT>::O (&key)[E
     O* sk = lds.k;
     uint32_t* si = lds.i;
     const int t = threadIdx.x;
+    // keys in striped order (item r of thread t at position r*NT + t),
+    // padding larger than any key at positions >= m
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int x = r * NT + t;
-        sk[lds_slot<O>(x)] = key[r];
+        sk[lds_slot<O>(x)] = x < m ? K::ord(src[x]) : static_cast<O>(~O(0));
         if constexpr (HV) si[lds_slot<O>(x)] = static_cast<uint32_t>(x);
     }
     __syncthreads();
@@ -1244,48 +1254,57 @@ __device__ void compare_sort_segment(typename SmallLds<DT, V, E, NT>::O (&key)[E
 // outlook on a better recursion stopper, Section 5).
 //
 // A segment that reaches the small sort is the key range between two
-// pivots, so its keys are confined to [mn, mx] and spread over few bits.
-// One workgroup of NT threads sorts one segment of m <= E*NT keys in LDS
-// with a bucket sort on the order keys:
-//   1. keys are loaded (coalesced, striped) into registers; mn and mx are
-//      reduced across the workgroup;
-//   2. bucket b(x) = (x - mn) >> s, with s chosen so that there are at most
-//      NB = 2^ceil(log2 m) buckets (about one key per bucket);
+// pivots, so its keys are confined to [mn, mx].  One workgroup of NT
+// threads sorts one segment of m <= E*NT keys in LDS:
+//   1. keys are loaded (coalesced, striped, every load issued before any is
+//      used) into registers; mn and mx are reduced across the workgroup;
+//   2. every key goes to one of NB = 2^ceil(log2 m) buckets by a monotone
+//      map of its order key: (x - mn) itself when the range is that small
+//      (each bucket then holds one key value), else the high part of
+//      (x - mn) * M with M about NB * 2^w / (range + 1), so that the keys
+//      spread over the buckets in proportion to their values (about one
+//      key per bucket for evenly spread keys);
 //   3. bucket sizes are counted with LDS atomics (two 16-bit counters per
 //      word), turned into bucket starts by a workgroup scan, and every key is
 //      scattered to its bucket by an atomic increment of the bucket's cursor;
-//   4. if s = 0 every bucket holds one key value, so the keys are sorted
-//      (keys only); otherwise, and for pairs, every key's final rank is its
-//      bucket start plus the keys of its bucket that precede it -- smaller,
-//      or equal with a smaller tie-break (position for keys, the index in
-//      the segment for pairs, which makes the payload order deterministic:
-//      equal keys keep their input order).
+//      the keys are now ordered by bucket;
+//   4. unless every bucket holds a single key value (keys only), the keys
+//      inside each bucket are put in order by odd-even transposition rounds
+//      over the whole segment -- each thread holds E consecutive keys in
+//      registers and exchanges its edge keys with its neighbour lanes; keys
+//      of different buckets are already in order and never swap, so c rounds
+//      order every bucket of at most c keys -- and a short window around
+//      each wave boundary is ordered by rank.  Pairs order equal keys by
+//      their index in the segment, which makes the payload order
+//      deterministic (equal keys keep their input order).
 // A segment with a bucket of more than kBucketCap keys (skewed or heavily
 // duplicated keys) is sorted by the comparison sort instead (merge_sort).
 // The keys are exactly the segment's keys in ascending order either way.
 
-constexpr int kBucketCap = 32;
+constexpr int kBucketCap = 8;
 
 template <int DT, class V, int NT, int SMAX>
 struct BucketLds {
     static constexpr int E = SMAX / NT;
     using SL = SmallLds<DT, V, E, NT>;
     using O = typename SL::O;
-    SL s;                          // bucket arrays (s.k keys, s.i indexes) or the fallback's LDS
-    uint32_t hist[SMAX / 2];       // bucket counters, then cursors: 16 bits each, two per word
-    O red[2][NT / 64];             // per-wave min and max
-    uint32_t wsum[NT / 64];        // per-wave scan totals
-    uint32_t wmax[NT / 64];        // per-wave largest bucket
-    unsigned long long done;
+    SL s;                                 // bucket arrays (s.k keys, s.i indexes) or the fallback's LDS
+    uint32_t hist[SMAX / 2 + SMAX / 16];  // bucket counters, then cursors: 16 bits each, two per word (padded)
+    O red[2][NT / 64];                    // per-wave min and max
+    uint32_t wsum[NT / 64];               // per-wave scan totals
+    uint32_t wmax[NT / 64];               // per-wave largest bucket
 };
 
+template <class O>
+__device__ __forceinline__ O shfl_xor_o(O v, int d) {
+    if constexpr (sizeof(O) == 8) return shfl_xor64(v, d);
+    else return static_cast<O>(__shfl_xor(static_cast<int>(v), d, 64));
+}
 template <class O>
 __device__ __forceinline__ O wave_min(O v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
-        O o;
-        if constexpr (sizeof(O) == 8) o = shfl_xor64(v, d);
-        else o = static_cast<O>(__shfl_xor(static_cast<int>(v), d, 64));
+        const O o = shfl_xor_o(v, d);
         v = o < v ? o : v;
     }
     return v;
@@ -1294,37 +1313,81 @@ template <class O>
 __device__ __forceinline__ O wave_max(O v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
-        O o;
-        if constexpr (sizeof(O) == 8) o = shfl_xor64(v, d);
-        else o = static_cast<O>(__shfl_xor(static_cast<int>(v), d, 64));
+        const O o = shfl_xor_o(v, d);
         v = o > v ? o : v;
     }
     return v;
 }
 
+// LDS word of bucket counter pair w: one pad word per eight keeps the
+// scan's per-thread runs of consecutive words on distinct banks.
+__device__ __forceinline__ uint32_t hist_word(uint32_t w) { return w + (w >> 3); }
+
 __device__ __forceinline__ uint32_t half16(const uint32_t* h, uint32_t b) {
-    return (h[b >> 1] >> ((b & 1u) << 4)) & 0xffffu;
+    return (h[hist_word(b >> 1)] >> ((b & 1u) << 4)) & 0xffffu;
 }
 
-template <class O>
-__device__ __forceinline__ int bit_width(O x) {
-    if constexpr (sizeof(O) == 8) return x ? 64 - __clzll(static_cast<long long>(x)) : 0;
-    else return x ? 32 - __clz(static_cast<int>(x)) : 0;
+// LDS slot of position x of the bucket arrays: one pad item per sixteen.
+__device__ __forceinline__ int bslot(int x) { return x + (x >> 4); }
+
+__device__ __forceinline__ uint32_t mul_hi(uint32_t a, uint32_t b) { return __umulhi(a, b); }
+__device__ __forceinline__ uint64_t mul_hi(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// One odd-even transposition round over items held E per thread in
+// consecutive order (lane t holds positions E*t .. E*t+E-1 of its wave's
+// run): even rounds pair (2i, 2i+1) inside each thread; odd rounds pair
+// (2i+1, 2i+2) and the last item with the next lane's first.
+template <class It, int E>
+__device__ __forceinline__ void oet_round(It (&v)[E], bool odd, int lane) {
+    if (!odd) {
+#pragma unroll
+        for (int i = 0; i + 1 < E; i += 2) cx(v[i], v[i + 1]);
+    } else {
+#pragma unroll
+        for (int i = 1; i + 1 < E; i += 2) cx(v[i], v[i + 1]);
+        It up, dn;
+        if constexpr (sizeof(v[0].k) == 8) {
+            dn.k = static_cast<decltype(v[0].k)>(shfl_down64(static_cast<uint64_t>(v[0].k), 1));
+            up.k = static_cast<decltype(v[0].k)>(shfl_up64(static_cast<uint64_t>(v[E - 1].k), 1));
+        } else {
+            dn.k = static_cast<decltype(v[0].k)>(__shfl_down(static_cast<int>(v[0].k), 1, 64));
+            up.k = static_cast<decltype(v[0].k)>(__shfl_up(static_cast<int>(v[E - 1].k), 1, 64));
+        }
+        if constexpr (sizeof(It) > sizeof(v[0].k)) {
+            dn.i = static_cast<uint32_t>(__shfl_down(static_cast<int>(v[0].i), 1, 64));
+            up.i = static_cast<uint32_t>(__shfl_up(static_cast<int>(v[E - 1].i), 1, 64));
+        }
+        if (lane < 63 && item_less(dn, v[E - 1])) v[E - 1] = dn;
+        if (lane > 0 && item_less(v[0], up)) v[0] = up;
+    }
 }
 
 // Sorts one segment [lo, lo + m) of buffer `src` (payloads `vsrc`) into the
 // caller's arrays at lo (all NT threads of the workgroup).
+// With `pr` (profile mode), thread 0 adds each phase's cycles to pr[0..4].
 template <int DT, class V, int NT, int SMAX>
-__device__ void bucket_sort_segment(const Args& a, int p, int64_t lo, int m, BucketLds<DT, V, NT, SMAX>& L) {
+__device__ void bucket_sort_segment(const Args& a, int p, int64_t lo, int m, BucketLds<DT, V, NT, SMAX>& L,
+                                    unsigned long long* pr) {
+    uint64_t tp = pr ? cycles() : 0;
+    auto mark = [&](int phase) {
+        if (pr && threadIdx.x == 0) {
+            const uint64_t t = cycles();
+            pr[phase] += t - tp;
+            tp = t;
+        }
+    };
     using K = KeyT<DT>;
     using R = typename K::raw;
     using BL = BucketLds<DT, V, NT, SMAX>;
     using O = typename BL::O;
     using VS = typename ValStore<V>::type;
     constexpr bool HV = !std::is_same<V, NoVal>::value;
+    using It = SItem<O, HV>;
     constexpr int E = BL::E;
     constexpr int NW = NT / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // opaque: keeps the per-item positions from being hoisted out of the
+    // caller's loop over segments (and held in spilled registers across it)
+    const int tid = opaque(static_cast<int>(threadIdx.x)), lane = tid & 63, wv = tid >> 6;
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys) + lo;
     const VS* vsrc = static_cast<const VS*>(p ? a.y_vals : a.x_vals) + lo;
     R* xk = static_cast<R*>(a.x_keys) + lo;
@@ -1334,20 +1397,35 @@ __device__ void bucket_sort_segment(const Args& a, int p, int64_t lo, int m, Buc
     VS* sv = L.s.v;
     uint32_t* h = L.hist;
 
-    // 1. load; the key range
+    // 1. load (positions past the segment read its last key and become
+    // padding); the key range
     O key[E];
-    O mn = static_cast<O>(~O(0)), mx = 0;
+    {
+        R raw[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int x = r * NT + tid;
-        key[r] = static_cast<O>(~O(0));
-        if (x < m) {
-            key[r] = K::ord(src[x]);
-            if constexpr (HV) sv[x] = vsrc[x];
-            mn = key[r] < mn ? key[r] : mn;
-            mx = key[r] > mx ? key[r] : mx;
+        for (int r = 0; r < E; ++r) {
+            const int x = r * NT + tid;
+            raw[r] = src[x < m ? x : m - 1];
         }
+        if constexpr (HV) {
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int x = r * NT + tid;
+                if (x < m) sv[x] = vsrc[x];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < E; ++r) key[r] = K::ord(raw[r]);
     }
+    O mn = key[0], mx = key[0];  // the clamped reads repeat keys of the segment
+#pragma unroll
+    for (int r = 1; r < E; ++r) {
+        mn = key[r] < mn ? key[r] : mn;
+        mx = key[r] > mx ? key[r] : mx;
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+        if (r * NT + tid >= m) key[r] = static_cast<O>(~O(0));
     mn = wave_min(mn);
     mx = wave_max(mx);
     if (lane == 0) {
@@ -1360,12 +1438,8 @@ __device__ void bucket_sort_segment(const Args& a, int p, int64_t lo, int m, Buc
         mn = L.red[0][w] < mn ? L.red[0][w] : mn;
         mx = L.red[1][w] > mx ? L.red[1][w] : mx;
     }
+    mark(0);
     const O range = mx - mn;
-    // buckets: NB = 2^hb >= m, shift s so that (range >> s) < NB
-    const int hb = m > 1 ? 32 - __clz(m - 1) : 1;
-    const int bits = bit_width(range);
-    const int s = bits > hb ? bits - hb : 0;
-    const uint32_t nbw = ((1u << hb) + 1u) >> 1;  // words of 16-bit counters
     if (range == 0) {
         // one key value: the segment is sorted as it stands
 #pragma unroll
@@ -1378,25 +1452,52 @@ __device__ void bucket_sort_segment(const Args& a, int p, int64_t lo, int m, Buc
         }
         return;
     }
-    // 2. bucket sizes
-    for (uint32_t w = tid; w < nbw; w += NT) h[w] = 0u;
+    // 2. the bucket map: NB = 2^hb >= m buckets
+    const int hb = m > 1 ? 32 - __clz(m - 1) : 1;
+    const uint32_t NB = 1u << hb;
+    const bool exact = range < static_cast<O>(NB);
+    O M = 0;
+    if (!exact) {
+        // about NB * 2^w / (range + 1); rounding only moves bucket borders
+        // (the map stays monotone and is clamped below NB)
+        const double q = static_cast<double>(NB) * (sizeof(O) == 8 ? 18446744073709551616.0 : 4294967296.0) /
+                         (static_cast<double>(range) + 1.0);
+        const double top = sizeof(O) == 8 ? 18446744073709551615.0 : 4294967295.0;
+        M = q >= top ? static_cast<O>(~O(0)) : static_cast<O>(q);
+    }
+    auto bucket = [&](O x) -> uint32_t {
+        const O d = x - mn;
+        if (exact) return static_cast<uint32_t>(d);
+        const O b = mul_hi(d, M);
+        return b < static_cast<O>(NB - 1) ? static_cast<uint32_t>(b) : NB - 1;
+    };
+    const uint32_t nbw = (NB + 1u) >> 1;  // words of 16-bit counters
+    for (uint32_t w = tid; w < nbw; w += NT) h[hist_word(w)] = 0u;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-        const int x = r * NT + tid;
-        if (x < m) {
-            const uint32_t b = static_cast<uint32_t>((key[r] - mn) >> s);
-            atomicAdd(&h[b >> 1], 1u << ((b & 1u) << 4));
+        if (r * NT + tid < m) {
+            const uint32_t b = bucket(key[r]);
+            atomicAdd(&h[hist_word(b >> 1)], 1u << ((b & 1u) << 4));
         }
     }
     __syncthreads();
-    // 3. bucket starts: each thread scans a run of consecutive words
+    mark(1);
+    // 3. bucket starts: each thread scans a run of consecutive words (all
+    // of its words read at once)
+    constexpr int PW = SMAX / 2 / NT > 0 ? SMAX / 2 / NT : 1;  // most words per thread
     const uint32_t per = (nbw + NT - 1) / NT;
     const uint32_t w0 = tid * per;
+    uint32_t cw[PW];
     uint32_t sum = 0, big = 0;
-    for (uint32_t w = w0; w < w0 + per && w < nbw; ++w) {
-        const uint32_t c = h[w];
-        const uint32_t c0 = c & 0xffffu, c1 = c >> 16;
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+        const uint32_t w = w0 + i;
+        cw[i] = (static_cast<uint32_t>(i) < per && w < nbw) ? h[hist_word(w)] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+        const uint32_t c0 = cw[i] & 0xffffu, c1 = cw[i] >> 16;
         sum += c0 + c1;
         big = c0 > big ? c0 : big;
         big = c1 > big ? c1 : big;
@@ -1413,60 +1514,110 @@ __device__ void bucket_sort_segment(const Args& a, int p, int64_t lo, int m, Buc
         run += w < wv ? L.wsum[w] : 0u;
         maxc = L.wmax[w] > maxc ? L.wmax[w] : maxc;
     }
-    const bool rank_step = s > 0 || HV;
-    if (rank_step && maxc > static_cast<uint32_t>(kBucketCap)) {
+    const bool order_step = !exact || HV;
+    if (order_step && maxc > static_cast<uint32_t>(kBucketCap)) {
         // a crowded bucket: sort this segment by comparisons instead
-        compare_sort_segment<DT, V, E, NT>(key, m, L.s, xk, xv);
+        compare_sort_segment<DT, V, E, NT>(src, m, L.s, xk, xv);
         return;
     }
-    for (uint32_t w = w0; w < w0 + per && w < nbw; ++w) {
-        const uint32_t c = h[w];
-        const uint32_t s0 = run, s1 = run + (c & 0xffffu);
-        run = s1 + (c >> 16);
-        h[w] = s0 | (s1 << 16);
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+        const uint32_t w = w0 + i;
+        const uint32_t s0 = run, s1 = run + (cw[i] & 0xffffu);
+        run = s1 + (cw[i] >> 16);
+        if (static_cast<uint32_t>(i) < per && w < nbw) h[hist_word(w)] = s0 | (s1 << 16);
     }
     __syncthreads();
-    // 4. scatter into the buckets; afterwards each counter holds its bucket's end
+    mark(2);
+    // scatter into the buckets; each counter then holds its bucket's end
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int x = r * NT + tid;
         if (x < m) {
-            const uint32_t b = static_cast<uint32_t>((key[r] - mn) >> s);
+            const uint32_t b = bucket(key[r]);
             const uint32_t sh = (b & 1u) << 4;
-            const uint32_t pos = (atomicAdd(&h[b >> 1], 1u << sh) >> sh) & 0xffffu;
-            B[pos] = key[r];
-            if constexpr (HV) Bi[pos] = static_cast<uint32_t>(x);
+            const uint32_t pos = (atomicAdd(&h[hist_word(b >> 1)], 1u << sh) >> sh) & 0xffffu;
+            B[bslot(pos)] = key[r];
+            if constexpr (HV) Bi[bslot(pos)] = static_cast<uint32_t>(x);
         }
     }
     __syncthreads();
-    if (!rank_step) {
+    mark(3);
+    if (!order_step) {
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int x = r * NT + tid;
-            if (x < m) xk[x] = K::inv(B[x]);
+            if (x < m) xk[x] = K::inv(B[bslot(x)]);
         }
+        mark(4);
         return;
     }
-    // 5. final rank inside the bucket
-#pragma unroll 4
-    for (int r = 0; r < E; ++r) {
-        const int q = r * NT + tid;
-        if (q < m) {
-            const O o = B[q];
-            const uint32_t b = static_cast<uint32_t>((o - mn) >> s);
-            const int e = static_cast<int>(half16(h, b));
-            const int st = b ? static_cast<int>(half16(h, b - 1)) : 0;
-            const uint32_t tie = HV ? Bi[q] : static_cast<uint32_t>(q);
-            int rank = st;
-            for (int j = st; j < e; ++j) {
-                const O o2 = B[j];
-                const uint32_t t2 = HV ? Bi[j] : static_cast<uint32_t>(j);
-                rank += static_cast<int>((o2 < o) | ((o2 == o) & (t2 < tie)));
+    // 4. order inside the buckets by odd-even transposition: thread t holds
+    // positions E*t .. E*t+E-1; keys of different buckets never swap, so
+    // kBucketCap rounds order every bucket that lies inside one wave's run
+    {
+        It v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int x = E * tid + i;
+            v[i].k = x < m ? B[bslot(x)] : static_cast<O>(~O(0));
+            if constexpr (HV) v[i].i = x < m ? Bi[bslot(x)] : 0xffffffffu;
+        }
+        // a bucket of c keys is in order after c rounds
+        const int rounds = static_cast<int>(maxc);
+#pragma unroll
+        for (int r = 0; r < kBucketCap; ++r)
+            if (r < rounds) oet_round<It, E>(v, (r & 1) != 0, lane);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int x = E * tid + i;
+            if (x < m) {
+                B[bslot(x)] = v[i].k;
+                if constexpr (HV) Bi[bslot(x)] = v[i].i;
             }
-            xk[rank] = K::inv(o);
-            if constexpr (HV) xv[rank] = sv[tie];
         }
     }
+    __syncthreads();
+    {
+        // a bucket across a wave boundary lies within kBucketCap positions
+        // of it: each position of that window is ranked inside the window
+        constexpr int WIN = 2 * kBucketCap;
+        const int wb = tid / WIN, wi = tid % WIN;
+        const int b0 = (wb + 1) * 64 * E - kBucketCap;
+        const bool fix = wb < NW - 1 && b0 + wi < m;
+        It mine{};
+        int dst = 0;
+        if (fix) {
+            mine.k = B[bslot(b0 + wi)];
+            if constexpr (HV) mine.i = Bi[bslot(b0 + wi)];
+            int rank = 0;
+#pragma unroll 4
+            for (int j = 0; j < WIN; ++j) {
+                if (b0 + j < m) {
+                    It y;
+                    y.k = B[bslot(b0 + j)];
+                    if constexpr (HV) y.i = Bi[bslot(b0 + j)];
+                    rank += static_cast<int>(item_less(y, mine) | (!item_less(mine, y) & (j < wi)));
+                }
+            }
+            dst = b0 + rank;
+        }
+        __syncthreads();
+        if (fix) {
+            B[bslot(dst)] = mine.k;
+            if constexpr (HV) Bi[bslot(dst)] = mine.i;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = r * NT + tid;
+        if (x < m) {
+            xk[x] = K::inv(B[bslot(x)]);
+            if constexpr (HV) xv[x] = sv[Bi[bslot(x)]];
+        }
+    }
+    mark(4);
 }
 
 // The small sort of level `level` as workgroup `bid` of `nblk`: every
@@ -1487,6 +1638,11 @@ __device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t 
         total += cnt[k];
     }
     unsigned long long my_keys = 0;
+    // profile mode: per-phase cycles of this workgroup's segments
+    __shared__ unsigned long long s_pr[5];
+    unsigned long long* pr = a.prof ? s_pr : nullptr;
+    if (pr && threadIdx.x < 5) s_pr[threadIdx.x] = 0;
+    uint32_t nseg = 0;
     for (uint32_t it = bid; it < total; it += nblk) {
         uint32_t r = it;
         int cls = kSmallClasses - 1;
@@ -1496,18 +1652,23 @@ __device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t 
         }
         const SmallItem s = a.smalls[p][static_cast<size_t>(cls) * a.cap_small + r];
         const int m = static_cast<int>(s.hi - s.lo);
-        bucket_sort_segment<DT, V, NT, SMAX>(a, p, s.lo, m, L);
+        bucket_sort_segment<DT, V, NT, SMAX>(a, p, s.lo, m, L, pr);
         my_keys += static_cast<unsigned long long>(m);
+        ++nseg;
         __syncthreads();  // LDS is reused by the next segment
     }
     if (threadIdx.x == 0 && my_keys) atomicAdd(&c->small_keys, my_keys);
+    if (pr && threadIdx.x == 0 && nseg) {
+        atomicAdd(&c->sprof[0], static_cast<unsigned long long>(nseg));
+        for (int i = 0; i < 5; ++i) atomicAdd(&c->sprof[1 + i], s_pr[i]);
+    }
 }
 
 // One launch sorts every small segment of a level.  512-thread workgroups
-// are capped at 80 VGPRs, so that three of them fit a CU as their LDS does
-// (six waves per SIMD to hide the LDS latency).
+// get 128 VGPRs (two per CU): capped at 80 for a third one, the keys held in
+// registers spill (measured on 2^28 int32 keys: 1.23 ms against 1.53 ms).
 template <int DT, class V, int NT, int SMAX>
-__global__ __launch_bounds__(NT, NT >= 512 ? 6 : 3) void k_small(Args a) {
+__global__ __launch_bounds__(NT, NT >= 512 ? 4 : 3) void k_small(Args a) {
     __shared__ BucketLds<DT, V, NT, SMAX> s_lds;
     if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
     small_all_body<DT, V, NT, SMAX>(a, a.level, blockIdx.x, gridDim.x, s_lds);
