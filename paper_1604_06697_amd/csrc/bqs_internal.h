@@ -24,7 +24,7 @@
 namespace bqs {
 
 constexpr int kFillChunk = 4096;  // keys per fill work unit
-constexpr int kSmallClasses = 8;  // small-sort size classes: padded size 64 << c
+constexpr int kSmallClasses = 9;  // small-sort size classes: segments of at most 64 << c keys
 
 // Size class of a small segment of m >= 1 keys: the smallest c with
 // m <= 64 << c.

@@ -1621,11 +1621,15 @@ __device__ void bucket_sort_segment(const Args& a, int p, int64_t lo, int m, Buc
 }
 
 // The small sort of level `level` as workgroup `bid` of `nblk`: every
-// segment recorded for the level's small lists (all size classes, largest
-// class first, so that the long sorts start early), one per workgroup.
-template <int DT, class V, int NT, int SMAX>
+// segment recorded for the level's small lists of the size classes up to
+// small_class(SMAX) (largest class first, so that the long sorts start
+// early), one per workgroup; CLO: the smallest class taken.
+template <int DT, class V, int NT, int SMAX, int CLO = 0>
 __device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
                                BucketLds<DT, V, NT, SMAX>& L) {
+    constexpr int CHI = SMAX <= 64 ? 0 : (SMAX <= 128 ? 1 : (SMAX <= 256 ? 2 : (SMAX <= 512 ? 3 : (SMAX <= 1024 ? 4 :
+                        (SMAX <= 2048 ? 5 : (SMAX <= 4096 ? 6 : (SMAX <= 8192 ? 7 : 8)))))));
+    static_assert(CHI < kSmallClasses && CLO <= CHI, "size classes of the small lists");
     Ctl* c = a.ctl;
     const int p = level & 1;
     uint32_t cnt[kSmallClasses];
@@ -1634,7 +1638,7 @@ __device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t 
     for (int k = 0; k < kSmallClasses; ++k) {
         // a count past the capacity means an overflow was latched; only the
         // items that were written are read
-        cnt[k] = c->lc[p].smalls[k] < a.cap_small ? c->lc[p].smalls[k] : a.cap_small;
+        cnt[k] = (k < CLO || k > CHI) ? 0u : (c->lc[p].smalls[k] < a.cap_small ? c->lc[p].smalls[k] : a.cap_small);
         total += cnt[k];
     }
     unsigned long long my_keys = 0;
@@ -1645,7 +1649,7 @@ __device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t 
     uint32_t nseg = 0;
     for (uint32_t it = bid; it < total; it += nblk) {
         uint32_t r = it;
-        int cls = kSmallClasses - 1;
+        int cls = CHI;
         while (r >= cnt[cls]) {
             r -= cnt[cls];
             --cls;
@@ -1667,11 +1671,11 @@ __device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t 
 // One launch sorts every small segment of a level.  512-thread workgroups
 // get 128 VGPRs (two per CU): capped at 80 for a third one, the keys held in
 // registers spill (measured on 2^28 int32 keys: 1.23 ms against 1.53 ms).
-template <int DT, class V, int NT, int SMAX>
+template <int DT, class V, int NT, int SMAX, int CLO>
 __global__ __launch_bounds__(NT, NT >= 512 ? 4 : 3) void k_small(Args a) {
     __shared__ BucketLds<DT, V, NT, SMAX> s_lds;
     if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
-    small_all_body<DT, V, NT, SMAX>(a, a.level, blockIdx.x, gridDim.x, s_lds);
+    small_all_body<DT, V, NT, SMAX, CLO>(a, a.level, blockIdx.x, gridDim.x, s_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1885,7 +1889,7 @@ __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
 
 // ---------------------------------------------------------------------------
 // Host-side launchers for one (dtype, payload, tile shape).  SMAX is the
-// largest small segment (a power of two between 64 and 8192).
+// largest small segment (a power of two between 64 and 16384).
 
 }  // namespace bqs
 
@@ -1946,10 +1950,18 @@ struct Launch {
         hipLaunchKernelGGL((k_complete<V>), dim3(grid), dim3(256), 0, s, a);
     }
     // small sort: 16 keys per thread (8 for pairs of 2048 keys), at least
-    // 256 threads
-    static constexpr int kSmallThreads = SMAX / 16 < 256 ? 256 : SMAX / 16;
+    // 256 threads.  Cutoffs past 8192 keys get a second launch for the
+    // largest class, on 1024 threads (one workgroup per CU), so that the
+    // smaller segments keep workgroups of 512 threads (two per CU).
+    static constexpr int kSmallMain = SMAX > 8192 ? 8192 : SMAX;
+    static constexpr int kSmallThreads = kSmallMain / 16 < 256 ? 256 : kSmallMain / 16;
     static void small(const Args& a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_small<DT, V, kSmallThreads, SMAX>), dim3(grid), dim3(kSmallThreads), 0, s, a);
+        hipLaunchKernelGGL((k_small<DT, V, kSmallThreads, kSmallMain, 0>), dim3(grid), dim3(kSmallThreads), 0, s,
+                           a);
+        if constexpr (SMAX > 8192) {
+            static_assert(SMAX == 16384, "one class past 8192 keys");
+            hipLaunchKernelGGL((k_small<DT, V, 1024, SMAX, 8>), dim3(grid), dim3(1024), 0, s, a);
+        }
     }
     static void map(const Args& a, int grid, hipStream_t s) { launch_map(a, grid, s); }
     // persistent mode: small segments up to 4096 keys (the classes whose

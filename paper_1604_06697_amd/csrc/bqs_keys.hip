@@ -5,7 +5,7 @@ namespace bqs {
 
 namespace {
 template <int DT, int EPT>
-using Keys4 = Launch<DT, NoVal, 256, EPT, 8192>;  // 4-byte keys: 32 KB small-sort LDS
+using Keys4 = Launch<DT, NoVal, 256, EPT, 16384>;  // 4-byte keys: small segments up to 16384 keys
 template <int DT>
 using Keys8 = Launch<DT, NoVal, 256, 16, 4096>;   // 8-byte keys: 32 KB small-sort LDS
 
