@@ -625,7 +625,11 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
         // previous level's children
         const uint64_t small_items = L ? sb_prev * (a.ways ? 16 : 2) : std::max<uint64_t>(a.k, 1);
         if (tm) tm->start_aux();
-        (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(std::max<uint64_t>((sb + 3) / 4, fill_units), 2048), s);
+        // (two-way plan: about 64 tile descriptors per workgroup on the
+        // first levels, whose few segments have many tiles each)
+        const uint64_t plan_wgs = std::max<uint64_t>(std::max<uint64_t>((sb + 3) / 4, fill_units),
+                                                     a.ways ? 0 : tile_bound(a, L) / 64);
+        (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(plan_wgs, 2048), s);
         if (a.ways) o->map(a, clamp_grid((tile_bound(a, L) + 255) / 256, 4096), s);
         if (tm) tm->stop_aux(0, L);
         if (tm) tm->start_aux();
@@ -778,7 +782,9 @@ bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int d
         // plan: one wave per segment (4 per workgroup), one workgroup per
         // fill chunk (the two-way plan also writes the tile descriptors; the
         // multiway levels map tiles to segments in a launch of their own)
-        (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(std::max<uint64_t>((nseg + 3) / 4, nchunk), 16384), s);
+        const uint64_t plan_wgs = std::max<uint64_t>(std::max<uint64_t>((nseg + 3) / 4, nchunk),
+                                                     a.ways ? 0 : ntile / 64);
+        (a.ways ? o->plan_multi : o->plan)(a, clamp_grid(plan_wgs, 16384), s);
         if (nseg && a.ways) o->map(a, clamp_grid((ntile + 255) / 256, 4096), s);
         tm.stop_aux(0, L);
         uint32_t nsmall = 0;

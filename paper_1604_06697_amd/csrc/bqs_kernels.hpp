@@ -122,6 +122,18 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d) {
     return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
 }
 
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
+    const int lo = __shfl(static_cast<int>(static_cast<uint32_t>(v)), src, 64);
+    const int hi = __shfl(static_cast<int>(static_cast<uint32_t>(v >> 32)), src, 64);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+template <class O>
+__device__ __forceinline__ O shfl_xor_o(O v, int d) {
+    if constexpr (sizeof(O) == 8) return shfl_xor64(v, d);
+    else return static_cast<O>(__shfl_xor(static_cast<int>(v), d, 64));
+}
+
 // `lane` is passed in so that callers inside loops can hand over an opaque
 // copy: otherwise the six lane >= d masks are hoisted out of the loop and
 // held in scalar registers across it.
@@ -360,14 +372,139 @@ __device__ inline PivotPlan pivot_plan(const Args& a, int64_t m, uint32_t depth)
     return pp;
 }
 
-// The plan step as workgroup `bid` of `nblk` (all NT threads).
+// Element of rank `target` among the 256 order keys a wave holds, four per
+// lane (lane l holds positions 4l .. 4l+3): a bitonic sorting network over
+// the wave -- partners two or one apart inside a lane's registers, farther
+// ones in other lanes (lane xor) -- then the element at position `target`.
+template <class O>
+__device__ __forceinline__ O wave_rank_select(O (&v)[4], int target, int lane) {
+#pragma unroll
+    for (int size = 2; size <= 256; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride < 4) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int pr = r ^ stride;
+                    if (pr > r) {
+                        const bool up = ((4 * lane + r) & size) == 0;
+                        const O x = v[r], y = v[pr];
+                        const O lo = x < y ? x : y, hi = x < y ? y : x;
+                        v[r] = up ? lo : hi;
+                        v[pr] = up ? hi : lo;
+                    }
+                }
+            } else {
+                const int d = stride >> 2;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int pos = 4 * lane + r;
+                    const O other = shfl_xor_o(v[r], d);
+                    const bool keep_small = ((pos & stride) == 0) == ((pos & size) == 0);
+                    v[r] = keep_small ? (other < v[r] ? other : v[r]) : (other > v[r] ? other : v[r]);
+                }
+            }
+        }
+    }
+    const int r = target & 3;
+    const O mine = r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3]));
+    if constexpr (sizeof(O) == 8) return static_cast<O>(bcast64(static_cast<uint64_t>(mine), target >> 2));
+    else return static_cast<O>(__shfl(static_cast<int>(mine), target >> 2, 64));
+}
+
+// The pivot of segment [lo, hi) at recursion depth `depth`, picked by wave
+// wv of the workgroup from its own sample (all NT threads call this together:
+// it holds workgroup barriers; `valid` false: the wave has no segment).
+template <int DT, int NT>
+__device__ typename KeyT<DT>::raw segment_pivot(const Args& a, const typename KeyT<DT>::raw* src, int64_t lo,
+                                                int64_t hi, uint32_t depth, bool valid, PlanLds<DT, NT>& lds) {
+    using K = KeyT<DT>;
+    using R = typename K::raw;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    using O = decltype(K::ord(R()));
+    R* ws = lds.samp[wv];
+    const int64_t m = hi - lo;
+    const PivotPlan pp = valid ? pivot_plan(a, m, depth) : PivotPlan{0, 0, 0};
+    const int k = pp.k;
+    // sample i sits in stratum i at a hashed offset (first, middle and
+    // last key for the median of three)
+    auto sample_pos = [&](int i) -> int64_t {
+        if (k == 3 && pp.g == 0) return i == 0 ? lo : (i == 1 ? lo + m / 2 : hi - 1);
+        const int64_t stride = m / k;
+        const uint64_t h = mix64((static_cast<uint64_t>(lo) * 0x9e3779b97f4a7c15ull) ^
+                                 (static_cast<uint64_t>(hi) << 17) ^ (static_cast<uint64_t>(i) << 40) ^ depth);
+        return lo + i * stride + static_cast<int64_t>(h % static_cast<uint64_t>(stride));
+    };
+    if (pp.g == 0) {
+        // one sample: sorted in registers across the wave; the pick is the
+        // key of the target rank
+        O v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 4 * lane + r;
+            v[r] = i < k ? K::ord(src[sample_pos(i)]) : static_cast<O>(~O(0));
+        }
+        const O pick = wave_rank_select(v, valid ? pp.rk : 0, lane);
+        // the workgroup's barriers stay the same for every wave (a wave with
+        // medians of medians may share the workgroup)
+        __syncthreads();
+        __syncthreads();
+        __syncthreads();
+        __syncthreads();
+        return K::inv(pick);
+    }
+    for (int i = lane; i < k; i += 64) ws[i] = src[sample_pos(i)];
+    __syncthreads();
+    // medians of medians: lane t takes the median of group t
+    if (pp.g > 0 && lane < k / pp.g) {
+        const R* grp = ws + lane * pp.g;
+        R med = grp[0];
+        for (int i = 0; i < pp.g; ++i) {
+            const auto om = K::ord(grp[i]);
+            int rank = 0;
+            for (int j = 0; j < pp.g; ++j) {
+                const auto oj = K::ord(grp[j]);
+                rank += (oj < om) | ((oj == om) & (j < i));
+            }
+            if (rank == pp.g / 2) med = grp[i];
+        }
+        lds.grp[wv][lane] = med;
+    }
+    __syncthreads();
+    // the pick: the candidate of the target rank (ties broken by index)
+    const R* cand = pp.g > 0 ? lds.grp[wv] : ws;
+    const int kc = pp.g > 0 ? k / pp.g : k;
+    const int target = pp.g > 0 ? kc / 2 : pp.rk;
+    for (int i = lane; i < kc; i += 64) {
+        const R mine = cand[i];
+        const auto om = K::ord(mine);
+        int rank = 0;
+#pragma unroll 8
+        for (int j = 0; j < kc; ++j) {
+            const auto oj = K::ord(cand[j]);
+            rank += (oj < om) | ((oj == om) & (j < i));
+        }
+        if (rank == target) lds.pick[wv] = mine;
+    }
+    __syncthreads();
+    const R piv = lds.pick[wv];
+    __syncthreads();  // lds is free for the next call
+    return piv;
+}
+
+// The plan step as workgroup `bid` of `nblk` (all NT threads).  Each
+// segment's pivot goes into its descriptor and into the descriptors of its
+// tiles (and the tiles' look-back words are cleared).  With at least two
+// workgroups per segment (the first levels) the workgroups of a segment each
+// pick its pivot -- the pick is deterministic -- and write a share of its
+// tile descriptors, so that a segment of many tiles is not left to one
+// wave; otherwise one wave per segment.
 template <int DT, class V, int NT>
 __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk, PlanLds<DT, NT>& lds) {
     using K = KeyT<DT>;
     using R = typename K::raw;
     constexpr int NW = NT / 64;  // one wave per segment
     static_assert(kMaxSample < 4 * 64, "a lane holds at most four samples");
-    auto& s_pick = lds.pick;
 
     Ctl* c = a.ctl;
     const int p = level & 1, q = p ^ 1;
@@ -376,96 +513,69 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
     reset_next_slot(c, q, nseg, bid);
     if (nseg > a.cap_seg) nseg = a.cap_seg;  // an overflow was latched
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
-    R* ws = lds.samp[wv];
 
-    // block-uniform trip count (the barriers below); wave wv takes segment base + wv
-    for (uint32_t base = bid * NW; base < nseg; base += nblk * NW) {
-        const uint32_t si = base + wv;
-        const bool valid = si < nseg;
-        SegDesc* sd = &a.segs[p][valid ? si : 0];
-        int64_t lo = 0, hi = 0, m = 0;
-        uint32_t depth = 0, t0 = 0, nt = 0;
-        PivotPlan pp{0, 0, 0};
-        if (valid) {
-            lo = sd->lo;
-            hi = sd->hi;
-            m = hi - lo;
-            depth = sd->depth;
-            t0 = sd->t0;
-            nt = sd->nt;
-            pp = pivot_plan(a, m, depth);
-        }
-        const int k = pp.k;
-        // sample i sits in stratum i at a hashed offset (first, middle and
-        // last key for the median of three)
-        for (int i = lane; i < k; i += 64) {
-            int64_t pos;
-            if (k == 3 && pp.g == 0) {
-                pos = i == 0 ? lo : (i == 1 ? lo + m / 2 : hi - 1);
-            } else {
-                const int64_t stride = m / k;
-                const uint64_t h = mix64((static_cast<uint64_t>(lo) * 0x9e3779b97f4a7c15ull) ^
-                                         (static_cast<uint64_t>(hi) << 17) ^
-                                         (static_cast<uint64_t>(i) << 40) ^ depth);
-                pos = lo + i * stride + static_cast<int64_t>(h % static_cast<uint64_t>(stride));
-            }
-            ws[i] = src[pos];
-        }
-        __syncthreads();
-        // medians of medians: lane t takes the median of group t
-        if (pp.g > 0 && lane < k / pp.g) {
-            const R* grp = ws + lane * pp.g;
-            R med = grp[0];
-            for (int i = 0; i < pp.g; ++i) {
-                const auto om = K::ord(grp[i]);
-                int rank = 0;
-                for (int j = 0; j < pp.g; ++j) {
-                    const auto oj = K::ord(grp[j]);
-                    rank += (oj < om) | ((oj == om) & (j < i));
-                }
-                if (rank == pp.g / 2) med = grp[i];
-            }
-            lds.grp[wv][lane] = med;
-        }
-        __syncthreads();
-        // the pick: the candidate of the target rank (ties broken by index)
-        const R* cand = pp.g > 0 ? lds.grp[wv] : ws;
-        const int kc = pp.g > 0 ? k / pp.g : k;
-        const int target = pp.g > 0 ? kc / 2 : pp.rk;
-        for (int i = lane; i < kc; i += 64) {
-            const R mine = cand[i];
-            const auto om = K::ord(mine);
-            int rank = 0;
-#pragma unroll 8
-            for (int j = 0; j < kc; ++j) {
-                const auto oj = K::ord(cand[j]);
-                rank += (oj < om) | ((oj == om) & (j < i));
-            }
-            if (rank == target) s_pick[wv] = mine;
-        }
-        __syncthreads();
-        if (valid) {
-            const R piv = s_pick[wv];
-            if (lane == 0) {
-                sd->pivot = static_cast<uint64_t>(K::ord(piv));
+    if (nseg > 0 && 2 * nseg <= nblk) {
+        const uint32_t parts = nblk / nseg;
+        const uint32_t si = bid % nseg, part = bid / nseg;
+        if (part < parts) {
+            SegDesc* sd = &a.segs[p][si];
+            const int64_t lo = sd->lo, hi = sd->hi;
+            const uint32_t t0 = sd->t0, nt = sd->nt;
+            // every wave picks the same pivot; wave 0's is used
+            const R piv = segment_pivot<DT, NT>(a, src, lo, hi, sd->depth, true, lds);
+            const uint64_t po = static_cast<uint64_t>(K::ord(piv));
+            if (part == 0 && tid == 0) {
+                sd->pivot = po;
                 sd->pivot_raw = static_cast<uint64_t>(piv);
                 sd->cursor = 0;
             }
-            // the segment's tile descriptors (and cleared look-back words):
-            // the wave that knows the pivot writes them, so no separate map
-            // step has to find each tile's segment
             TileDesc d;
             d.lo = lo;
             d.hi = hi;
-            d.pivot = static_cast<uint64_t>(K::ord(piv));
+            d.pivot = po;
             d.t0 = t0;
             d.si = si;
-            for (uint32_t j = lane; j < nt; j += 64) {
+            const uint32_t j0 = static_cast<uint32_t>(static_cast<uint64_t>(nt) * part / parts);
+            const uint32_t j1 = static_cast<uint32_t>(static_cast<uint64_t>(nt) * (part + 1) / parts);
+            for (uint32_t j = j0 + tid; j < j1; j += NT) {
                 a.tile_desc[t0 + j] = d;
                 a.status[t0 + j] = 0;
             }
         }
-        __syncthreads();
+    } else {
+        // block-uniform trip count (the barriers inside); wave wv takes segment base + wv
+        for (uint32_t base = bid * NW; base < nseg; base += nblk * NW) {
+            const uint32_t si = base + wv;
+            const bool valid = si < nseg;
+            SegDesc* sd = &a.segs[p][valid ? si : 0];
+            int64_t lo = 0, hi = 0;
+            uint32_t depth = 0, t0 = 0, nt = 0;
+            if (valid) {
+                lo = sd->lo;
+                hi = sd->hi;
+                depth = sd->depth;
+                t0 = sd->t0;
+                nt = sd->nt;
+            }
+            const R piv = segment_pivot<DT, NT>(a, src, lo, hi, depth, valid, lds);
+            if (valid) {
+                if (lane == 0) {
+                    sd->pivot = static_cast<uint64_t>(K::ord(piv));
+                    sd->pivot_raw = static_cast<uint64_t>(piv);
+                    sd->cursor = 0;
+                }
+                TileDesc d;
+                d.lo = lo;
+                d.hi = hi;
+                d.pivot = static_cast<uint64_t>(K::ord(piv));
+                d.t0 = t0;
+                d.si = si;
+                for (uint32_t j = lane; j < nt; j += 64) {
+                    a.tile_desc[t0 + j] = d;
+                    a.status[t0 + j] = 0;
+                }
+            }
+        }
     }
 
     run_fills<DT, V, NT>(a, p, bid, nblk);
@@ -828,11 +938,6 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
 // every tile's claim and output is visible.  Appends are aggregated per wave:
 // a wave prefix sum of the lanes' requests, one atomic add per wave and list.
 
-__device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
-    const int lo = __shfl(static_cast<int>(static_cast<uint32_t>(v)), src, 64);
-    const int hi = __shfl(static_cast<int>(static_cast<uint32_t>(v >> 32)), src, 64);
-    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
-}
 
 // All 64 lanes: lane's first slot of a wave-wide append of `inc` to *ctr.
 __device__ __forceinline__ uint64_t wave_append(unsigned long long* ctr, uint64_t inc, int lane) {
@@ -1295,11 +1400,6 @@ struct BucketLds {
     uint32_t wmax[NT / 64];               // per-wave largest bucket
 };
 
-template <class O>
-__device__ __forceinline__ O shfl_xor_o(O v, int d) {
-    if constexpr (sizeof(O) == 8) return shfl_xor64(v, d);
-    else return static_cast<O>(__shfl_xor(static_cast<int>(v), d, 64));
-}
 template <class O>
 __device__ __forceinline__ O wave_min(O v) {
 #pragma unroll
