@@ -26,8 +26,12 @@
  *     Device-detected errors (a work list overflowing its capacity, a
  *     malformed offsets array, a NaN key in check mode, a device-side wait
  *     that gave up) are latched in the context when the call has completed
- *     and are returned by bqs_ctx_sync_status() (and, in BQS_MODE_LEVELS,
- *     by the call itself).
+ *     and are returned by bqs_ctx_sync_status(); in BQS_MODE_LEVELS the
+ *     call itself returns them instead.  Once a kernel has latched such an
+ *     error, the call's later kernels do nothing: the keys (and payloads)
+ *     are then in an unspecified state, except after malformed offsets or
+ *     a NaN found by check mode, which are detected before anything moves
+ *     and leave them as they were.
  *   - Keys are 1-D and contiguous.  Integer keys use their usual order;
  *     float keys use IEEE-754 totalOrder restricted to non-NaN values, so
  *     -0.0 sorts before +0.0.  NaN keys violate the precondition (their
@@ -53,7 +57,12 @@ typedef enum {
     BQS_I64 = 3,
     BQS_U64 = 4,
     BQS_F32 = 5,
-    BQS_F64 = 6
+    BQS_F64 = 6,
+    /* Not dtypes: these two widen the enum's range to every int, so an
+       out-of-range value from a caller is a defined value that the library
+       rejects with BQS_EDTYPE. */
+    BQS_DTYPE_RANGE_MIN_ = -0x7fffffff - 1,
+    BQS_DTYPE_RANGE_MAX_ = 0x7fffffff
 } bqs_dtype;
 
 typedef enum {
@@ -64,7 +73,10 @@ typedef enum {
     BQS_EHIP = 4,       /* a HIP runtime call failed                                        */
     BQS_ENAN = 5,       /* a floating-point key is NaN (only with BQS_PARAM_CHECK_NAN = 1)   */
     BQS_EOVERFLOW = 6,  /* a device work list or the level cap was exceeded                 */
-    BQS_ETOOBIG = 7     /* bqs_sort_noalloc: the input needs more than its fixed scratch    */
+    BQS_ETOOBIG = 7,    /* bqs_sort_noalloc: the input needs more than its fixed scratch    */
+    /* Not statuses: they widen the enum's range to every int (see bqs_dtype). */
+    BQS_STATUS_RANGE_MIN_ = -0x7fffffff - 1,
+    BQS_STATUS_RANGE_MAX_ = 0x7fffffff
 } bqs_status;
 
 /* Tunable parameters (bqs_ctx_set_param).  Values <= 0 restore defaults. */
@@ -106,6 +118,18 @@ typedef enum {
                                    last completed call of the same shape needed plus one, or an
                                    estimate).  The result is the same for any value; small
                                    values leave more of the recursion to the tail              */
+    BQS_PARAM_DEPTH_LIMIT = 15, /* recursion depth past which every pivot is the median of the
+                                   largest sample (0: the paper's 2 floor(log2 n) + 3, Section 2);
+                                   the level cap is 4 times this plus 64                        */
+    BQS_PARAM_LIST_CAP = 16,    /* stress test: at most this many entries in each per-level work
+                                   list (segments, small segments, equal runs; 0: sized for n).
+                                   A recursion that needs more latches BQS_EOVERFLOW; nothing is
+                                   written past a list                                          */
+    BQS_PARAM_SHUFFLE = 17,     /* stress test of the decoupled look-back (BQS_MODE_ASYNC and
+                                   BQS_MODE_LEVELS): partition tiles take their tiles in reverse
+                                   order within each window of 64 tickets and pause a
+                                   pseudo-random time before publishing their status.  Results
+                                   are identical                                                */
     BQS_PARAM_CHECK_NAN = 13,   /* 1: float keys are checked for NaN (one extra read of the keys)
                                    before the sort; a NaN is reported as BQS_ENAN and the keys
                                    are then in an unspecified order.  The sort's precondition

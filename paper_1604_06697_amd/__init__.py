@@ -59,6 +59,9 @@ PARAM_MULTIWAY = 11
 PARAM_PIVOT_SKEW = 12
 PARAM_CHECK_NAN = 13
 PARAM_ENQUEUE_LEVELS = 14
+PARAM_DEPTH_LIMIT = 15
+PARAM_LIST_CAP = 16
+PARAM_SHUFFLE = 17
 RECORD_VECTOR, RECORD_RECORD = 1, 2
 MODE_ASYNC, MODE_LEVELS, MODE_PERSISTENT = 0, 1, 2
 
@@ -249,6 +252,9 @@ class Context:
         "pivot_skew": PARAM_PIVOT_SKEW,
         "check_nan": PARAM_CHECK_NAN,
         "enqueue_levels": PARAM_ENQUEUE_LEVELS,
+        "depth_limit": PARAM_DEPTH_LIMIT,
+        "list_cap": PARAM_LIST_CAP,
+        "shuffle": PARAM_SHUFFLE,
     }
 
     def set_param(self, name: str, value: int):

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_init_segments(Args a) {
 // segment list is ordered by first tile) and writes the tile descriptor;
 // it also clears the tile's look-back status word.
 __global__ __launch_bounds__(256) void k_map(Args a) {
-    if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
+    if (a.ctl->error) return;  // an earlier step latched an error: the rest of the call does nothing
     map_tiles(a, a.level, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
@@ -304,6 +304,9 @@ struct bqs_ctx {
     int64_t multiway = 0;   // 1: keys-only levels split around up to 15 splitters
     int64_t check_nan = 0;  // 1: floating-point keys are checked for NaN first
     int64_t enqueue_levels = 0;  // > 0: levels enqueued before the tail launch
+    int64_t depth_limit = 0;     // > 0: replaces 2 floor(log2 n) + 3
+    int64_t list_cap = 0;        // > 0: caps the per-level list capacities (stress test)
+    int64_t shuffle = 0;         // 1: out-of-order tile claims and delayed look-back publication
     // graph mode: the captured launch sequence and the call shape it belongs to
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph_obj = nullptr;
@@ -552,7 +555,9 @@ std::vector<uint64_t> call_shape(const Ops* o, const Args& a, bool segmented) {
     return {u(o), static_cast<uint64_t>(a.n), static_cast<uint64_t>(a.k), static_cast<uint64_t>(a.small_cut),
             static_cast<uint64_t>(a.sample_max), static_cast<uint64_t>(a.pivot_mode),
             static_cast<uint64_t>(a.pivot_skew), static_cast<uint64_t>(a.tile_keys), static_cast<uint64_t>(a.prof),
-            static_cast<uint64_t>(a.claim), static_cast<uint64_t>(a.ways), segmented ? 1ull : 0ull};
+            static_cast<uint64_t>(a.claim), static_cast<uint64_t>(a.ways), static_cast<uint64_t>(a.depth_limit),
+            static_cast<uint64_t>(a.shuffle), static_cast<uint64_t>(a.cap_seg), static_cast<uint64_t>(a.cap_small),
+            segmented ? 1ull : 0ull};
 }
 
 // Graph key: the shape plus the buffers the launches were captured with.
@@ -924,7 +929,17 @@ bqs_status prepare_in(const bqs_ctx* ctx, void* ws, size_t ws_bytes, const Ops* 
     a.sample_max = static_cast<int>(smax > 0 ? std::min<int64_t>(smax, kMaxSample) : (multiway ? kMaxSample : 127));
     a.pivot_mode = ctx ? static_cast<int>(ctx->pivot_mode) : 0;
     a.pivot_skew = ctx ? static_cast<int>(ctx->pivot_skew) : 0;
-    a.depth_limit = static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
+    a.depth_limit = ctx && ctx->depth_limit > 0 ? static_cast<int>(std::min<int64_t>(ctx->depth_limit, 1 << 20))
+                                                : static_cast<int>(2 * floor_log2(std::max<int64_t>(n, 2)) + 3);
+    a.shuffle = ctx && ctx->shuffle ? 1 : 0;
+    if (ctx && ctx->list_cap > 0) {
+        // smaller lists inside the same layout: a recursion that needs more
+        // room latches an overflow
+        const uint32_t c = static_cast<uint32_t>(std::min<int64_t>(ctx->list_cap, 0x7fffffff));
+        a.cap_seg = std::min(a.cap_seg, c);
+        a.cap_small = std::min(a.cap_small, c);
+        a.cap_fill = std::min(a.cap_fill, c);
+    }
     a.tile_keys = static_cast<int>(eff_tile_keys(ctx, o));
     a.prof = ctx ? static_cast<int>(ctx->profile) : 0;
     a.claim = ctx && ctx->lookback ? 0 : 1;
@@ -986,8 +1001,10 @@ bool record_kind(int kind, RecordKind& rk) {
 size_t record_head(int64_t n, const RecordKind& rk) {
     return align_up(static_cast<size_t>(n) * key_bytes(rk.key_dtype)) + align_up(static_cast<size_t>(n) * 4);
 }
+// A call's own status is returned, not latched: the latch holds what the
+// device found after the call returned.
 bqs_status finish(bqs_ctx* ctx, bqs_status st) {
-    latch(ctx, st);
+    (void)ctx;
     return st;
 }
 
@@ -1067,6 +1084,18 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             ctx->enqueue_levels = value;
             drop_graph(ctx);
             break;
+        case BQS_PARAM_DEPTH_LIMIT:
+            ctx->depth_limit = value;
+            drop_graph(ctx);
+            break;
+        case BQS_PARAM_LIST_CAP:
+            ctx->list_cap = value;
+            drop_graph(ctx);
+            break;
+        case BQS_PARAM_SHUFFLE:
+            ctx->shuffle = value ? 1 : 0;
+            drop_graph(ctx);
+            break;
         case BQS_PARAM_MODE:
             if (value != BQS_MODE_ASYNC && value != BQS_MODE_LEVELS && value != BQS_MODE_PERSISTENT)
                 return BQS_EINVAL;
@@ -1095,6 +1124,9 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_MULTIWAY: return ctx->multiway;
         case BQS_PARAM_CHECK_NAN: return ctx->check_nan;
         case BQS_PARAM_ENQUEUE_LEVELS: return ctx->enqueue_levels;
+        case BQS_PARAM_DEPTH_LIMIT: return ctx->depth_limit;
+        case BQS_PARAM_LIST_CAP: return ctx->list_cap;
+        case BQS_PARAM_SHUFFLE: return ctx->shuffle;
         default: return -1;
     }
 }

@@ -111,6 +111,7 @@ struct Ctl {
     // arrivals per XCD (one line each); resident workgroups per XCD.
     alignas(256) unsigned int bar_arrive;
     alignas(256) unsigned int bar_gen;
+    unsigned int bar_err;  // `error` as it stood when the current barrier generation opened
     alignas(256) unsigned int xcd_arrive[kMaxXcd][64];
     unsigned int xcd_n[kMaxXcd];
 };
@@ -142,6 +143,7 @@ struct Args {
     int claim;  // 1: keys-only tiles claim their ranges with the segment's cursor
     int ways;   // 1: multiway partition levels (keys only)
     int retile; // 1: the first level's segments were tiled for another tile size (tail kernel)
+    int shuffle; // stress test: tiles claimed out of order within windows of 64, delayed publication
     uint64_t* splitters[2];  // per slot: 16 order keys per segment
     uint32_t* toff;          // per tile: offset of its keys inside each bucket
     uint32_t* bcur;          // per segment: bucket cursors (stride 32)

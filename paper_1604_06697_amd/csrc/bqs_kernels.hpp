@@ -584,7 +584,7 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
 template <int DT, class V, int NT>
 __global__ __launch_bounds__(NT) void k_plan(Args a) {
     __shared__ PlanLds<DT, NT> s_lds;
-    if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
+    if (a.ctl->error) return;  // an earlier step latched an error: the rest of the call does nothing
     plan_body<DT, V, NT>(a, a.level, blockIdx.x, gridDim.x, s_lds);
 }
 
@@ -614,6 +614,7 @@ struct TileIO {
     int64_t lo, hi;
     uint64_t pivot;
     uint32_t j;
+    uint32_t delay;  // stress test: sleep this many short periods before publishing the look-back status
 };
 
 struct TileOut {
@@ -774,6 +775,7 @@ __device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned lon
         } else if (j == 0) {
             if (lane == 0) st_status(st_me, st_pack(kStInc, nlt, ngt));
         } else {
+            for (uint32_t d = 0; d < io.delay; ++d) __builtin_amdgcn_s_sleep(16);
             if (lane == 0) st_status(st_me, st_pack(kStAgg, nlt, ngt));
             int64_t pos = static_cast<int64_t>(j) - 1;
             const unsigned long long t_wait = wall_clock64();
@@ -871,7 +873,8 @@ __device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned lon
 // segment, buffers and claim form, then the partition.
 template <int DT, class V, int NT, int EPT>
 __device__ __forceinline__ void tile_body(const Args& a, int level, uint32_t tile, const TileDesc& td,
-                                          TileLds<DT, V, NT, EPT>& lds, unsigned long long* s_prof) {
+                                          TileLds<DT, V, NT, EPT>& lds, unsigned long long* s_prof,
+                                          uint32_t delay = 0) {
     Ctl* c = a.ctl;
     const int p = level & 1;
     const int tid = threadIdx.x;
@@ -892,6 +895,7 @@ __device__ __forceinline__ void tile_body(const Args& a, int level, uint32_t til
     io.hi = td.hi;
     io.pivot = td.pivot;
     io.j = tile - td.t0;
+    io.delay = delay;
     const TileOut r = tile_partition<DT, V, NT, EPT>(io, s_prof, lds);
     if (!r.ok && tid == 0) atomicOr(&c->error, ERR_OVERFLOW);  // inconsistent claim: nothing was written
 }
@@ -912,10 +916,18 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     if (ntiles > a.cap_tile) ntiles = a.cap_tile;  // an overflow was latched
     // a launch may cover more workgroups than the level has tiles (a grid
     // fixed in advance); the surplus leaves before taking a ticket
-    if (blockIdx.x >= ntiles || (c->error & ERR_OFFSETS)) return;
+    if (blockIdx.x >= ntiles || c->error) return;  // (an error latched by an earlier step: nothing runs)
     if (a.prof && tid < 6) s_prof[tid] = 0;
     if (tid == 0) {
-        const uint32_t t = atomicAdd(&c->lc[p].tile_next, 1u);
+        uint32_t t = atomicAdd(&c->lc[p].tile_next, 1u);
+        if (a.shuffle && t < ntiles) {
+            // stress test: tiles of each window of 64 tickets in reverse
+            // order, so look-backs wait on tiles claimed after them (each
+            // waits only inside its window, which the GPU holds at once)
+            const uint32_t base = t & ~63u;
+            const uint32_t w = ntiles - base < 64u ? ntiles - base : 64u;
+            t = base + (w - 1u - (t - base));
+        }
         s_tile = t;
         if (t < ntiles) s_desc = a.tile_desc[t];
     }
@@ -923,7 +935,9 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     const uint32_t tile = s_tile;
     if (tile >= ntiles) return;
     const TileDesc td = s_desc;
-    tile_body<DT, V, NT, EPT>(a, a.level, tile, td, s_lds, a.prof ? s_prof : nullptr);
+    // stress test: a pseudo-random pause before the look-back status is published
+    const uint32_t delay = a.shuffle ? static_cast<uint32_t>(mix64(tile * 0x9e3779b97f4a7c15ull + a.level) & 31u) : 0u;
+    tile_body<DT, V, NT, EPT>(a, a.level, tile, td, s_lds, a.prof ? s_prof : nullptr, delay);
     if (a.prof) {
         __syncthreads();
         if (tid < 6) atomicAdd(&c->prof[tid], s_prof[tid]);
@@ -1098,7 +1112,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
 
 template <class V>
 __global__ __launch_bounds__(256) void k_complete(Args a) {
-    if (a.ctl->error & ERR_OFFSETS) return;
+    if (a.ctl->error) return;  // an earlier step latched an error: the rest of the call does nothing
     complete_body<V>(a, a.level, blockIdx.x, gridDim.x);
 }
 
@@ -1774,7 +1788,7 @@ __device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t 
 template <int DT, class V, int NT, int SMAX, int CLO>
 __global__ __launch_bounds__(NT, NT >= 512 ? 4 : 3) void k_small(Args a) {
     __shared__ BucketLds<DT, V, NT, SMAX> s_lds;
-    if (a.ctl->error & ERR_OFFSETS) return;  // malformed offsets: nothing runs
+    if (a.ctl->error) return;  // an earlier step latched an error: the rest of the call does nothing
     small_all_body<DT, V, NT, SMAX, CLO>(a, a.level, blockIdx.x, gridDim.x, s_lds);
 }
 
@@ -1844,6 +1858,11 @@ __device__ inline bool grid_sync(Ctl* c, uint32_t nblk, uint32_t& gen, int* s_ok
 // of them and counts the XCD in; the last XCD opens the next generation.
 // Acquire stays per workgroup.  `my_n`: resident workgroups on this
 // workgroup's XCD; `nxcd`: XCDs with resident workgroups.
+// The opener also records the error word as it stands once every workgroup
+// has arrived (bar_err); every workgroup reads that record, which nobody
+// rewrites before the next barrier, so all of them agree on whether an
+// error ends the launch here (an error written during a step is seen by
+// all at the step's closing barrier, never by some workgroups earlier).
 __device__ inline bool grid_sync_xcd(Ctl* c, uint32_t xcd, uint32_t my_n, uint32_t nxcd, uint32_t& gen, int* s_ok) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -1855,13 +1874,15 @@ __device__ inline bool grid_sync_xcd(Ctl* c, uint32_t xcd, uint32_t my_n, uint32
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (atomicAdd(&c->bar_arrive, 1u) == nxcd - 1u) {
                 __hip_atomic_store(&c->bar_arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned err = __hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&c->bar_err, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&c->bar_gen, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         const int ok = wait_gen(c, want);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         gen = want;
-        *s_ok = ok;
+        *s_ok = ok && __hip_atomic_load(&c->bar_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
     }
     __syncthreads();
     return *s_ok != 0;
@@ -1924,7 +1945,9 @@ __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
     __shared__ uint32_t s_tile;
     __shared__ int s_ok;
     Ctl* c = a.ctl;
-    if (c->error & ERR_OFFSETS) return;  // set by the init launch only: the same for every workgroup
+    // errors latched by earlier launches (no workgroup of this one writes
+    // before the first barrier): the same for every workgroup
+    if (c->error) return;
     const uint32_t bid = blockIdx.x, nblk = gridDim.x;
     const int tid = threadIdx.x;
     const int level_cap = 4 * a.depth_limit + 64;

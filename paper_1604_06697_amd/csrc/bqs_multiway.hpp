@@ -66,7 +66,7 @@ __global__ __launch_bounds__(NT) void k_plan_multi(Args a) {
     __shared__ R s_sorted[NW][kMaxSample + 1];
 
     Ctl* c = a.ctl;
-    if (c->error & ERR_OFFSETS) return;
+    if (c->error) return;  // an earlier step latched an error: the rest of the call does nothing
     const int p = a.level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(NT) void k_mcount(Args a) {
     uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
     if (ntiles > a.cap_tile) ntiles = a.cap_tile;  // an overflow was latched
     const uint32_t tile = blockIdx.x;
-    if (tile >= ntiles || (c->error & ERR_OFFSETS)) return;
+    if (tile >= ntiles || c->error) return;  // (an error latched by an earlier step: nothing runs)
     const int tid = threadIdx.x;
     const TileDesc td = a.tile_desc[tile];
     const int u = load_splitters(a, p, td.si, s_spl);
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
     constexpr int NW = NT / 64;
     __shared__ unsigned long long s_stat[NW][3];
     Ctl* c = a.ctl;
-    if (c->error & ERR_OFFSETS) return;
+    if (c->error) return;  // an earlier step latched an error: the rest of the call does nothing
     const int p = a.level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(NT) void k_mscatter(Args a) {
     uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
     if (ntiles > a.cap_tile) ntiles = a.cap_tile;  // an overflow was latched
     const uint32_t tile = blockIdx.x;
-    if (tile >= ntiles || (c->error & ERR_OFFSETS)) return;
+    if (tile >= ntiles || c->error) return;  // (an error latched by an earlier step: nothing runs)
     const int tid = threadIdx.x, lane = tid & 63;
     const TileDesc td = a.tile_desc[tile];
     const int u = load_splitters(a, p, td.si, s_spl);

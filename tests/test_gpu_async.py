@@ -102,10 +102,12 @@ def test_bad_offsets_latched_until_synchronize(torch_mod, bqs):
     keys = to_dev(torch, W.uniform_i32(1000, 0))
     bad = torch.tensor([0, 600, 500, 1000], dtype=torch.int64, device="cuda")
     note("bad offsets, asynchronous")
+    before = keys.clone()
     ctx.sort_segments(keys, bad)
     with pytest.raises(bqs.BqsError) as e:
         ctx.synchronize()
     assert e.value.status == 1
+    assert torch.equal(keys, before)  # nothing ran
     ctx.synchronize()  # cleared
     good = torch.tensor([0, 500, 600, 1000], dtype=torch.int64, device="cuda")
     ctx.sort_segments(keys, good)
@@ -133,6 +135,8 @@ def test_nan_check_mode(torch_mod, bqs, oracle, dtype):
         with pytest.raises(bqs.BqsError) as e:
             ctx.synchronize()
         assert e.value.status == 5
+        # found before anything moved: the keys are as they were
+        assert np.array_equal(host(t, dtype).view(f"u{a.itemsize}"), b.view(f"u{a.itemsize}"))
     # a negative NaN and a signalling NaN pattern are NaNs too
     b = a.copy()
     b.view(f"u{a.itemsize}")[7] = (0xFFF0000000000001 if a.itemsize == 8 else 0xFF800001)
