@@ -44,8 +44,6 @@ def parse():
                     help="skip the persistent-mode line (a cooperative launch, which some profilers "
                          "do not shut down cleanly)")
     ap.add_argument("--serve-requests", type=int, default=100_000)
-    ap.add_argument("--cpu-log2", type=int, default=26, help="CPU sample: arrays of 2^x keys")
-    ap.add_argument("--cpu-arrays", type=int, default=6)
     return ap.parse_args()
 
 
@@ -97,8 +95,10 @@ def make_pairs(torch, n: int, copies: int, seed: int):
     return [(k.clone(), v.clone()) for _ in range(copies)]
 
 
-def run_workload(torch, bqs, ctx, kind, n, steps, warmup, seed=0):
-    """Times `steps` sorts; returns (ms_per_step, stats dict, per-level list)."""
+def run_workload(torch, bqs, ctx, kind, n, steps, warmup, seed=0, keep=None):
+    """Times `steps` sorts; returns (ms_per_step, stats dict, per-level list,
+    partition ms and keys per step, correct).  With `keep` (a list), the last
+    step's sorted keys are appended to it as a host array."""
     pairs = kind == "pairs_u64_u32"
     copies = steps + warmup
     data = make_pairs(torch, n, copies, seed) if pairs else make_inputs(torch, kind, n, copies, seed)
@@ -141,13 +141,15 @@ def run_workload(torch, bqs, ctx, kind, n, steps, warmup, seed=0):
         vals = data[-1][1].to(torch.int64) & 0xFFFFFFFF
         ok = ok and bool(torch.equal(keys_in[vals], last))
     del ref
+    if keep is not None:
+        keep.append(last.cpu().numpy())
     del data
     torch.cuda.empty_cache()
     ms = (t1 - t0) * 1e3 / steps
     return ms, st, levels, part_ms / steps, part_keys / steps, ok
 
 
-def batched_segments(torch, bqs, steps, warmup, k=20000, seed=7, per_array=True):
+def batched_segments(torch, bqs, steps, warmup, k=20000, seed=7, per_array=True, cpu=True):
     """k int32 arrays, sizes log-uniform in [16, 2^20] (uniform keys),
     concatenated with an int64 offsets array: one sort_segments call per
     step, against one sort call per array on the same stream."""
@@ -182,14 +184,29 @@ def batched_segments(torch, bqs, steps, warmup, k=20000, seed=7, per_array=True)
     st = ctx.stats()
     ok = check_segments(torch, pristine, work, offsets)
     ms = 1e3 * float(np.median(times))
+    # bytes the method moves: 8 B per key and two-way pass (read + write),
+    # 12 B per key and multiway pass (two reads + write), 8 B per small-sorted
+    # key, 4 B per key of an equal run
+    pass_b = 12 if tuned["plan"].get("multiway") else 8
+    alg_b = pass_b * st["partitioned_keys"] + 8 * st["small_sorted_keys"] + 4 * st["filled_keys"]
+    # per-phase breakdown: one more call with the same plan, every launch
+    # timed (outside the timed steps)
+    bctx = bqs.Context(timing=1, **tuned["plan"])
+    work.copy_(pristine)
+    bctx.sort_segments(work, off_d)
+    bctx.synchronize()
+    bst = bctx.stats()
+    bctx.close()
     out = {
         "workload": f"{k} int32 arrays, sizes log-uniform in [16, 2^20], {n} keys, int64 offsets",
         "k": k, "n": n, "seed": seed,
         "batched": {"ms": round(ms, 3), "ms_min": round(1e3 * min(times), 3),
                     "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3),
-                    "alg_GBps": round((8 * (st["partitioned_keys"] + st["small_sorted_keys"]) +
-                                       4 * st["filled_keys"]) / (ms * 1e-3) / 1e9, 1),
+                    "alg_GBps": round(alg_b / (ms * 1e-3) / 1e9, 1),
+                    "frac": round(alg_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "levels": st["levels"], "graph_replay": bool(st["graph_launches"]),
+                    "breakdown": {"partition_ms": round(bst["partition_ms"], 3),
+                                  "small_ms": round(bst["small_ms"], 3), "plan_ms": round(bst["plan_ms"], 3)},
                     # every array completes when the call does
                     "array_done_p50_ms": round(ms, 3), "array_done_p99_ms": round(ms, 3)},
         "correct": ok,
@@ -216,6 +233,8 @@ def batched_segments(torch, bqs, steps, warmup, k=20000, seed=7, per_array=True)
                             "array_done_p99_ms": round(1e3 * float(np.percentile(done, 99, method="nearest")), 1),
                             "correct": ok_pa}
         out["speedup_vs_per_array"] = round(total * 1e3 / ms, 2)
+    if cpu:
+        out["cpu_oracle"] = cpu_segments(pristine.cpu().numpy(), offsets)
     del work, pristine
     torch.cuda.empty_cache()
     return out
@@ -470,33 +489,165 @@ def record_bytes(kind):
     return 12  # u64 key + u32 payload
 
 
-def cpu_baseline(log2n: int, arrays: int):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(torch, n: int, gpu_sorted):
+    """The CPU oracle (single-threaded BlockQuicksort, the paper's algorithm)
+    on the headline's own input: the same 2^28 seeded keys the timed GPU
+    steps sorted, copied to the host.  The host's std::sort is timed beside
+    it on the same bytes (the paper's comparison, Section 4), and the
+    oracle's output is compared bit for bit with the GPU's."""
     import oracle
-    import workloads as W
 
     orc = oracle.default()
-    n = 1 << log2n
-    total, keys = 0.0, 0
-    for s in range(arrays):
-        a = W.uniform_i32(n, 1000 + s)
-        t0 = time.perf_counter()
-        out = orc.sort(a)
-        total += time.perf_counter() - t0
-        keys += n
-        assert out[0] <= out[-1]
+    host = make_inputs(torch, "i32_uniform", n, 1, 0)[0].cpu().numpy()
+    t0 = time.perf_counter()
+    out = orc.sort(host)
+    t_or = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref = orc.std_sort(host)
+    t_std = time.perf_counter() - t0
+    same = bool(np.array_equal(out, ref)) and (gpu_sorted is None or bool(np.array_equal(out, gpu_sorted)))
     return {
-        "value": keys / total / 1e9,
+        "value": round(n / t_or / 1e9, 5),
         "unit": "Gkeys/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{arrays} arrays of 2^{log2n} uniform int32 keys (seeds {1000}..{1000 + arrays - 1}), "
-                  f"single-threaded BlockQuicksort oracle, {total:.1f} s",
-        "host": platform.processor() or platform.machine(),
+        "sample": f"the headline input ({n} uniform int32 keys, device seed 0) copied to the host, "
+                  f"single-threaded BlockQuicksort oracle, {t_or:.1f} s",
+        "ns_per_key": round(t_or / n * 1e9, 2),
+        "std_sort": {"Gkeys/s": round(n / t_std / 1e9, 5), "ns_per_key": round(t_std / n * 1e9, 2),
+                     "s": round(t_std, 2), "oracle_speedup_over_std_sort": round(t_std / t_or, 3)},
+        "matches_gpu_bit_for_bit": same,
+        "cpu_model": cpu_model(),
         "nproc": os.cpu_count(),
     }
 
 
+def cpu_segments(keys, offsets, every=10):
+    """The CPU oracle on a bounded sample of the batched workload (every
+    `every`-th array): one core, and all host cores with one array per
+    task (threads; the oracle's calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    orc = oracle.default()
+    pick = np.arange(0, offsets.size - 1, every)
+    arrays = [keys[offsets[i]:offsets[i + 1]].copy() for i in pick]
+    nk = sum(a.size for a in arrays)
+    t0 = time.perf_counter()
+    for a in arrays:
+        orc.sort(a)
+    t1 = time.perf_counter() - t0
+    cores = min(os.cpu_count() or 1, 64)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(orc.sort, arrays))
+    tc = time.perf_counter() - t0
+    return {"sample": f"every {every}th array ({len(arrays)} arrays, {nk} keys)", "keys": nk,
+            "one_core": {"Gkeys/s": round(nk / t1 / 1e9, 5), "s": round(t1, 2), "cores": 1},
+            "all_cores": {"Gkeys/s": round(nk / tc / 1e9, 5), "s": round(tc, 2), "cores": cores},
+            "cpu_model": cpu_model()}
+
+
+def _csv_rows(path):
+    import csv
+
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def trace_summary(trace_dir: str, bench_json: str | None, counters: list[str]) -> str:
+    """Markdown summary of a rocprofv3 run of this benchmark (written to
+    profiles/): per-kernel statistics from --kernel-trace --stats, the
+    dispatches of one headline sort with the partition kernel's rate per
+    level (keys per level from the benchmark's JSON line of the same run),
+    and, from --pmc runs, the HBM bytes of a partition launch (FETCH_SIZE and
+    WRITE_SIZE scaled by what they read on the benchmark's 1 GiB copy)."""
+    import glob
+
+    out = []
+    stats = glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))
+    trace = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))
+    passes = None
+    if bench_json:
+        with open(bench_json) as f:
+            line = [ln for ln in f.read().splitlines() if ln.startswith("{")][-1]
+        passes = json.loads(line).get("passes")
+    if stats:
+        rows = _csv_rows(stats[0])
+        out.append("| kernel | calls | total ms | average us |\n|---|---|---|---|")
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
+            name = r["Name"].split("(")[0].replace("void ", "")
+            name = name if len(name) <= 70 else name[:67] + "..."
+            out.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                       f"{float(r['AverageNs']) / 1e3:.2f} |")
+    if trace:
+        rows = sorted(_csv_rows(trace[0]), key=lambda r: int(r["Start_Timestamp"]))
+        starts = [i for i, r in enumerate(rows) if "k_init_single" in r["Kernel_Name"]]
+        if len(starts) >= 2:
+            # the last sort of the timed headline steps: the third init of a
+            # run with one warm-up and two steps
+            i0 = starts[min(2, len(starts) - 2)]
+            i1 = next((i + 1 for i in range(i0, len(rows)) if "k_persist" in rows[i]["Kernel_Name"]),
+                      starts[starts.index(i0) + 1])
+            sort = rows[i0:i1]
+            t0 = int(sort[0]["Start_Timestamp"])
+            t1 = max(int(r["End_Timestamp"]) for r in sort)
+            parts = [r for r in sort if "k_partition" in r["Kernel_Name"]]
+            out.append(f"\nOne headline sort: {len(sort)} dispatches, {(t1 - t0) / 1e6:.3f} ms first start "
+                       f"to last end (under the profiler), "
+                       f"{sum(int(r['End_Timestamp']) - int(r['Start_Timestamp']) for r in sort) / 1e6:.3f} ms "
+                       "of kernel time.\n")
+            out.append("| level | partition us | keys | GB/s (8 B per key) |\n|---|---|---|---|")
+            for lv, r in enumerate(parts):
+                us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                keys = passes[lv]["keys"] if passes and lv < len(passes) else None
+                gbs = f"{8 * keys / (us * 1e-6) / 1e9:.0f}" if keys else "-"
+                out.append(f"| {lv} | {us:.1f} | {keys if keys is not None else '-'} | {gbs} |")
+    hbm = 0.0
+    for cdir in counters:
+        rows = _csv_rows(glob.glob(os.path.join(cdir, "*counter_collection.csv"))[0])
+        byname = {}
+        for r in rows:
+            byname.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        copy = {c: max(v) for (k, c), v in byname.items() if "copyBuffer" in k}
+        for (kname, cname), vals in sorted(byname.items()):
+            if "k_partition" not in kname:
+                continue
+            # the benchmark's largest copy moves 1 GiB each way: the counter's
+            # scale factor
+            factor = (1 << 20) / copy[cname] if copy.get(cname) else float("nan")
+            work = [v for v in vals if v > 0.01 * max(vals)]  # launches with tiles
+            per_launch = sum(work) / len(work) * 1024 * factor
+            hbm += per_launch
+            out.append(f"- `{cname}` k_partition: {len(work)} launches with tiles of {len(vals)}, mean "
+                       f"{sum(work) / len(work):.1f} KiB, scale {factor:.3f} (1 GiB copy reads "
+                       f"{copy.get(cname, float('nan')):.1f} KiB) -> {per_launch:.0f} B per launch")
+    if counters:
+        out.append(f"- HBM bytes per partition launch (fetch + write): {hbm:.0f}")
+    return "\n".join(out) + "\n"
+
+
 def main():
+    if "--trace-summary" in sys.argv:
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--trace-summary", required=True, help="rocprofv3 --output-format csv directory")
+        ap.add_argument("--bench-json", help="this benchmark's output of the same run")
+        ap.add_argument("--counters", nargs="*", default=[], help="rocprofv3 --pmc csv directories")
+        a = ap.parse_args()
+        print(trace_summary(a.trace_summary, a.bench_json, a.counters), end="")
+        return
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -513,8 +664,9 @@ def main():
     # the timed region records HIP events around the partition kernels only
     ctx = bqs.Context(timing=2)
 
+    kept = [] if not args.no_cpu else None
     ms, st, levels, part_ms, part_keys, ok = run_workload(
-        torch, bqs, ctx, "i32_uniform", args.n, args.steps, args.warmup)
+        torch, bqs, ctx, "i32_uniform", args.n, args.steps, args.warmup, keep=kept)
     n = args.n
     value = n / (ms * 1e-3) / 1e9
     r = 4
@@ -578,7 +730,11 @@ def main():
     mctx = bqs.Context(timing=1, multiway=1, small_cutoff=8192)
     mms, mst, _, mpart_ms, mpart_keys, mok = run_workload(
         torch, bqs, mctx, "i32_uniform", args.n, max(2, args.steps // 2), 1)
+    # a multiway pass reads each key twice (count, scatter) and writes it once
+    mw_bytes = 3 * r * mst["partitioned_keys"] + 2 * r * mst["small_sorted_keys"] + r * mst["filled_keys"]
     out["multiway"] = {"ms": round(mms, 3), "Gkeys/s": round(n / (mms * 1e-3) / 1e9, 3),
+                       "alg_GBps": round(mw_bytes / (mms * 1e-3) / 1e9, 1),
+                       "frac": round(mw_bytes / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        "partition_ms": round(mst["partition_ms"], 3), "small_ms": round(mst["small_ms"], 3),
                        "plan_ms": round(mst["plan_ms"], 3), "levels": mst["levels"],
                        "partitioned_keys": mst["partitioned_keys"], "small_cutoff": 8192, "correct": mok}
@@ -611,7 +767,7 @@ def main():
         out["records"] = records(torch, bqs)
 
     if not args.no_batched:
-        out["segmented"] = batched_segments(torch, bqs, max(2, args.steps // 3), 1)
+        out["segmented"] = batched_segments(torch, bqs, max(2, args.steps // 3), 2, cpu=not args.no_cpu)
 
     if not args.no_serve:
         out["serving"] = serving(torch, args.serve_requests)
@@ -629,7 +785,7 @@ def main():
                              "small_cutoff": pst["small_cutoff"], "correct": pok}
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_log2, args.cpu_arrays)
+        out["cpu_baseline"] = cpu_baseline(torch, n, kept[0] if kept else None)
     print(json.dumps(out), flush=True)
 
 

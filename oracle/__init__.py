@@ -91,6 +91,8 @@ class Oracle:
         L.oracle_partition.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int, P]
         L.oracle_partition.restype = ctypes.c_int64
+        L.oracle_std_sort.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]
+        L.oracle_std_sort.restype = ctypes.c_int
         L.oracle_mutant.argtypes = []
         L.oracle_mutant.restype = ctypes.c_int
 
@@ -162,6 +164,13 @@ class Oracle:
         if cut < 0:
             raise OracleError("invalid partition arguments")
         return a, int(cut)
+
+    def std_sort(self, keys: np.ndarray) -> np.ndarray:
+        """The host's std::sort with the same key order (a library routine:
+        the CPU context the paper compares against, not an oracle)."""
+        a = np.ascontiguousarray(keys).copy()
+        self._rc(self.lib.oracle_std_sort(a.ctypes.data, a.size, self._code(a)))
+        return a
 
     def mutant(self) -> int:
         return int(self.lib.oracle_mutant())

@@ -38,6 +38,7 @@
 // (no fused multiply-add: the Vector comparator rounds every product and sum)
 // A planted mistake for the pin tests is selected with -DORACLE_MUTANT=k.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -548,6 +549,28 @@ int oracle_sort_records(void* recs, int64_t n, int kind, oracle_params* p) {
         return OR_OK;
     }
     return OR_EDTYPE;
+}
+
+// The host's std::sort with the oracle's key order (the paper's comparison
+// baseline, Section 4), called as a library routine: the CPU context timed
+// beside the oracle.  Returns OR_OK, OR_EINVAL, OR_EDTYPE or OR_ENAN.
+int oracle_std_sort(void* keys, int64_t n, int dtype) {
+    if (n < 0 || (n > 0 && !keys)) return OR_EINVAL;
+    switch (dtype) {
+        case OR_I32: std::sort(static_cast<int32_t*>(keys), static_cast<int32_t*>(keys) + n); return OR_OK;
+        case OR_U32: std::sort(static_cast<uint32_t*>(keys), static_cast<uint32_t*>(keys) + n); return OR_OK;
+        case OR_I64: std::sort(static_cast<int64_t*>(keys), static_cast<int64_t*>(keys) + n); return OR_OK;
+        case OR_U64: std::sort(static_cast<uint64_t*>(keys), static_cast<uint64_t*>(keys) + n); return OR_OK;
+        case OR_F32:
+            if (has_nan(static_cast<float*>(keys), n)) return OR_ENAN;
+            std::sort(static_cast<float*>(keys), static_cast<float*>(keys) + n, KeyLess<float>::lt);
+            return OR_OK;
+        case OR_F64:
+            if (has_nan(static_cast<double*>(keys), n)) return OR_ENAN;
+            std::sort(static_cast<double*>(keys), static_cast<double*>(keys) + n, KeyLess<double>::lt);
+            return OR_OK;
+        default: return OR_EDTYPE;
+    }
 }
 
 int oracle_mutant(void) { return ORACLE_MUTANT; }
