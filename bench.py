@@ -615,26 +615,67 @@ def trace_summary(trace_dir: str, bench_json: str | None, counters: list[str]) -
                 keys = passes[lv]["keys"] if passes and lv < len(passes) else None
                 gbs = f"{8 * keys / (us * 1e-6) / 1e9:.0f}" if keys else "-"
                 out.append(f"| {lv} | {us:.1f} | {keys if keys is not None else '-'} | {gbs} |")
+            if passes and len(starts) >= 3:
+                # the partition launches with tiles of the timed sorts (the
+                # second and third inits), the launches bench.py averages
+                durs = []
+                for j in (1, 2):
+                    a0 = starts[j]
+                    a1 = next((i for i in range(a0, len(rows)) if "k_persist" in rows[i]["Kernel_Name"]), len(rows))
+                    ps = [r for r in rows[a0:a1] if "k_partition" in r["Kernel_Name"]][:len(passes)]
+                    durs += [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in ps]
+                avg = json.loads(line).get("roofline", {}).get("avg_launch_ms")
+                out.append(f"\nk_partition launches with tiles in the two timed sorts: {len(durs)}, average "
+                           f"{sum(durs) / len(durs):.1f} us (bench.py's HIP events, same run: "
+                           f"{avg * 1e3 if avg else float('nan'):.1f} us)")
     hbm = 0.0
     for cdir in counters:
         rows = _csv_rows(glob.glob(os.path.join(cdir, "*counter_collection.csv"))[0])
         byname = {}
         for r in rows:
             byname.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        if any(c.startswith("SQ_") for _, c in byname):
+            # instruction-mix counters: per-launch means over the launches
+            # that did work (wave cycles above 1 % of the kernel's largest)
+            kernels = sorted({k for k, _ in byname})
+            cnames = sorted({c for _, c in byname})
+            out.append("\n| kernel | launches | " + " | ".join(c.replace("SQ_", "") for c in cnames) +
+                       " |\n|---|---|" + "---|" * len(cnames))
+            for k in kernels:
+                wc = byname.get((k, "SQ_WAVE_CYCLES"))
+                keep = [i for i, v in enumerate(wc) if v > 0.01 * max(wc)] if wc else None
+                cells = []
+                for c in cnames:
+                    v = byname.get((k, c), [])
+                    v = [v[i] for i in keep] if keep is not None else v
+                    cells.append(f"{sum(v) / len(v):.3g}" if v else "-")
+                name = k.split("(")[0].replace("void ", "")
+                out.append(f"| `{name}` | {len(keep) if keep is not None else '-'} | " + " | ".join(cells) + " |")
+            continue
         copy = {c: max(v) for (k, c), v in byname.items() if "copyBuffer" in k}
-        for (kname, cname), vals in sorted(byname.items()):
-            if "k_partition" not in kname:
-                continue
+        order = sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
+        for cname in sorted({c for _, c in byname}):
             # the benchmark's largest copy moves 1 GiB each way: the counter's
             # scale factor
             factor = (1 << 20) / copy[cname] if copy.get(cname) else float("nan")
-            work = [v for v in vals if v > 0.01 * max(vals)]  # launches with tiles
-            per_launch = sum(work) / len(work) * 1024 * factor
+            # every partition launch of every sort, over the launches that
+            # had tiles (more than 64 KiB moved): bench.py's launch count
+            total, launches, empty = 0.0, 0, 0
+            for r in order:
+                if r["Counter_Name"] != cname or "k_partition" not in r["Kernel_Name"]:
+                    continue
+                v = float(r["Counter_Value"])
+                total += v
+                launches += v > 64.0
+                empty += v <= 64.0
+            if not launches:
+                continue
+            per_launch = total / launches * 1024 * factor
             hbm += per_launch
-            out.append(f"- `{cname}` k_partition: {len(work)} launches with tiles of {len(vals)}, mean "
-                       f"{sum(work) / len(work):.1f} KiB, scale {factor:.3f} (1 GiB copy reads "
+            out.append(f"- `{cname}` k_partition: {total:.0f} KiB over {launches} launches with tiles "
+                       f"(+{empty} without), scale {factor:.4f} (1 GiB copy: "
                        f"{copy.get(cname, float('nan')):.1f} KiB) -> {per_launch:.0f} B per launch")
-    if counters:
+    if hbm:
         out.append(f"- HBM bytes per partition launch (fetch + write): {hbm:.0f}")
     return "\n".join(out) + "\n"
 
