@@ -132,7 +132,7 @@ typedef enum {
                                    are identical                                                */
     BQS_PARAM_CHECK_NAN = 13,   /* 1: float keys are checked for NaN (one extra read of the keys)
                                    before the sort; a NaN is reported as BQS_ENAN and the keys
-                                   are then in an unspecified order.  The sort's precondition
+                                   are left as they were.  The sort's precondition
                                    (a totally ordered key set, Introduction) excludes NaN; 0
                                    (default) does not check                                     */
     BQS_PARAM_LOOKBACK = 10,    /* how a partition tile claims its output ranges.  0 (default):
@@ -148,13 +148,27 @@ typedef enum {
                                    64; past the depth limit the median again).  0 (default):
                                    the median.  Sorted output is identical; only the number of
                                    levels changes                                               */
-    BQS_PARAM_MULTIWAY = 11     /* 1: keys-only sorts split each segment around up to 15
+    BQS_PARAM_MULTIWAY = 11,    /* 1: keys-only sorts split each segment around up to 15
                                    splitters per pass instead of one pivot (a sample-sort step:
                                    the paper's multi-pivot outlook, Section 5; 31 buckets, keys
                                    equal to a splitter finish at once), so far fewer passes
                                    run; pairs keep the two-way step.  0 (default): the paper's
                                    block partition around one pivot.  Sorted output is
                                    identical either way.                                        */
+    BQS_PARAM_INPLACE = 18      /* 1: in-place levels (Section 3, Algorithm 3: the partition
+                                   swaps misplaced elements inside the array instead of copying
+                                   it; Section 3.2): keys and payloads never leave the caller's
+                                   buffers, and the workspace holds one bit per key plus lists
+                                   and per-tile counts (5 to 9 % of the default workspace;
+                                   bqs_workspace_bytes reflects the setting).  Each
+                                   level reads the keys twice and writes the misplaced ones once,
+                                   about 1.5x the traffic of the default level.  Applies to
+                                   bqs_sort, bqs_sort_pairs, bqs_sort_segments and
+                                   bqs_sort_records; takes precedence over BQS_PARAM_MULTIWAY;
+                                   not available in BQS_MODE_PERSISTENT (BQS_EINVAL).  Sorted
+                                   keys are identical; payloads of equal keys may come out in
+                                   another (still deterministic) order.  0 (default): out of
+                                   place                                                        */
 } bqs_param;
 
 /* Execution modes (BQS_PARAM_MODE).
@@ -321,7 +335,7 @@ bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offset
  *                    the stream reaches the end of the sort; NULL: none.
  * Returns BQS_ETOOBIG, with nothing enqueued, when the sort needs more than
  * the scratch: n up to bqs_workspace_bytes(NULL, n, dtype, 0, 1) <= 64 MiB,
- * about 15.9 million 4-byte or 7.96 million 8-byte keys.  Other argument
+ * about 16.5 million 4-byte or 8.16 million 8-byte keys.  Other argument
  * errors as for bqs_sort.  Every call on a GPU shares that GPU's scratch
  * (which keeps the last call's contents; every call starts by clearing what
  * must start at zero): calls that overlap on one GPU -- on different

@@ -62,6 +62,7 @@ PARAM_ENQUEUE_LEVELS = 14
 PARAM_DEPTH_LIMIT = 15
 PARAM_LIST_CAP = 16
 PARAM_SHUFFLE = 17
+PARAM_INPLACE = 18
 RECORD_VECTOR, RECORD_RECORD = 1, 2
 MODE_ASYNC, MODE_LEVELS, MODE_PERSISTENT = 0, 1, 2
 
@@ -255,6 +256,7 @@ class Context:
         "depth_limit": PARAM_DEPTH_LIMIT,
         "list_cap": PARAM_LIST_CAP,
         "shuffle": PARAM_SHUFFLE,
+        "inplace": PARAM_INPLACE,
     }
 
     def set_param(self, name: str, value: int):

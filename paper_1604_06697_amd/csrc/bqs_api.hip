@@ -229,6 +229,7 @@ void launch_init_segments(const Args& a, hipStream_t s) {
 struct Layout {
     size_t ctl, yk, yv, side, segs[2], smalls[2], fills[2], tile_desc, status, total;
     size_t splitters[2], toff, bcur, bstart;
+    size_t ipmask, iptile;
     uint64_t cap_seg, cap_tile, cap_small, cap_fill;
 };
 
@@ -236,8 +237,10 @@ static size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255);
 
 // Workspace layout: the control block, the double buffer (keys, payloads
 // and the side buffer for payloads of pivot-equal keys) and the per-level
-// work lists in two slots.
-static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S, bool multiway) {
+// work lists in two slots.  In-place levels have no double buffer: one
+// class bit per key (per tile of kIpT keys) and per-tile counts instead.
+static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T, int64_t S, bool multiway,
+                          bool inplace) {
     Layout L{};
     const uint64_t un = static_cast<uint64_t>(n);
     const uint64_t uk = static_cast<uint64_t>(k);
@@ -249,9 +252,9 @@ static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T,
         return at;
     };
     L.ctl = take(sizeof(Ctl));
-    L.yk = take(un * kb);
-    L.yv = take(vb ? un * vb : 0);
-    L.side = take(vb ? un * vb : 0);
+    L.yk = take(inplace ? 0 : un * kb);
+    L.yv = take(vb && !inplace ? un * vb : 0);
+    L.side = take(vb && !inplace ? un * vb : 0);
     // a two-way level gives each segment two children and one equal run;
     // a multiway level up to 16 children and 15 equal runs
     const uint64_t fan = multiway ? 16 : 2;
@@ -266,10 +269,13 @@ static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T,
     L.status = take(L.cap_tile * sizeof(unsigned long long));
     // multiway levels: 16 splitters, 32 bucket cursors and 32 bucket
     // starts per segment, 32 bucket offsets per tile
-    for (int s = 0; s < 2; ++s) L.splitters[s] = take(L.cap_seg * 16 * sizeof(uint64_t));
-    L.toff = take(L.cap_tile * 32 * sizeof(uint32_t));
-    L.bcur = take(L.cap_seg * 32 * sizeof(uint32_t));
-    L.bstart = take(L.cap_seg * 32 * sizeof(uint32_t));
+    const bool mw = multiway && !inplace;
+    for (int s = 0; s < 2; ++s) L.splitters[s] = take(mw ? L.cap_seg * 16 * sizeof(uint64_t) : 0);
+    L.toff = take(mw ? L.cap_tile * 32 * sizeof(uint32_t) : 0);
+    L.bcur = take(mw ? L.cap_seg * 32 * sizeof(uint32_t) : 0);
+    L.bstart = take(mw ? L.cap_seg * 32 * sizeof(uint32_t) : 0);
+    L.ipmask = take(inplace ? L.cap_tile * kIpWords * sizeof(uint64_t) : 0);
+    L.iptile = take(inplace ? L.cap_tile * sizeof(IpTile) : 0);
     L.total = off;
     return L;
 }
@@ -302,6 +308,7 @@ struct bqs_ctx {
     int64_t graph = 0;
     int64_t lookback = 0;   // 1: keys-only tiles also claim by decoupled look-back
     int64_t multiway = 0;   // 1: keys-only levels split around up to 15 splitters
+    int64_t inplace = 0;    // 1: in-place levels (no double buffer)
     int64_t check_nan = 0;  // 1: floating-point keys are checked for NaN first
     int64_t enqueue_levels = 0;  // > 0: levels enqueued before the tail launch
     int64_t depth_limit = 0;     // > 0: replaces 2 floor(log2 n) + 3
@@ -361,6 +368,7 @@ const Ops* select_ops(const bqs_ctx* ctx, int dtype, int val_bytes) {
 
 // Keys per partition tile of a call: the multiway levels have their own.
 int64_t eff_tile_keys(const bqs_ctx* ctx, const Ops* o) {
+    if (ctx && ctx->inplace) return kIpT;
     return ctx && ctx->multiway && o->mscan ? o->multi_tile_keys : o->tile_keys;
 }
 
@@ -557,7 +565,7 @@ std::vector<uint64_t> call_shape(const Ops* o, const Args& a, bool segmented) {
             static_cast<uint64_t>(a.pivot_skew), static_cast<uint64_t>(a.tile_keys), static_cast<uint64_t>(a.prof),
             static_cast<uint64_t>(a.claim), static_cast<uint64_t>(a.ways), static_cast<uint64_t>(a.depth_limit),
             static_cast<uint64_t>(a.shuffle), static_cast<uint64_t>(a.cap_seg), static_cast<uint64_t>(a.cap_small),
-            segmented ? 1ull : 0ull};
+            static_cast<uint64_t>(a.inplace), segmented ? 1ull : 0ull};
 }
 
 // Graph key: the shape plus the buffers the launches were captured with.
@@ -625,7 +633,7 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
         const uint64_t sb_prev = L ? seg_bound(a, L - 1) : 0;
         // equal runs written at level L: at most one chunk per kFillChunk
         // keys plus one per run (the previous level's segments)
-        const uint64_t fill_units = L ? n / kFillChunk + sb_prev * (a.ways ? 15 : 1) : 0;
+        const uint64_t fill_units = L && !a.inplace ? n / kFillChunk + sb_prev * (a.ways ? 15 : 1) : 0;
         // small segments sorted at level L: the inputs (level 0) or the
         // previous level's children
         const uint64_t small_items = L ? sb_prev * (a.ways ? 16 : 2) : std::max<uint64_t>(a.k, 1);
@@ -644,7 +652,15 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
         if (tb > 0x7fffffffull) return BQS_EINVAL;
         const int tg = clamp_grid(tb, 0x7fffffff);
         if (tm) tm->start();
-        if (a.ways) {
+        if (a.inplace) {
+            o->ip_count(a, tg, s);
+            o->ip_scan(a, clamp_grid(sb, 2048), s);
+            o->ip_exchange(a, tg, s);
+            if (tm) tm->stop(2, L);
+            if (tm) tm->start_aux();
+            o->ip_complete(a, clamp_grid((sb + 255) / 256, 1024), s);
+            if (tm) tm->stop_aux(0, L);
+        } else if (a.ways) {
             o->mcount(a, tg, s);
             o->mscan(a, clamp_grid((sb + 3) / 4, 1024), s);
             o->mscatter(a, tg, s);
@@ -662,10 +678,13 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
     Args t = a;
     t.level = levels;
     t.ways = 0;
-    t.tile_keys = o->tile_keys;
-    t.retile = a.tile_keys != o->tile_keys ? 1 : 0;
+    if (!a.inplace) {
+        t.tile_keys = o->tile_keys;
+        t.retile = a.tile_keys != o->tile_keys ? 1 : 0;
+    }
     if (tm) tm->start_aux();
-    o->tail(t, s);
+    if (a.inplace) o->ip_tail(t, s);
+    else o->tail(t, s);
     if (tm) tm->stop_aux(0, levels);
     return hipGetLastError() == hipSuccess ? BQS_OK : BQS_EHIP;
 }
@@ -805,7 +824,15 @@ bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int d
         if (L >= cap) return BQS_EOVERFLOW;
         lkeys.push_back(static_cast<int64_t>(cur.keys));
         tm.start();
-        if (a.ways) {
+        if (a.inplace) {
+            o->ip_count(a, static_cast<int>(ntile), s);
+            o->ip_scan(a, clamp_grid(nseg, 16384), s);
+            o->ip_exchange(a, static_cast<int>(ntile), s);
+            tm.stop(2, L);
+            tm.start_aux();
+            o->ip_complete(a, clamp_grid((nseg + 255) / 256, 4096), s);
+            tm.stop_aux(0, L);
+        } else if (a.ways) {
             o->mcount(a, static_cast<int>(ntile), s);
             o->mscan(a, clamp_grid((nseg + 3) / 4, 4096), s);
             o->mscatter(a, static_cast<int>(ntile), s);
@@ -839,7 +866,7 @@ bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int d
 // Init, then one cooperative launch of every workgroup the GPU holds at
 // once, which runs all levels; asynchronous like the default mode.
 bqs_status run_persist(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int dtype) {
-    if (a.ways) return BQS_EINVAL;  // the multiway step has no persistent form
+    if (a.ways || a.inplace) return BQS_EINVAL;  // the multiway and in-place steps have no persistent form
     harvest(ctx, false);
     const hipStream_t s = ctx->stream;
     if (ctx->persist_grid <= 0 || ctx->persist_ops != o) {
@@ -888,8 +915,9 @@ bqs_status prepare_in(const bqs_ctx* ctx, void* ws, size_t ws_bytes, const Ops* 
                       int64_t k, void* keys, void* vals, Args& a) {
     const size_t kb = key_bytes(dtype);
     const int64_t S = eff_small_cut(ctx, o);
-    const bool multiway = ctx && ctx->multiway && o->mscan;
-    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S, multiway);
+    const bool inplace = ctx && ctx->inplace;
+    const bool multiway = ctx && ctx->multiway && o->mscan && !inplace;
+    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S, multiway, inplace);
     if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull)
         return BQS_EINVAL;
     if (!ws || ws_bytes < L.total) return BQS_EINVAL;
@@ -901,10 +929,20 @@ bqs_status prepare_in(const bqs_ctx* ctx, void* ws, size_t ws_bytes, const Ops* 
     a = Args{};
     a.ctl = reinterpret_cast<Ctl*>(w + L.ctl);
     a.x_keys = keys;
-    a.y_keys = w + L.yk;
     a.x_vals = vals;
-    a.y_vals = vb ? w + L.yv : nullptr;
-    a.side = vb ? w + L.side : nullptr;
+    if (inplace) {
+        // every level reads and writes the caller's buffers
+        a.y_keys = keys;
+        a.y_vals = vals;
+        a.side = nullptr;
+        a.ipmask = reinterpret_cast<uint64_t*>(w + L.ipmask);
+        a.iptile = reinterpret_cast<IpTile*>(w + L.iptile);
+        a.inplace = 1;
+    } else {
+        a.y_keys = w + L.yk;
+        a.y_vals = vb ? w + L.yv : nullptr;
+        a.side = vb ? w + L.side : nullptr;
+    }
     for (int s = 0; s < 2; ++s) {
         a.segs[s] = reinterpret_cast<SegDesc*>(w + L.segs[s]);
         a.smalls[s] = reinterpret_cast<SmallItem*>(w + L.smalls[s]);
@@ -1079,6 +1117,7 @@ bqs_status bqs_ctx_set_param(bqs_ctx* ctx, int param, int64_t value) {
             break;
         case BQS_PARAM_LOOKBACK: ctx->lookback = value ? 1 : 0; break;
         case BQS_PARAM_MULTIWAY: ctx->multiway = value ? 1 : 0; break;
+        case BQS_PARAM_INPLACE: ctx->inplace = value ? 1 : 0; break;
         case BQS_PARAM_CHECK_NAN: ctx->check_nan = value ? 1 : 0; break;
         case BQS_PARAM_ENQUEUE_LEVELS:
             ctx->enqueue_levels = value;
@@ -1122,6 +1161,7 @@ int64_t bqs_ctx_get_param(const bqs_ctx* ctx, int param) {
         case BQS_PARAM_GRAPH: return ctx->graph;
         case BQS_PARAM_LOOKBACK: return ctx->lookback;
         case BQS_PARAM_MULTIWAY: return ctx->multiway;
+        case BQS_PARAM_INPLACE: return ctx->inplace;
         case BQS_PARAM_CHECK_NAN: return ctx->check_nan;
         case BQS_PARAM_ENQUEUE_LEVELS: return ctx->enqueue_levels;
         case BQS_PARAM_DEPTH_LIMIT: return ctx->depth_limit;
@@ -1154,7 +1194,7 @@ size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, i
     if (!o) return 0;
     const Layout L = make_layout(n_total, key_bytes(key), static_cast<size_t>(val_bytes),
                                  std::max<int64_t>(k_segments, 1), eff_tile_keys(ctx, o), eff_small_cut(ctx, o),
-                                 ctx && ctx->multiway && o->mscan);
+                                 ctx && ctx->multiway && o->mscan && !ctx->inplace, ctx && ctx->inplace);
     return L.total;
 }
 

@@ -47,10 +47,42 @@ struct SegDesc {
     uint64_t pivot;      // pivot as an order key (set by the plan kernel)
     uint64_t pivot_raw;  // pivot as stored bits
     uint32_t t0, nt;     // tiles [t0, t0 + nt) of this level belong to the segment
-    uint32_t depth, pad;
+    uint32_t depth;
+    uint32_t pad;        // in-place levels: kSegForced, kSegARight
     // cursor claims (keys only): low 32 bits keys already placed in the left
-    // run, high 32 bits in the right run (cleared by the plan kernel)
+    // run, high 32 bits in the right run (cleared by the plan kernel).
+    // In-place levels: low 32 bits class-L keys, high 32 bits keys equal to
+    // the pivot (written by the scan step)
     unsigned long long cursor;
+};
+
+// SegDesc::pad bits of the in-place step.  kSegForced: the pivot was fixed
+// by the parent (the parent's pivot, the segment's smallest key) and the
+// classes are x <= p, so the left part holds only keys equal to p and is
+// finished.  kSegARight: the right part is the larger one, and its tiles
+// own the exchange of misplaced keys.
+constexpr uint32_t kSegForced = 1u;
+constexpr uint32_t kSegARight = 2u;
+
+// In-place step: tiles of kIpT keys (256 threads x 16), one bit per key.
+constexpr int kIpNT = 256;
+constexpr int kIpEPT = 16;
+constexpr int kIpT = kIpNT * kIpEPT;
+constexpr int kIpWords = kIpT / 64;  // 64-bit class words per tile
+
+// Per tile of an in-place level: counts from the count step, misplaced
+// counts and running sums from the scan step.  mis[0]: keys of the tile
+// left of the segment's boundary that are not class L; mis[1]: class-L
+// keys right of it.  rank[0]: mis[0] of the segment's earlier tiles;
+// rank[1]: mis[1] of the segment's tiles up to this one (inclusive), so
+// that the tile's misplaced keys right of the boundary have ranks
+// [M - rank[1], M - rank[1] + mis[1]) counted from the segment's right end
+// (M: the segment's misplaced keys per side).
+struct IpTile {
+    uint32_t nl, neq;
+    uint32_t mis[2];
+    uint32_t rank[2];
+    uint32_t pad[2];
 };
 
 // Per-tile copy of what a partition tile needs, written by the map kernel so
@@ -144,6 +176,9 @@ struct Args {
     int ways;   // 1: multiway partition levels (keys only)
     int retile; // 1: the first level's segments were tiled for another tile size (tail kernel)
     int shuffle; // stress test: tiles claimed out of order within windows of 64, delayed publication
+    int inplace; // 1: in-place levels (keys and payloads stay in x_keys / x_vals)
+    uint64_t* ipmask;        // in-place levels: class bits, kIpWords words per tile
+    IpTile* iptile;          // in-place levels: per tile counts and running sums
     uint64_t* splitters[2];  // per slot: 16 order keys per segment
     uint32_t* toff;          // per tile: offset of its keys inside each bucket
     uint32_t* bcur;          // per segment: bucket cursors (stride 32)
@@ -177,6 +212,14 @@ struct Ops {
     int (*persist_blocks_per_cu)();
     int persist_small_max;
     int multi_tile_keys;  // keys per tile of the multiway levels (0 without them)
+    // in-place levels: class bits and counts per tile, boundary and running
+    // sums per segment, exchange of misplaced keys per tile, children per
+    // segment; and the one-workgroup tail of an in-place sort
+    void (*ip_count)(const Args&, int grid, hipStream_t);
+    void (*ip_scan)(const Args&, int grid, hipStream_t);
+    void (*ip_exchange)(const Args&, int grid, hipStream_t);
+    void (*ip_complete)(const Args&, int grid, hipStream_t);
+    void (*ip_tail)(const Args&, hipStream_t);
 };
 
 // The map step of level `level`, as thread `gtid` of `gstride`: every tile

@@ -522,7 +522,9 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
             const int64_t lo = sd->lo, hi = sd->hi;
             const uint32_t t0 = sd->t0, nt = sd->nt;
             // every wave picks the same pivot; wave 0's is used
-            const R piv = segment_pivot<DT, NT>(a, src, lo, hi, sd->depth, true, lds);
+            const R pick = segment_pivot<DT, NT>(a, src, lo, hi, sd->depth, true, lds);
+            // an in-place segment whose pivot its parent fixed keeps it
+            const R piv = (sd->pad & kSegForced) ? static_cast<R>(sd->pivot_raw) : pick;
             const uint64_t po = static_cast<uint64_t>(K::ord(piv));
             if (part == 0 && tid == 0) {
                 sd->pivot = po;
@@ -557,8 +559,9 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
                 t0 = sd->t0;
                 nt = sd->nt;
             }
-            const R piv = segment_pivot<DT, NT>(a, src, lo, hi, depth, valid, lds);
+            const R pick = segment_pivot<DT, NT>(a, src, lo, hi, depth, valid, lds);
             if (valid) {
+                const R piv = (sd->pad & kSegForced) ? static_cast<R>(sd->pivot_raw) : pick;
                 if (lane == 0) {
                     sd->pivot = static_cast<uint64_t>(K::ord(piv));
                     sd->pivot_raw = static_cast<uint64_t>(piv);
@@ -2017,6 +2020,7 @@ __global__ __launch_bounds__(NT, 4) void k_persist(Args a) {
 }  // namespace bqs
 
 #include "bqs_multiway.hpp"
+#include "bqs_inplace.hpp"
 
 namespace bqs {
 
@@ -2100,6 +2104,22 @@ struct Launch {
     static void tail(const Args& a, hipStream_t s) {
         hipLaunchKernelGGL((k_persist<DT, V, NT, EPT, SMAX>), dim3(1), dim3(NT), 0, s, a);
     }
+    // in-place levels (tiles of kIpT keys) and their one-workgroup tail
+    static void ip_count(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_ip_count<DT, kIpNT, kIpEPT>), dim3(grid), dim3(kIpNT), 0, s, a);
+    }
+    static void ip_scan(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_ip_scan<256>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void ip_exchange(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_ip_exchange<DT, V, kIpNT, kIpEPT>), dim3(grid), dim3(kIpNT), 0, s, a);
+    }
+    static void ip_complete(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL(k_ip_complete<V>, dim3(grid), dim3(256), 0, s, a);
+    }
+    static void ip_tail(const Args& a, hipStream_t s) {
+        hipLaunchKernelGGL((k_ip_tail<DT, V, kIpNT, kIpEPT, SMAX>), dim3(1), dim3(kIpNT), 0, s, a);
+    }
     static int persist_blocks_per_cu() {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<DT, V, NT, EPT, kPersistSmall>, NT, 0) !=
@@ -2127,7 +2147,12 @@ struct Launch {
             &tail,
             &persist_blocks_per_cu,
             kPersistSmall,
-            MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::tile()};
+            MultiFns<DT, NT, EPT, std::is_same<V, NoVal>::value>::tile(),
+            &ip_count,
+            &ip_scan,
+            &ip_exchange,
+            &ip_complete,
+            &ip_tail};
         return &o;
     }
 };

@@ -137,7 +137,7 @@ def test_argument_errors_need_no_gpu(bqs):
         assert L.bqs_sort_noalloc(ctypes.c_void_p(64), -5, bqs.I32, None, None) == 1
         assert L.bqs_sort_noalloc(ctypes.c_void_p(64), 10, 42, None, None) == 2
         assert L.bqs_sort_noalloc(ctypes.c_void_p(64), 1 << 24, bqs.I32, None, None) == 7
-        assert L.bqs_sort_noalloc(ctypes.c_void_p(64), 8_000_000, bqs.F64, None, None) == 7
+        assert L.bqs_sort_noalloc(ctypes.c_void_p(64), 8_200_000, bqs.F64, None, None) == 7
     finally:
         L.bqs_ctx_destroy(h)
     L.bqs_ctx_destroy(None)
@@ -150,3 +150,23 @@ def test_binding_rejects_cpu_tensors(bqs):
         bqs.sort(torch.zeros(10, dtype=torch.int32))
     with pytest.raises(bqs.BqsError):
         bqs.Context().sort(torch.zeros(10, dtype=torch.int16))
+
+
+def test_inplace_workspace_is_a_fraction_of_the_double_buffer(bqs):
+    """In-place levels keep one class bit per key instead of a copy of the
+    keys and payloads: the workspace shrinks to a few percent."""
+    ws = bqs.lib.bqs_workspace_bytes
+    ctx = bqs.Context(inplace=1)
+    assert ctx.get_param("inplace") == 1
+    n = 1 << 24
+    for dt, vb, copy in ((bqs.I32, 0, 4), (bqs.F64, 0, 8), (bqs.U64, 4, 16), (bqs.I32, 8, 20)):
+        out = ws(None, n, dt, vb, 1)
+        inp = ws(ctx._h, n, dt, vb, 1)
+        assert out >= copy * n
+        # class bits (n / 8 bytes, per 4096-key tile) plus lists and counts:
+        # under a tenth of the double-buffered workspace
+        assert n // 8 <= inp < 0.1 * out, (dt, vb, inp, out)
+    # segments: lists grow with k, the class bits do not
+    assert ws(ctx._h, n, bqs.I32, 0, 20000) > ws(ctx._h, n, bqs.I32, 0, 1)
+    ctx.set_param("inplace", 0)
+    assert ws(ctx._h, n, bqs.I32, 0, 1) == ws(None, n, bqs.I32, 0, 1)
