@@ -171,6 +171,7 @@ def batched_segments(torch, bqs, steps, warmup, k=20000, seed=7, per_array=True,
 
     work.copy_(pristine)
     tuned = tune.autotune(work, off_d, graph=True, reps=1, path=None)
+    progress(f"batched: autotuner picked {tuned['plan']}")
     ctx = bqs.Context(graph=1, **tuned["plan"])
     times = []
     for i in range(warmup + steps):
@@ -314,11 +315,14 @@ def measured_traffic():
 
 def serving(torch, requests, seed=11, budget=64 << 30, workers=3):
     """Serving loop: Poisson arrivals of mixed requests (sizes log-uniform in
-    [2^10, 2^24]; 50 % int32, 30 % float64, 20 % uint64+uint32 pairs), admitted
-    under an HBM budget and batched continuously.  The arrival rate is 0.7 x
-    the service's saturated capacity, measured first on a burst of requests
-    that all arrive at once.  The same trace is then replayed with one plain
-    sort call per request, in arrival order on one stream."""
+    [2^10, 2^24]; 50 % int32, 30 % float64, 20 % uint64+uint32 pairs), placed
+    in a device arena under an HBM budget, batched continuously and sorted
+    where they sit (the service's default step: multiway for keys, two-way
+    for pairs).  The arrival rate is 0.7 x the service's saturated capacity,
+    measured first on a burst of requests that all arrive at once.  The
+    same burst is served with the in-place step (workspace a few percent of
+    a batch), and the trace is replayed with one plain sort call per
+    request, in arrival order on one stream."""
     from paper_1604_06697_amd import serve
 
     def fresh(tr):
@@ -336,6 +340,7 @@ def serving(torch, requests, seed=11, budget=64 << 30, workers=3):
     caps.sort(key=lambda c: c[0])
     mk, cap = caps[1]
     qps = 0.7 * len(burst) / mk
+    progress(f"serving: saturated capacity {cap['Gkeys/s']} Gkeys/s")
     trace = serve.make_trace(requests, qps=qps, seed=seed)
     sample = [r.rid for r in trace if r.rid % 100 == 0]
     trace, mk, svc = serve.run_service(trace, budget, workers=workers, seed_base=0, keep_inputs=sample)
@@ -348,9 +353,21 @@ def serving(torch, requests, seed=11, budget=64 << 30, workers=3):
         "saturated": {"requests": cap["requests"], "Gkeys/s": cap["Gkeys/s"],
                       "bursts_Gkeys/s": sorted(c[1]["Gkeys/s"] for c in caps)},
         "service": dict(serve.latency_summary(trace, mk), batches=svc.batches,
-                        peak_budget_GiB=round(svc.budget.peak / 2**30, 2)),
+                        step="multiway (pairs: two-way), out of place",
+                        workspace_GiB=round(svc.workspace_bytes / 2**30, 3),
+                        peak_device_GiB=round(svc.peak_bytes() / 2**30, 2)),
         "correct_sample": ok,
     }
+    progress(f"serving: service p50 {out['service']['p50_ms']} ms")
+    # the in-place step on the calibration burst: capacity and device memory
+    ib = fresh(burst)
+    ib, mk_i, isvc = serve.run_service(ib, budget, workers=workers, seed_base=(1 << 40) + 1,
+                                       keep_inputs=[r.rid for r in ib if r.rid % 50 == 0], params=dict(inplace=1))
+    out["inplace_saturated"] = dict(serve.latency_summary(ib, mk_i), step="in-place",
+                                    workspace_GiB=round(isvc.workspace_bytes / 2**30, 3),
+                                    peak_device_GiB=round(isvc.peak_bytes() / 2**30, 2),
+                                    correct_sample=check_requests(torch, [r for r in ib if r.rid % 50 == 0]))
+    progress(f"serving: in-place burst {out['inplace_saturated']['Gkeys/s']} Gkeys/s")
     base = fresh(trace)
     base, mk_b = serve.run_one_per_launch(base, seed_base=0, keep_inputs=sample)
     out["one_per_launch"] = dict(serve.latency_summary(base, mk_b),
@@ -514,6 +531,7 @@ def cpu_baseline(torch, n: int, gpu_sorted):
     out = orc.sort(host)
     t_or = time.perf_counter() - t0
     t0 = time.perf_counter()
+    progress("cpu baseline: oracle timed")
     ref = orc.std_sort(host)
     t_std = time.perf_counter() - t0
     same = bool(np.array_equal(out, ref)) and (gpu_sorted is None or bool(np.array_equal(out, gpu_sorted)))
@@ -680,6 +698,36 @@ def trace_summary(trace_dir: str, bench_json: str | None, counters: list[str]) -
     return "\n".join(out) + "\n"
 
 
+def progress(msg: str):
+    """One line per finished bench section on stderr (the JSON line stays
+    alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def inplace_lines(torch, bqs, n, steps):
+    """The in-place step (BQS_PARAM_INPLACE) on the headline input and on
+    the pairs workload: time, rate and workspace against the default step.
+    Algorithmic bytes per in-place level: the count pass reads every key,
+    the exchange reads and writes the tiles that hold misplaced keys (about
+    every tile on random input): 3 r per partitioned key."""
+    out = {}
+    for kind, nn, r, vb, code in (("i32_uniform", n, 4, 0, bqs.I32), ("pairs_u64_u32", n // 4, 12, 4, bqs.U64)):
+        ctx = bqs.Context(timing=1, inplace=1)
+        ms, st, _, part_ms, part_keys, ok = run_workload(torch, bqs, ctx, kind, nn, steps, 1)
+        ws_in = bqs.lib.bqs_workspace_bytes(ctx._h, nn, code, vb, 1)
+        ws_out = bqs.lib.bqs_workspace_bytes(None, nn, code, vb, 1)
+        ab = 3 * r * st["partitioned_keys"] + 2 * r * st["small_sorted_keys"]
+        out[kind] = {"n": nn, "ms": round(ms, 3), "Gkeys/s": round(nn / (ms * 1e-3) / 1e9, 3),
+                     "alg_GBps": round(ab / (ms * 1e-3) / 1e9, 1),
+                     "frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "partition_ms": round(st["partition_ms"], 3), "small_ms": round(st["small_ms"], 3),
+                     "plan_ms": round(st["plan_ms"], 3), "levels": st["levels"],
+                     "workspace_bytes": int(ws_in), "default_workspace_bytes": int(ws_out),
+                     "workspace_saved_bytes": int(ws_out - ws_in), "correct": ok}
+        ctx.close()
+    return out
+
+
 def main():
     if "--trace-summary" in sys.argv:
         ap = argparse.ArgumentParser()
@@ -759,6 +807,7 @@ def main():
         "copy_context": copy_bandwidth(torch),
     }
 
+    progress(f"headline: {ms:.3f} ms per sort")
     # per-phase breakdown of one more sort with every launch timed (outside
     # the timed region: the extra events cost the host time)
     bctx = bqs.Context(timing=1)
@@ -779,6 +828,11 @@ def main():
                        "partition_ms": round(mst["partition_ms"], 3), "small_ms": round(mst["small_ms"], 3),
                        "plan_ms": round(mst["plan_ms"], 3), "levels": mst["levels"],
                        "partitioned_keys": mst["partitioned_keys"], "small_cutoff": 8192, "correct": mok}
+
+    progress("breakdown and multiway done")
+    # the in-place step: keys never leave the caller's buffer, the workspace
+    # holds one class bit per key instead of a second copy of the keys
+    out["inplace"] = inplace_lines(torch, bqs, n, max(2, args.steps // 2))
 
     if not args.no_dists:
         dists = {}
@@ -802,16 +856,20 @@ def main():
             }
         out["distributions"] = dists
 
+    progress("in-place and distributions done")
     if not args.no_dists:
         out["paper_families"] = paper_families(torch, bqs)
         out["pivot_study"] = pivot_study(torch, bqs, n)
         out["records"] = records(torch, bqs)
 
+    progress("paper families, pivot study and records done")
     if not args.no_batched:
         out["segmented"] = batched_segments(torch, bqs, max(2, args.steps // 3), 2, cpu=not args.no_cpu)
 
+    progress("batched segments done")
     if not args.no_serve:
         out["serving"] = serving(torch, args.serve_requests)
+        progress("serving done")
 
     # persistent mode: every level in one cooperative launch, one host wait.
     # Runs after the serving loop: once a process has made a cooperative
@@ -825,6 +883,7 @@ def main():
                              "levels": pst["levels"], "partition_launches": pst["partition_launches"],
                              "small_cutoff": pst["small_cutoff"], "correct": pok}
 
+    progress("persistent done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(torch, n, kept[0] if kept else None)
     print(json.dumps(out), flush=True)

@@ -365,6 +365,13 @@ bqs_status bqs_sort_records(const void* in, void* out, int64_t n, int kind, bqs_
  * call, or an error an asynchronous call returned -- and clears it. */
 bqs_status bqs_ctx_sync_status(bqs_ctx* ctx);
 
+/* Returns the first error latched by this context's calls that have
+ * completed so far -- without waiting for the calls still running -- and
+ * clears it (BQS_OK when there is none).  For callers that track each
+ * call's completion themselves (an event recorded after the call) and
+ * must not block on the calls enqueued after it. */
+bqs_status bqs_ctx_poll_status(bqs_ctx* ctx);
+
 /* Static, human-readable name of a status code. */
 const char* bqs_status_str(bqs_status status);
 

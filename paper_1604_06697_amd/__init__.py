@@ -81,7 +81,7 @@ EXPORTED = [
     "bqs_ctx_set_param", "bqs_ctx_get_param", "bqs_ctx_get_stats", "bqs_ctx_get_level",
     "bqs_workspace_bytes",
     "bqs_sort", "bqs_sort_pairs", "bqs_sort_segments", "bqs_sort_segments_pairs",
-    "bqs_records_workspace_bytes", "bqs_sort_records", "bqs_ctx_sync_status",
+    "bqs_records_workspace_bytes", "bqs_sort_records", "bqs_ctx_sync_status", "bqs_ctx_poll_status",
     "bqs_status_str", "bqs_version", "bqs_sort_noalloc",
 ]
 
@@ -151,6 +151,7 @@ def _load(path: str = LIBRARY) -> ctypes.CDLL:
         "bqs_records_workspace_bytes": ([vp, i64, ctypes.c_int], sz),
         "bqs_sort_records": ([vp, vp, i64, ctypes.c_int, vp], st),
         "bqs_ctx_sync_status": ([vp], st),
+        "bqs_ctx_poll_status": ([vp], st),
         "bqs_status_str": ([st], ctypes.c_char_p),
         "bqs_version": ([], ctypes.c_int),
         "bqs_sort_noalloc": ([vp, i64, ctypes.c_int, vp, vp], st),
@@ -269,6 +270,17 @@ class Context:
         """Waits for every call enqueued on this context; raises BqsError for
         the first error the device latched since the last synchronize()."""
         _check(lib.bqs_ctx_sync_status(self._h), "bqs_ctx_sync_status")
+
+    def poll(self):
+        """Raises BqsError for the first error latched by calls that have
+        completed so far, without waiting for the others."""
+        _check(lib.bqs_ctx_poll_status(self._h), "bqs_ctx_poll_status")
+
+    def reserve(self, nbytes: int, device=None):
+        """Allocates the workspace up front (at least `nbytes`), so that
+        later calls of up to that size allocate nothing."""
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._prepare(dev, int(nbytes))
 
     def stats(self) -> dict:
         s = Stats()

@@ -1342,6 +1342,14 @@ bqs_status bqs_ctx_sync_status(bqs_ctx* ctx) {
     return st;
 }
 
+bqs_status bqs_ctx_poll_status(bqs_ctx* ctx) {
+    if (!ctx) return BQS_EINVAL;
+    harvest(ctx, false);
+    const bqs_status st = ctx->latched;
+    ctx->latched = BQS_OK;
+    return st;
+}
+
 const char* bqs_status_str(bqs_status s) {
     switch (s) {
         case BQS_OK: return "ok";

@@ -34,27 +34,59 @@ def test_form_batch_takes_oldest_kind_in_arrival_order(serve):
     assert serve.form_batch(deque(), 10) == []
 
 
-def test_budget_blocks_until_release(serve):
-    b = serve.Budget(100)
-    assert b.try_acquire(60)
-    assert not b.try_acquire(50)
+def test_form_batch_stops_where_the_ring_slots_do_not_follow(serve):
+    R = serve.Request
+    # ring positions: 0, 10 follow each other; 17 does not follow 10 + 5 = 15
+    # (a wrap or another type's slots in between); 15 does
+    w = deque([R(0, "i32", 10, 0.0, pos=0), R(1, "i32", 5, 0.1, pos=10), R(2, "i32", 3, 0.2, pos=17),
+               R(3, "i32", 4, 0.3, pos=15)])
+    b = serve.form_batch(w, max_keys=100)
+    assert [r.rid for r in b] == [0, 1, 3]
+    assert [r.rid for r in w] == [2]
+
+
+def test_ring_allocates_in_order_wraps_and_reuses_released_space(serve):
+    ring = serve.Ring(100)
+    a = ring.alloc(40)
+    b = ring.alloc(40)
+    assert (a, b) == (0, 40)
+    assert ring.try_alloc(30) is None          # 20 free at the end, 0 at the start
+    ring.release(b)                            # out of order: the oldest is still live
+    assert ring.used == 40 and ring.try_alloc(30) is None
+    ring.release(a)                            # now everything is free again
+    assert ring.used == 0
+    c = ring.alloc(70)
+    assert c == 0
+    d = ring.try_alloc(30)
+    assert d == 70
+    ring.release(c)
+    e = ring.alloc(50)                         # wraps to the start, before d
+    assert e == 0
+    assert ring.try_alloc(21) is None          # 20 free between e and d
+    f = ring.alloc(20)
+    assert f == 50
+    assert ring.peak == 100
+    with pytest.raises(ValueError):
+        ring.alloc(101)
+
+
+def test_ring_alloc_blocks_until_release(serve):
+    ring = serve.Ring(100)
+    a = ring.alloc(60)
     got = []
-    t = threading.Thread(target=lambda: (b.acquire(50), got.append(1)))
+    t = threading.Thread(target=lambda: got.append(ring.alloc(50)))
     t.start()
     t.join(0.1)
     assert not got
-    b.release(60)
+    ring.release(a)
     t.join(2.0)
-    assert got == [1] and b.used == 50 and b.peak == 60
-    # a request larger than the whole budget is admitted alone
-    b.release(50)
-    assert b.try_acquire(1000)
+    assert got == [0] and ring.used == 50 and ring.peak == 60
 
 
-def test_footprint_counts_input_batch_and_workspace(serve):
-    assert serve.footprint("i32", 1000) == 1000 * (2 * 4 + 4)
-    assert serve.footprint("f64", 1000) == 1000 * (2 * 8 + 8)
-    assert serve.footprint("pairs", 1000) == 1000 * (2 * 12 + 8 + 8)
+def test_footprint_is_the_request_in_the_arena(serve):
+    assert serve.footprint("i32", 1000) == 1000 * 4
+    assert serve.footprint("f64", 1000) == 1000 * 8
+    assert serve.footprint("pairs", 1000) == 1000 * 12
 
 
 def test_trace_shape(serve):
@@ -88,7 +120,8 @@ def test_latency_summary_nearest_rank(serve):
 
 
 @pytest.mark.gpu
-def test_results_same_alone_and_in_the_mix(serve, oracle):
+@pytest.mark.parametrize("params", [None, {"inplace": 1}], ids=["default", "inplace"])
+def test_results_same_alone_and_in_the_mix(serve, oracle, params):
     import torch
 
     if not torch.cuda.is_available():
@@ -96,10 +129,11 @@ def test_results_same_alone_and_in_the_mix(serve, oracle):
     import paper_1604_06697_amd as bqs
 
     trace = serve.make_trace(240, qps=4000.0, seed=5, lo_exp=10, hi_exp=17)
-    print(f"[case] serving mix of {len(trace)} requests", flush=True)
+    print(f"[case] serving mix of {len(trace)} requests, params {params}", flush=True)
     trace, makespan, svc = serve.run_service(trace, budget_bytes=1 << 30, workers=3, seed_base=100,
-                                             keep_inputs=[r.rid for r in trace])
+                                             keep_inputs=[r.rid for r in trace], params=params)
     assert svc.batches < len(trace)  # requests were batched together
+    assert svc.peak_bytes() <= 1 << 30
     alone = bqs.Context()
     for r in trace:
         assert r.done >= r.arrival
