@@ -52,7 +52,7 @@ __device__ void clear_ctl(Ctl* c) {
             c->lc[s].fills = 0;
             for (int k = 0; k < kSmallClasses; ++k) c->lc[s].smalls[k] = 0;
             c->lc[s].tile_next = 0;
-            c->lc[s].pad = 0;
+            c->lc[s].tab = 0;
             c->lc[s].keys = 0;
         }
         c->error = 0;
@@ -229,7 +229,8 @@ void launch_init_segments(const Args& a, hipStream_t s) {
 struct Layout {
     size_t ctl, yk, yv, side, segs[2], smalls[2], fills[2], tile_desc, status, total;
     size_t splitters[2], toff, bcur, bstart;
-    size_t ipmask, iptile;
+    size_t ipmask, iptile, iprank;
+    uint64_t cap_tab;
     uint64_t cap_seg, cap_tile, cap_small, cap_fill;
 };
 
@@ -276,6 +277,8 @@ static Layout make_layout(int64_t n, size_t kb, size_t vb, int64_t k, int64_t T,
     L.bstart = take(mw ? L.cap_seg * 32 * sizeof(uint32_t) : 0);
     L.ipmask = take(inplace ? L.cap_tile * kIpWords * sizeof(uint64_t) : 0);
     L.iptile = take(inplace ? L.cap_tile * sizeof(IpTile) : 0);
+    L.cap_tab = inplace ? un / kIpRankStep + 2 * L.cap_seg + 2 : 0;
+    L.iprank = take(L.cap_tab * sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -653,9 +656,10 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
         const int tg = clamp_grid(tb, 0x7fffffff);
         if (tm) tm->start();
         if (a.inplace) {
-            o->ip_count(a, tg, s);
+            // (the per-tile kernels loop over the level's tiles)
+            o->ip_count(a, clamp_grid(tb, 32768), s);
             o->ip_scan(a, clamp_grid(sb, 2048), s);
-            o->ip_exchange(a, tg, s);
+            o->ip_exchange(a, clamp_grid(tb, 8192), s);
             if (tm) tm->stop(2, L);
             if (tm) tm->start_aux();
             o->ip_complete(a, clamp_grid((sb + 255) / 256, 1024), s);
@@ -825,9 +829,9 @@ bqs_status run_levels(bqs_ctx* ctx, const Ops* o, Args& a, bool segmented, int d
         lkeys.push_back(static_cast<int64_t>(cur.keys));
         tm.start();
         if (a.inplace) {
-            o->ip_count(a, static_cast<int>(ntile), s);
+            o->ip_count(a, clamp_grid(ntile, 32768), s);
             o->ip_scan(a, clamp_grid(nseg, 16384), s);
-            o->ip_exchange(a, static_cast<int>(ntile), s);
+            o->ip_exchange(a, clamp_grid(ntile, 8192), s);
             tm.stop(2, L);
             tm.start_aux();
             o->ip_complete(a, clamp_grid((nseg + 255) / 256, 4096), s);
@@ -918,7 +922,8 @@ bqs_status prepare_in(const bqs_ctx* ctx, void* ws, size_t ws_bytes, const Ops* 
     const bool inplace = ctx && ctx->inplace;
     const bool multiway = ctx && ctx->multiway && o->mscan && !inplace;
     const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S, multiway, inplace);
-    if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull)
+    if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull ||
+        L.cap_tab > 0xffffffffull)
         return BQS_EINVAL;
     if (!ws || ws_bytes < L.total) return BQS_EINVAL;
     if (overlaps(keys, static_cast<size_t>(n) * kb, ws, ws_bytes)) return BQS_EINVAL;
@@ -937,6 +942,8 @@ bqs_status prepare_in(const bqs_ctx* ctx, void* ws, size_t ws_bytes, const Ops* 
         a.side = nullptr;
         a.ipmask = reinterpret_cast<uint64_t*>(w + L.ipmask);
         a.iptile = reinterpret_cast<IpTile*>(w + L.iptile);
+        a.iprank = reinterpret_cast<uint32_t*>(w + L.iprank);
+        a.cap_tab = static_cast<uint32_t>(L.cap_tab);
         a.inplace = 1;
     } else {
         a.y_keys = w + L.yk;

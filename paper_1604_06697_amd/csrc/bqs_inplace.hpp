@@ -129,8 +129,8 @@ __global__ __launch_bounds__(NT) void k_ip_count(Args a) {
     const int p = a.level & 1;
     uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
     if (ntiles > a.cap_tile) ntiles = a.cap_tile;
-    if (blockIdx.x >= ntiles || c->error) return;  // (an error latched by an earlier step: nothing runs)
-    ip_count_tile<DT, NT, EPT>(a, p, blockIdx.x, s_red);
+    if (c->error) return;  // an earlier step latched an error: the rest of the call does nothing
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) ip_count_tile<DT, NT, EPT>(a, p, t, s_red);
 }
 
 // ------------------------------------------------------------------- scan --
@@ -138,13 +138,13 @@ __global__ __launch_bounds__(NT) void k_ip_count(Args a) {
 // Exclusive prefix sum over the workgroup (NT threads, one value each) and
 // the workgroup total.  s_w: NT/64 words of LDS.
 template <int NT>
-__device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* s_w, uint32_t& total) {
+__device__ __forceinline__ uint64_t block_exclusive_sum(uint64_t v, uint64_t* s_w, uint64_t& total) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const uint32_t inc = static_cast<uint32_t>(wave_inclusive_sum(static_cast<uint64_t>(v), lane));
+    const uint64_t inc = wave_inclusive_sum(v, lane);
     if (lane == 63) s_w[wv] = inc;
     __syncthreads();
-    uint32_t before = 0;
+    uint64_t before = 0;
     total = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -155,83 +155,123 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* s_
     return before + inc - v;
 }
 
+// Class-L keys of tile (t0 + j) of a segment left of the boundary b.
+__device__ __forceinline__ uint32_t class_left_of(const Args& a, uint32_t t, int k) {
+    const uint64_t* mw = a.ipmask + static_cast<size_t>(t) * kIpWords;
+    uint32_t left = 0;
+    for (int w = 0; w < (k >> 6); ++w) left += static_cast<uint32_t>(__popcll(mw[w]));
+    if (k & 63) left += static_cast<uint32_t>(__popcll(mw[k >> 6] & bits_between(0, k & 63)));
+    return left;
+}
+
+// One segment of an in-place level, by all NT threads of a workgroup, in
+// three passes over its tiles (TPT consecutive tiles per thread and pass):
+// (1) its class-L keys and keys equal to the pivot, hence the boundary;
+// (2) per tile the misplaced keys on each side and the ranks of the first
+// ones from the left end (left side) and, for now, the running sum from the
+// left (right side); (3) the right-side ranks counted from the right end,
+// the segment's values in every tile, and the rank table of the partner
+// side.
 template <int NT>
-__device__ void ip_scan_segment(const Args& a, int p, uint32_t si, uint32_t* s_w) {
-    constexpr int NW = NT / 64;
+__device__ void ip_scan_segment(const Args& a, int p, uint32_t si, uint64_t* s_w) {
+    constexpr int TPT = 8;
+    constexpr uint32_t CH = NT * TPT;
     const int tid = threadIdx.x;
     SegDesc* sd = &a.segs[p][si];
     const int64_t lo = sd->lo, hi = sd->hi;
     const uint32_t t0 = sd->t0, nt = sd->nt;
-    // class-L keys and keys equal to the pivot
+    __shared__ uint32_t s_tbase;
+    // (1)
     uint64_t nl = 0, ne = 0;
     for (uint32_t j = tid; j < nt; j += NT) {
         nl += a.iptile[t0 + j].nl;
         ne += a.iptile[t0 + j].neq;
     }
-    nl = wave_sum(nl);
-    ne = wave_sum(ne);
-    __shared__ unsigned long long s_tot[2][NW];
-    if ((tid & 63) == 0) {
-        s_tot[0][tid >> 6] = nl;
-        s_tot[1][tid >> 6] = ne;
-    }
-    __syncthreads();
-    nl = ne = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        nl += s_tot[0][w];
-        ne += s_tot[1][w];
-    }
-    __syncthreads();
+    uint64_t tot = 0;
+    (void)block_exclusive_sum<NT>((nl << 32) | ne, s_w, tot);
+    nl = tot >> 32;
+    ne = tot & 0xffffffffull;
     const int64_t b = lo + static_cast<int64_t>(nl);
-    // misplaced keys per tile and side, with running sums
-    uint32_t carry_l = 0, carry_r = 0;
-    for (uint32_t jb = 0; jb < nt; jb += NT) {
-        const uint32_t j = jb + tid;
-        uint32_t mis_l = 0, mis_r = 0;
-        if (j < nt) {
-            const int64_t tlo = lo + static_cast<int64_t>(j) * kIpT;
-            const int64_t thi = hi - tlo < kIpT ? hi : tlo + kIpT;
-            const uint32_t tnl = a.iptile[t0 + j].nl;
-            if (thi <= b) {
-                mis_l = static_cast<uint32_t>(thi - tlo) - tnl;
-            } else if (tlo >= b) {
-                mis_r = tnl;
-            } else {
-                // the tile holding the boundary: class-L keys left of it
-                const int k = static_cast<int>(b - tlo);
-                const uint64_t* mw = a.ipmask + static_cast<size_t>(t0 + j) * kIpWords;
-                uint32_t left = 0;
-                for (int w = 0; w < (k >> 6); ++w) left += static_cast<uint32_t>(__popcll(mw[w]));
-                if (k & 63) left += static_cast<uint32_t>(__popcll(mw[k >> 6] & bits_between(0, k & 63)));
-                mis_l = static_cast<uint32_t>(k) - left;
-                mis_r = tnl - left;
+    const bool aright = b - lo < hi - b;  // the right part is the larger one
+    // (2)
+    uint64_t carry = 0;  // misplaced so far: left side << 32 | right side
+    for (uint32_t jb = 0; jb < nt; jb += CH) {
+        const uint32_t j0 = jb + static_cast<uint32_t>(tid) * TPT;
+        uint32_t ml[TPT], mr[TPT];
+        uint64_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < TPT; ++i) {
+            const uint32_t j = j0 + i;
+            ml[i] = mr[i] = 0;
+            if (j < nt) {
+                const int64_t tlo = lo + static_cast<int64_t>(j) * kIpT;
+                const int64_t thi = hi - tlo < kIpT ? hi : tlo + kIpT;
+                const uint32_t tnl = a.iptile[t0 + j].nl;
+                if (thi <= b) {
+                    ml[i] = static_cast<uint32_t>(thi - tlo) - tnl;
+                } else if (tlo >= b) {
+                    mr[i] = tnl;
+                } else {
+                    const int k = static_cast<int>(b - tlo);
+                    const uint32_t left = class_left_of(a, t0 + j, k);
+                    ml[i] = static_cast<uint32_t>(k) - left;
+                    mr[i] = tnl - left;
+                }
+                mine += (static_cast<uint64_t>(ml[i]) << 32) | mr[i];
             }
         }
-        uint32_t tot_l = 0, tot_r = 0;
-        const uint32_t ex_l = block_exclusive_sum<NT>(mis_l, s_w, tot_l);
-        const uint32_t ex_r = block_exclusive_sum<NT>(mis_r, s_w, tot_r);
-        if (j < nt) {
-            IpTile& it = a.iptile[t0 + j];
-            it.mis[0] = mis_l;
-            it.mis[1] = mis_r;
-            it.rank[0] = carry_l + ex_l;
-            it.rank[1] = carry_r + ex_r + mis_r;
+        uint64_t ctot = 0;
+        uint64_t run = carry + block_exclusive_sum<NT>(mine, s_w, ctot);
+#pragma unroll
+        for (int i = 0; i < TPT; ++i) {
+            const uint32_t j = j0 + i;
+            if (j < nt) {
+                IpTile& it = a.iptile[t0 + j];
+                it.mis[0] = ml[i];
+                it.mis[1] = mr[i];
+                it.rank[0] = static_cast<uint32_t>(run >> 32);
+                run += (static_cast<uint64_t>(ml[i]) << 32) | mr[i];
+                it.rank[1] = static_cast<uint32_t>(run);  // inclusive, from the left: converted in (3)
+            }
         }
-        carry_l += tot_l;
-        carry_r += tot_r;
+        carry += ctot;
     }
+    const uint32_t M = static_cast<uint32_t>(carry);  // == carry >> 32
     if (tid == 0) {
-        if (carry_l != carry_r) atomicOr(&a.ctl->error, ERR_OVERFLOW);  // inconsistent counts
-        sd->cursor = static_cast<unsigned long long>(nl) | (static_cast<unsigned long long>(ne) << 32);
-        sd->pad = (sd->pad & kSegForced) | (b - lo < hi - b ? kSegARight : 0u);
+        if ((carry >> 32) != (carry & 0xffffffffull)) atomicOr(&a.ctl->error, ERR_OVERFLOW);  // inconsistent
+        const uint32_t entries = (M + kIpRankStep - 1) / kIpRankStep;
+        uint32_t tb = atomicAdd(&a.ctl->lc[p].tab, entries);
+        if (tb + entries > a.cap_tab) {
+            atomicOr(&a.ctl->error, ERR_OVERFLOW);
+            tb = 0;
+        }
+        s_tbase = tb;
+        sd->cursor = nl | (ne << 32);
+        sd->pad = (sd->pad & kSegForced) | (aright ? kSegARight : 0u);
+    }
+    __syncthreads();
+    const uint32_t tbase = s_tbase;
+    const int bside = aright ? 0 : 1;  // the partner side: the smaller part
+    // (3)
+    for (uint32_t j = tid; j < nt; j += NT) {
+        IpTile& it = a.iptile[t0 + j];
+        const uint32_t r1 = M - it.rank[1];
+        it.rank[1] = r1;
+        it.seg_nl = static_cast<uint32_t>(nl);
+        it.flags = aright ? kSegARight : 0u;
+        it.tbase = tbase;
+        // partner-side tiles: entry e names the tile of rank e * step
+        const uint32_t rb = bside == 0 ? it.rank[0] : r1;
+        const uint32_t m = it.mis[bside];
+        for (uint32_t e = (rb + kIpRankStep - 1) / kIpRankStep; e * kIpRankStep < rb + m; ++e)
+            if (tbase + e < a.cap_tab) a.iprank[tbase + e] = t0 + j;
     }
     __syncthreads();
 }
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_ip_scan(Args a) {
-    __shared__ uint32_t s_w[NT / 64];
+    __shared__ uint64_t s_w[NT / 64];
     const Ctl* c = a.ctl;
     if (c->error) return;  // an earlier step latched an error: the rest of the call does nothing
     const int p = a.level & 1;
@@ -251,170 +291,185 @@ struct IpLds {
     R k[T];                  // the owning tile's part, by tile offset
     VS v[HV ? T : 1];
     uint16_t pos[T];         // tile offset of the owned misplaced key of local rank i
-    uint32_t wpre[T / 64];   // per class word: misplaced keys in the words before it (in rank order)
-    uint32_t omin, omax;     // offsets of a partner tile that this workgroup owns
-    uint32_t u;              // first partner tile
 };
 
-// Per class word w of tile `t` (wave 0, lane w): misplaced keys of part
-// [s0, s1) on side `side` in the words that precede w in rank order
-// (ascending offsets on the left side, descending on the right side).
-template <int NT>
-__device__ __forceinline__ void ip_word_prefix(const Args& a, uint32_t t, int s0, int s1, int side, uint32_t* wpre) {
+// The class words of tile t seen by one wave: lane w holds word w, its
+// misplaced bits for part [s0, s1) on side `side`, and the misplaced keys
+// of the words before it in rank order (ascending offsets on the left side,
+// descending on the right side).
+struct IpWords {
+    uint64_t bits;
+    uint32_t before;
+};
+
+__device__ __forceinline__ IpWords ip_words(const Args& a, uint32_t t, int s0, int s1, int side, int lane) {
     static_assert(kIpWords == 64, "one class word per lane");
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        const uint64_t word = a.ipmask[static_cast<size_t>(t) * kIpWords + tid];
-        const uint64_t m = misplaced_bits(word, tid, s0, s1, side);
-        const uint64_t c = static_cast<uint64_t>(__popcll(m));
-        const uint64_t inc = wave_inclusive_sum(c, tid);
-        const uint64_t tot = bcast64(inc, 63);
-        wpre[tid] = static_cast<uint32_t>(side == 0 ? inc - c : tot - inc);
-    }
+    IpWords r;
+    const uint64_t word = a.ipmask[static_cast<size_t>(t) * kIpWords + lane];
+    r.bits = misplaced_bits(word, lane, s0, s1, side);
+    const uint64_t c = static_cast<uint64_t>(__popcll(r.bits));
+    const uint64_t inc = wave_inclusive_sum(c, lane);
+    const uint64_t tot = bcast64(inc, 63);
+    r.before = static_cast<uint32_t>(side == 0 ? inc - c : tot - inc);
+    return r;
 }
 
-// Rank (within its tile part, in rank order) of the key at lane `lane` of
-// class word w, whose misplaced bits are m.
-__device__ __forceinline__ uint32_t ip_local_rank(uint64_t m, uint32_t before, int lane, int side) {
+// Misplaced keys of word w that precede lane `lane` in rank order.
+__device__ __forceinline__ uint32_t ip_rank_in_word(uint64_t m, int lane, int side) {
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint64_t above = lane == 63 ? 0ull : (~0ull << (lane + 1));
-    return before + static_cast<uint32_t>(__popcll(m & (side == 0 ? below : above)));
+    return static_cast<uint32_t>(__popcll(m & (side == 0 ? below : above)));
 }
 
 template <int DT, class V, int NT, int EPT>
-__device__ void ip_exchange_tile(const Args& a, int p, uint32_t t, IpLds<DT, V, NT, EPT>& L) {
+__device__ void ip_exchange_tile(const Args& a, uint32_t t, IpLds<DT, V, NT, EPT>& L) {
     using R = typename KeyT<DT>::raw;
     using VS = typename ValStore<V>::type;
     constexpr bool HV = !std::is_same<V, NoVal>::value;
     constexpr int T = NT * EPT;
     constexpr int NW = NT / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const TileDesc td = a.tile_desc[t];
-    const SegDesc& sd = a.segs[p][td.si];
-    const int64_t b = td.lo + static_cast<int64_t>(sd.cursor & 0xffffffffull);
-    const int aside = (sd.pad & kSegARight) ? 1 : 0, bside = 1 - aside;
-    const uint32_t c = a.iptile[t].mis[aside];
+    // opaque: keeps the per-item offsets and lane masks from being hoisted
+    // out of the caller's loop over tiles (and spilled across it)
+    const int tid = opaque(static_cast<int>(threadIdx.x)), lane = tid & 63, wv = tid >> 6;
+    // (fields picked with selects: an array member indexed at run time
+    // would put the copy in scratch memory)
+    const IpTile me = a.iptile[t];
+    const int aside = (me.flags & kSegARight) ? 1 : 0, bside = 1 - aside;
+    const uint32_t c = aside ? me.mis[1] : me.mis[0];
     if (c == 0) return;
-    const uint32_t tl = td.t0 + sd.nt - 1;  // the segment's last tile
-    const uint32_t M = a.iptile[tl].rank[1];
-    const uint32_t base = aside == 0 ? a.iptile[t].rank[0] : M - a.iptile[t].rank[1];
+    const TileDesc td = a.tile_desc[t];
+    const int64_t b = td.lo + static_cast<int64_t>(me.seg_nl);
+    const uint32_t base = aside ? me.rank[1] : me.rank[0];
+    const uint32_t nt = seg_tiles(td.lo, td.hi, T);
     const int64_t tlo = td.lo + static_cast<int64_t>(t - td.t0) * T;
     const int len = static_cast<int>(td.hi - tlo < T ? td.hi - tlo : T);
     int s0, s1;
     side_part(tlo, len, b, aside, s0, s1);
-    R* keys = static_cast<R*>(a.x_keys);
-    VS* vals = static_cast<VS*>(a.x_vals);
-    const uint64_t* mw = a.ipmask + static_cast<size_t>(t) * kIpWords;
+    // tile base pointers (uniform): per-item addresses are 32-bit offsets
+    R* const tk = static_cast<R*>(a.x_keys) + tlo;
+    VS* const tv = static_cast<VS*>(a.x_vals) + (HV ? tlo : 0);
 
-    // 1. the owning tile's part into LDS; the tile offset of each owned
-    // misplaced key by its rank
-    ip_word_prefix<NT>(a, t, s0, s1, aside, L.wpre);
-    if (tid == 0) {
-        // first partner tile: bside 0 (left, ascending ranks) the first tile
-        // whose ranks reach past `base`; bside 1 (right, ranks from the
-        // right end) the first tile whose running sum reaches M - base
-        uint32_t lo_i = td.t0, hi_i = tl;
-        while (lo_i < hi_i) {
-            const uint32_t mid = (lo_i + hi_i) >> 1;
-            const bool past = bside == 0 ? a.iptile[mid].rank[0] + a.iptile[mid].mis[0] > base
-                                         : a.iptile[mid].rank[1] >= M - base;
-            if (past) hi_i = mid; else lo_i = mid + 1;
-        }
-        L.u = lo_i;
-    }
-    __syncthreads();
+    // 1. the owning tile's part into LDS; the offset of each owned
+    // misplaced key by its rank.  The loads are issued first, so that they
+    // overlap the lookup of the first partner tile.
+    R own_k[EPT];
+    VS own_v[HV ? EPT : 1];
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
         const int o = r * NT + tid;
         if (o >= s0 && o < s1) {
-            L.k[o] = keys[tlo + o];
-            if constexpr (HV) L.v[o] = vals[tlo + o];
+            own_k[r] = tk[o];
+            if constexpr (HV) own_v[r] = tv[o];
         }
+    }
+    const IpWords wd = ip_words(a, t, s0, s1, aside, lane);
+    // first partner tile: the table names the tile holding rank
+    // floor(base / step) * step; walk on in rank order to the one holding base
+    uint32_t u = a.iprank[me.tbase + base / kIpRankStep];
+    for (;;) {
+        const IpTile ut = a.iptile[u];
+        if (base < (bside ? ut.rank[1] + ut.mis[1] : ut.rank[0] + ut.mis[0])) break;
+        u = bside == 0 ? u + 1 : u - 1;
+        if (u < td.t0 || u >= td.t0 + nt) break;  // inconsistent ranks (caught below)
     }
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
+        const int o = r * NT + tid;
+        if (o >= s0 && o < s1) {
+            L.k[o] = own_k[r];
+            if constexpr (HV) L.v[o] = own_v[r];
+        }
         const int w = r * NW + wv;
-        const uint64_t m = misplaced_bits(mw[w], w, s0, s1, aside);
-        if ((m >> lane) & 1ull) L.pos[ip_local_rank(m, L.wpre[w], lane, aside)] = static_cast<uint16_t>(r * NT + tid);
+        const uint64_t m = bcast64(wd.bits, w);
+        const uint32_t before = static_cast<uint32_t>(__shfl(static_cast<int>(wd.before), w, 64));
+        if ((m >> lane) & 1ull)
+            L.pos[before + ip_rank_in_word(m, lane, aside)] = static_cast<uint16_t>(o);
     }
-    const uint32_t first = L.u;
     __syncthreads();
 
     // 2. partner tiles in rank order; each swaps its share of ranks
     // [base, base + c) with the owned keys through LDS
     uint32_t covered = 0;
-    uint32_t u = first;
     while (covered < c) {
-        if (u < td.t0 || u > tl) {
-            if (tid == 0) atomicOr(&a.ctl->error, ERR_OVERFLOW);  // inconsistent running sums
+        if (u < td.t0 || u >= td.t0 + nt) {
+            if (tid == 0) atomicOr(&a.ctl->error, ERR_OVERFLOW);  // inconsistent ranks
             break;
         }
-        const uint32_t umis = a.iptile[u].mis[bside];
-        const uint32_t ubase = bside == 0 ? a.iptile[u].rank[0] : M - a.iptile[u].rank[1];
-        const uint32_t r0 = ubase > base ? ubase : base;
-        const uint32_t r1 = ubase + umis < base + c ? ubase + umis : base + c;
+        const IpTile ut = a.iptile[u];
+        const uint32_t ub = bside ? ut.rank[1] : ut.rank[0], um = bside ? ut.mis[1] : ut.mis[0];
+        const uint32_t r0 = ub > base ? ub : base;
+        const uint32_t r1 = ub + um < base + c ? ub + um : base + c;
         if (r1 > r0) {
             const int64_t ulo = td.lo + static_cast<int64_t>(u - td.t0) * T;
             const int ulen = static_cast<int>(td.hi - ulo < T ? td.hi - ulo : T);
             int q0, q1;
             side_part(ulo, ulen, b, bside, q0, q1);
-            const uint64_t* uw = a.ipmask + static_cast<size_t>(u) * kIpWords;
-            ip_word_prefix<NT>(a, u, q0, q1, bside, L.wpre);
-            if (tid == 0) {
-                L.omin = 0xffffffffu;
-                L.omax = 0u;
-            }
-            __syncthreads();
-            // which of this thread's keys are partners, and their ranks
-            uint32_t idx[EPT];
-            uint32_t mine = 0;
-            uint32_t omin = 0xffffffffu, omax = 0;
-#pragma unroll
-            for (int r = 0; r < EPT; ++r) {
+            const IpWords wd = ip_words(a, u, q0, q1, bside, lane);
+            R* const uk = static_cast<R*>(a.x_keys) + ulo;
+            VS* const uv = static_cast<VS*>(a.x_vals) + (HV ? ulo : 0);
+            // a key is this workgroup's if it is a partner (rank in [r0, r1))
+            // or lies between two of them: counted in rank order, the
+            // misplaced keys before it number between lr0 and lr1.  Only
+            // two bit masks live across the loads; the ranks are recomputed
+            // for the swaps.
+            const uint32_t lr0 = r0 - ub, lr1 = r1 - ub;
+            auto before_of = [&](int r, uint64_t& m) -> uint32_t {
                 const int w = r * NW + wv;
-                const uint64_t m = misplaced_bits(uw[w], w, q0, q1, bside);
-                const uint32_t rk = ubase + ip_local_rank(m, L.wpre[w], lane, bside);
-                const bool hit = ((m >> lane) & 1ull) && rk >= r0 && rk < r1;
-                idx[r] = rk - base;
-                if (hit) {
-                    mine |= 1u << r;
-                    const uint32_t o = static_cast<uint32_t>(r * NT + tid);
-                    omin = o < omin ? o : omin;
-                    omax = o > omax ? o : omax;
-                }
-            }
-            if (mine) {
-                atomicMin(&L.omin, omin);
-                atomicMax(&L.omax, omax);
-            }
-            __syncthreads();
-            const uint32_t lo_o = L.omin, hi_o = L.omax;
-            // the owned range [lo_o, hi_o] of the partner tile: read, swap,
-            // write back
+                m = bcast64(wd.bits, w);
+                return static_cast<uint32_t>(__shfl(static_cast<int>(wd.before), w, 64)) +
+                       ip_rank_in_word(m, lane, bside);
+            };
+            uint32_t own = 0, hit = 0;
 #pragma unroll
             for (int r = 0; r < EPT; ++r) {
-                const uint32_t o = static_cast<uint32_t>(r * NT + tid);
-                if (o >= lo_o && o <= hi_o) {
-                    R x = keys[ulo + o];
-                    VS y{};
-                    if constexpr (HV) y = vals[ulo + o];
-                    if ((mine >> r) & 1u) {
-                        const int op = L.pos[idx[r]];
-                        const R x_own = L.k[op];
-                        L.k[op] = x;
-                        x = x_own;
-                        if constexpr (HV) {
-                            const VS y_own = L.v[op];
-                            L.v[op] = y;
-                            y = y_own;
-                        }
+                uint64_t m;
+                const uint32_t before = before_of(r, m);
+                const int o = r * NT + tid;
+                const bool mis = (m >> lane) & 1ull;
+                const bool h = mis && before >= lr0 && before < lr1;
+                const bool in = o >= q0 && o < q1 && (h || (!mis && before > lr0 && before < lr1));
+                hit |= h ? 1u << r : 0u;
+                own |= in ? 1u << r : 0u;
+            }
+            R x[EPT];
+#pragma unroll
+            for (int r = 0; r < EPT; ++r)
+                if ((own >> r) & 1u) x[r] = uk[r * NT + tid];
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) {
+                // (the shuffles run with every lane active: a lane outside
+                // the branch could not serve as a source)
+                uint64_t m;
+                const uint32_t bf = before_of(r, m);
+                if ((hit >> r) & 1u) {
+                    const int op = L.pos[ub + bf - base];
+                    const R x_own = L.k[op];
+                    L.k[op] = x[r];
+                    x[r] = x_own;
+                }
+                if ((own >> r) & 1u) uk[r * NT + tid] = x[r];
+            }
+            if constexpr (HV) {
+                // payloads follow with the same masks (a second pass keeps
+                // the key registers free)
+                VS y[EPT];
+#pragma unroll
+                for (int r = 0; r < EPT; ++r)
+                    if ((own >> r) & 1u) y[r] = uv[r * NT + tid];
+#pragma unroll
+                for (int r = 0; r < EPT; ++r) {
+                    uint64_t m;
+                    const uint32_t bf = before_of(r, m);
+                    if ((hit >> r) & 1u) {
+                        const int op = L.pos[ub + bf - base];
+                        const VS y_own = L.v[op];
+                        L.v[op] = y[r];
+                        y[r] = y_own;
                     }
-                    keys[ulo + o] = x;
-                    if constexpr (HV) vals[ulo + o] = y;
+                    if ((own >> r) & 1u) uv[r * NT + tid] = y[r];
                 }
             }
             covered += r1 - r0;
-            __syncthreads();  // wpre, omin and omax are free again
         }
         u = bside == 0 ? u + 1 : u - 1;
     }
@@ -424,22 +479,23 @@ __device__ void ip_exchange_tile(const Args& a, int p, uint32_t t, IpLds<DT, V, 
     for (int r = 0; r < EPT; ++r) {
         const int o = r * NT + tid;
         if (o >= s0 && o < s1) {
-            keys[tlo + o] = L.k[o];
-            if constexpr (HV) vals[tlo + o] = L.v[o];
+            tk[o] = L.k[o];
+            if constexpr (HV) tv[o] = L.v[o];
         }
     }
     __syncthreads();  // LDS is free for the next tile
 }
 
+// At most 168 VGPRs: three waves per SIMD (no spills).
 template <int DT, class V, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_ip_exchange(Args a) {
+__global__ __launch_bounds__(NT, 3) void k_ip_exchange(Args a) {
     __shared__ IpLds<DT, V, NT, EPT> s_lds;
     const Ctl* c = a.ctl;
     const int p = a.level & 1;
     uint32_t ntiles = static_cast<uint32_t>(c->lc[p].segs >> 32);
     if (ntiles > a.cap_tile) ntiles = a.cap_tile;
-    if (blockIdx.x >= ntiles || c->error) return;  // (an error latched by an earlier step: nothing runs)
-    ip_exchange_tile<DT, V, NT, EPT>(a, p, blockIdx.x, s_lds);
+    if (c->error) return;  // an earlier step latched an error: the rest of the call does nothing
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) ip_exchange_tile<DT, V, NT, EPT>(a, t, s_lds);
 }
 
 // --------------------------------------------------------------- complete --
@@ -594,7 +650,8 @@ __global__ __launch_bounds__(NT) void k_ip_tail(Args a) {
     static_assert(NT == 256, "the plan and completion steps run 256 threads");
     using TL = IpTailLds<DT, V, NT, EPT, SP>;
     __shared__ alignas(16) unsigned char s_raw[TL::bytes];
-    __shared__ uint32_t s_w[2 * (NT / 64)];
+    __shared__ uint32_t s_red[2 * (NT / 64)];
+    __shared__ uint64_t s_w[NT / 64];
     Ctl* c = a.ctl;
     if (tail_error(c)) return;  // an earlier step latched an error: the rest of the call does nothing
     const int level_cap = 4 * a.depth_limit + 64;
@@ -615,13 +672,13 @@ __global__ __launch_bounds__(NT) void k_ip_tail(Args a) {
             if (threadIdx.x == 0) atomicOr(&c->error, ERR_OVERFLOW);
             break;
         }
-        for (uint32_t t = 0; t < ntile; ++t) ip_count_tile<DT, NT, EPT>(a, p, t, s_w);
+        for (uint32_t t = 0; t < ntile; ++t) ip_count_tile<DT, NT, EPT>(a, p, t, s_red);
         tail_sync();
         for (uint32_t si = 0; si < nseg; ++si) ip_scan_segment<NT>(a, p, si, s_w);
         tail_sync();
         if (tail_error(c)) break;
         auto& xl = *reinterpret_cast<IpLds<DT, V, NT, EPT>*>(s_raw);
-        for (uint32_t t = 0; t < ntile; ++t) ip_exchange_tile<DT, V, NT, EPT>(a, p, t, xl);
+        for (uint32_t t = 0; t < ntile; ++t) ip_exchange_tile<DT, V, NT, EPT>(a, t, xl);
         tail_sync();
         ip_complete_body(a, L, 0, 1);
         tail_sync();

@@ -48,7 +48,7 @@ struct SegDesc {
     uint64_t pivot_raw;  // pivot as stored bits
     uint32_t t0, nt;     // tiles [t0, t0 + nt) of this level belong to the segment
     uint32_t depth;
-    uint32_t pad;        // in-place levels: kSegForced, kSegARight
+    uint32_t pad;        // multiway levels: splitters in use; in-place levels: kSegForced
     // cursor claims (keys only): low 32 bits keys already placed in the left
     // run, high 32 bits in the right run (cleared by the plan kernel).
     // In-place levels: low 32 bits class-L keys, high 32 bits keys equal to
@@ -70,20 +70,29 @@ constexpr int kIpEPT = 16;
 constexpr int kIpT = kIpNT * kIpEPT;
 constexpr int kIpWords = kIpT / 64;  // 64-bit class words per tile
 
-// Per tile of an in-place level: counts from the count step, misplaced
-// counts and running sums from the scan step.  mis[0]: keys of the tile
-// left of the segment's boundary that are not class L; mis[1]: class-L
-// keys right of it.  rank[0]: mis[0] of the segment's earlier tiles;
-// rank[1]: mis[1] of the segment's tiles up to this one (inclusive), so
-// that the tile's misplaced keys right of the boundary have ranks
-// [M - rank[1], M - rank[1] + mis[1]) counted from the segment's right end
-// (M: the segment's misplaced keys per side).
+// Per tile of an in-place level: counts from the count step; misplaced
+// counts, ranks and the segment's values from the scan step.  mis[0]: keys
+// of the tile left of the segment's boundary that are not class L; mis[1]:
+// class-L keys right of it.  rank[0]: rank of the tile's first misplaced
+// key left of the boundary, counted from the segment's left end; rank[1]:
+// rank of its first misplaced key right of the boundary, counted from the
+// segment's right end (so its right-side keys have ranks [rank[1],
+// rank[1] + mis[1]) in descending position order).
 struct IpTile {
     uint32_t nl, neq;
     uint32_t mis[2];
     uint32_t rank[2];
-    uint32_t pad[2];
+    uint32_t seg_nl;   // the segment's class-L keys: boundary b = lo + seg_nl
+    uint32_t flags;    // kSegARight: the right part's tiles own the exchange
+    uint32_t tbase;    // the segment's first entry in the level's rank table
+    uint32_t pad[3];
 };
+
+// Rank table of an in-place level: per segment, entry j names the tile of
+// the partner side (the smaller part) that holds the misplaced key of rank
+// j * kIpRankStep, so that an owning tile finds its first partner tile with
+// one lookup and a short walk.
+constexpr int kIpRankStep = 256;
 
 // Per-tile copy of what a partition tile needs, written by the map kernel so
 // that a tile reaches its segment with one load.
@@ -113,7 +122,7 @@ struct LevelCtr {
     unsigned long long fills;  // low 32 bits: items, high 32 bits: work units
     unsigned int smalls[kSmallClasses];  // small segments per size class
     unsigned int tile_next;    // tile claim counter of the level that consumes this slot
-    unsigned int pad;
+    unsigned int tab;          // in-place levels: rank-table entries handed out
     unsigned long long keys;   // keys in the segments of this list (statistics)
 };
 
@@ -179,6 +188,8 @@ struct Args {
     int inplace; // 1: in-place levels (keys and payloads stay in x_keys / x_vals)
     uint64_t* ipmask;        // in-place levels: class bits, kIpWords words per tile
     IpTile* iptile;          // in-place levels: per tile counts and running sums
+    uint32_t* iprank;        // in-place levels: rank table (cap_tab entries)
+    uint32_t cap_tab;
     uint64_t* splitters[2];  // per slot: 16 order keys per segment
     uint32_t* toff;          // per tile: offset of its keys inside each bucket
     uint32_t* bcur;          // per segment: bucket cursors (stride 32)

@@ -303,6 +303,7 @@ __device__ inline void reset_next_slot(Ctl* c, int q, uint32_t nseg, uint32_t bi
         c->lc[q].fills = 0;
         for (int k = 0; k < kSmallClasses; ++k) c->lc[q].smalls[k] = 0;
         c->lc[q].tile_next = 0;
+        c->lc[q].tab = 0;
         c->lc[q].keys = 0;
         if (nseg) c->levels += 1;
     }
