@@ -10,9 +10,10 @@ continue the batch's range of the ring (in arrival order, up to a batch
 size), and sorts that range in place with one segmented call of the library
 (the request boundaries are the segment offsets) on its own HIP stream.
 Nothing is copied to form a batch.  The worker records an event after the
-call and goes on to the next batch at once; a batch's requests complete
-when its event has passed, at the device time the event records, and their
-slots go back to the ring then.
+call and waits for that event before it takes the next batch (one batch
+in flight per worker, so that requests arriving meanwhile join the next
+batch); a batch's requests complete at the device time the event records,
+and their slots go back to the ring then.
 
 Keys come out bit for bit as a request sorted alone would give them (the
 sorted sequence of a totally ordered key set is unique); for pairs, every
@@ -212,11 +213,19 @@ class SortService:
         self._ingest = torch.cuda.Stream()
         self._start = torch.cuda.Event(enable_timing=True)
         self._start.record()
-        # workspace of every worker, for the largest batch of any key type
+        # workspace of every worker, for the largest batch of any key type;
+        # the largest batch shrinks (by halves, down to 2^16 keys) until the
+        # workspaces take at most half the budget.  A request larger than the
+        # batch size is sorted alone and grows its worker's workspace.
         self._ctxs = [Context(**self.params) for _ in range(workers)]
-        most_segments = max(1, self.max_batch_keys >> 10)  # requests hold at least 2^10 keys
-        ws = max(self._ctxs[0].workspace_bytes(self.max_batch_keys, KEY_CODE[k], VAL_BYTES[k], most_segments)
-                 for k in KINDS)
+
+        def workspace(keys):
+            segs = max(1, keys >> 10)  # requests hold at least 2^10 keys
+            return max(self._ctxs[0].workspace_bytes(keys, KEY_CODE[k], VAL_BYTES[k], segs) for k in KINDS)
+
+        while self.max_batch_keys > (1 << 16) and workers * workspace(self.max_batch_keys) > budget_bytes // 2:
+            self.max_batch_keys //= 2
+        ws = workspace(self.max_batch_keys)
         for c in self._ctxs:
             c.reserve(ws)
         self.workspace_bytes = ws * workers
@@ -305,11 +314,11 @@ class SortService:
                         return
                 if batch:
                     pending.append(self._launch(batch, bid, stream, ctx))
-                # finish the batches whose event has passed; with nothing new
-                # to launch, wait for the oldest one
-                while pending and (pending[0][1].query() or not batch):
+                # one batch in flight per worker: requests that arrive while
+                # it runs join the next batch instead of each taking a small
+                # batch of its own (three workers keep the device busy)
+                while pending:
                     self._finish(*pending.popleft(), stream, ctx)
-                    batch = [None]  # one wait per round when idle
         except Exception as e:  # surfaced by close()
             self._errors.append(e)
             with self._cv:
