@@ -365,6 +365,21 @@ bqs_status bqs_sort_records(const void* in, void* out, int64_t n, int kind, bqs_
  * call, or an error an asynchronous call returned -- and clears it. */
 bqs_status bqs_ctx_sync_status(bqs_ctx* ctx);
 
+/* Completion clock of segmented calls (for callers that measure per-segment
+ * latency inside one batched call).  For the bqs_sort_segments and
+ * bqs_sort_segments_pairs calls made on this context from now on, `ticks`
+ * (a device array of at least k + 1 entries, caller-owned, kept alive until
+ * the calls complete) receives at [i] the device wall clock (a 100 MHz
+ * counter) at which the last key of segment i reached its final place --
+ * after the kernel that finished it had issued its stores -- and at [k]
+ * the clock when the call's first kernel started.  Segments of at most one
+ * key get that start time.  A call with more segments than
+ * `count` - 1 fails with BQS_EINVAL; a call that does no work (k = 0 or
+ * n_total <= 1) writes nothing.  ticks = NULL turns the clock off.  Changing
+ * it drops a captured graph.  The clock costs one atomic per finished
+ * piece. */
+bqs_status bqs_ctx_set_segment_ticks(bqs_ctx* ctx, uint64_t* ticks, int64_t count);
+
 /* Returns the first error latched by this context's calls that have
  * completed so far -- without waiting for the calls still running -- and
  * clears it (BQS_OK when there is none).  For callers that track each

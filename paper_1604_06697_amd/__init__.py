@@ -81,7 +81,7 @@ EXPORTED = [
     "bqs_ctx_set_param", "bqs_ctx_get_param", "bqs_ctx_get_stats", "bqs_ctx_get_level",
     "bqs_workspace_bytes",
     "bqs_sort", "bqs_sort_pairs", "bqs_sort_segments", "bqs_sort_segments_pairs",
-    "bqs_records_workspace_bytes", "bqs_sort_records", "bqs_ctx_sync_status", "bqs_ctx_poll_status",
+    "bqs_records_workspace_bytes", "bqs_sort_records", "bqs_ctx_sync_status", "bqs_ctx_poll_status", "bqs_ctx_set_segment_ticks",
     "bqs_status_str", "bqs_version", "bqs_sort_noalloc",
 ]
 
@@ -152,6 +152,7 @@ def _load(path: str = LIBRARY) -> ctypes.CDLL:
         "bqs_sort_records": ([vp, vp, i64, ctypes.c_int, vp], st),
         "bqs_ctx_sync_status": ([vp], st),
         "bqs_ctx_poll_status": ([vp], st),
+        "bqs_ctx_set_segment_ticks": ([vp, vp, i64], st),
         "bqs_status_str": ([st], ctypes.c_char_p),
         "bqs_version": ([], ctypes.c_int),
         "bqs_sort_noalloc": ([vp, i64, ctypes.c_int, vp, vp], st),
@@ -275,6 +276,22 @@ class Context:
         """Raises BqsError for the first error latched by calls that have
         completed so far, without waiting for the others."""
         _check(lib.bqs_ctx_poll_status(self._h), "bqs_ctx_poll_status")
+
+    def set_segment_ticks(self, ticks: torch.Tensor | None):
+        """Completion clock of later segmented calls: `ticks` (int64 on the
+        device, at least k + 1 entries) receives per segment the device
+        clock (100 MHz) when it was final, and at [k] the call's start;
+        None turns it off."""
+        if ticks is None:
+            _check(lib.bqs_ctx_set_segment_ticks(self._h, None, 0), "bqs_ctx_set_segment_ticks")
+            self._ticks = None
+            return
+        self._check_tensor(ticks, "ticks")
+        if ticks.dtype != torch.int64:
+            raise BqsError(1, "ticks must be int64")
+        self._ticks = ticks  # kept alive while calls may write it
+        _check(lib.bqs_ctx_set_segment_ticks(self._h, ctypes.c_void_p(ticks.data_ptr()), ticks.numel()),
+               "bqs_ctx_set_segment_ticks")
 
     def reserve(self, nbytes: int, device=None):
         """Allocates the workspace up front (at least `nbytes`), so that

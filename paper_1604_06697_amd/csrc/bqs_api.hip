@@ -89,12 +89,15 @@ __global__ __launch_bounds__(64) void k_init_single(Args a) {
         c->tiles = nt;
     } else if (n >= 2) {
         const int cls = small_class(n);
-        a.smalls[0][static_cast<size_t>(cls) * a.cap_small] = SmallItem{0, n};
+        a.smalls[0][static_cast<size_t>(cls) * a.cap_small] = SmallItem{0, n, 0u, 0u};
         c->lc[0].smalls[cls] = 1;
     }
 }
 
-__global__ __launch_bounds__(64) void k_zero_ctl(Args a) { clear_ctl(a.ctl); }
+__global__ __launch_bounds__(64) void k_zero_ctl(Args a) {
+    clear_ctl(a.ctl);
+    if (a.ticks && threadIdx.x == 0) a.ticks[a.k] = wall_clock64();  // segmented calls: the start
+}
 
 // One thread per segment: validate the offsets, then route the segment to
 // the level-0 partition list or straight to the small sort.
@@ -109,6 +112,9 @@ __global__ __launch_bounds__(256) void k_init_segments(Args a) {
         const bool bad = lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) ||
                          (i == a.k - 1 && hi != a.n) || hi - lo >= (int64_t(1) << 31);
         const int64_t m = hi - lo;
+        // completion clock: a segment of at most one key is final already;
+        // the others' times are raised by the kernels that finish their pieces
+        if (a.ticks) a.ticks[i] = bad || m > 1 ? 0ull : a.ticks[a.k];
         if (bad) {
             atomicOr(&c->error, ERR_OFFSETS);
         } else if (m > a.small_cut) {
@@ -126,6 +132,7 @@ __global__ __launch_bounds__(256) void k_init_segments(Args a) {
                 d.hi = hi;
                 d.t0 = static_cast<uint32_t>(t0);
                 d.nt = nt;
+                d.origin = static_cast<uint32_t>(i);
                 a.segs[0][idx] = d;
                 atomicAdd(&s_keys, static_cast<unsigned long long>(m));
                 atomicAdd(&s_tiles, static_cast<unsigned long long>(nt));
@@ -134,7 +141,7 @@ __global__ __launch_bounds__(256) void k_init_segments(Args a) {
             const int cls = small_class(m);
             const uint32_t idx = atomicAdd(&c->lc[0].smalls[cls], 1u);
             if (idx >= a.cap_small) atomicOr(&c->error, ERR_OVERFLOW);
-            else a.smalls[0][static_cast<size_t>(cls) * a.cap_small + idx] = SmallItem{lo, hi};
+            else a.smalls[0][static_cast<size_t>(cls) * a.cap_small + idx] = SmallItem{lo, hi, static_cast<uint32_t>(i), 0u};
         }
     }
     __syncthreads();
@@ -312,6 +319,8 @@ struct bqs_ctx {
     int64_t lookback = 0;   // 1: keys-only tiles also claim by decoupled look-back
     int64_t multiway = 0;   // 1: keys-only levels split around up to 15 splitters
     int64_t inplace = 0;    // 1: in-place levels (no double buffer)
+    unsigned long long* ticks = nullptr;  // segmented calls' completion clock (caller's device array)
+    int64_t ticks_count = 0;
     int64_t check_nan = 0;  // 1: floating-point keys are checked for NaN first
     int64_t enqueue_levels = 0;  // > 0: levels enqueued before the tail launch
     int64_t depth_limit = 0;     // > 0: replaces 2 floor(log2 n) + 3
@@ -575,7 +584,8 @@ std::vector<uint64_t> call_shape(const Ops* o, const Args& a, bool segmented) {
 std::vector<uint64_t> graph_key(const Ops* o, const Args& a, bool segmented, bool check) {
     auto u = [](const void* p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); };
     std::vector<uint64_t> k = call_shape(o, a, segmented);
-    for (uint64_t v : {u(a.ctl), u(a.x_keys), u(a.x_vals), u(a.y_keys), u(a.offsets), uint64_t(check ? 1 : 0)})
+    for (uint64_t v : {u(a.ctl), u(a.x_keys), u(a.x_vals), u(a.y_keys), u(a.offsets), u(a.ticks),
+                       uint64_t(check ? 1 : 0)})
         k.push_back(v);
     return k;
 }
@@ -1237,10 +1247,12 @@ bqs_status bqs_sort_segments(void* keys, const int64_t* offsets, int64_t k, int6
     const Ops* o = select_ops(ctx, dtype, 0);
     if (!o) return BQS_EDTYPE;
     if (k == 0 || n_total <= 1) return BQS_OK;
+    if (ctx->ticks && ctx->ticks_count < k + 1) return BQS_EINVAL;
     Args a;
     bqs_status st = prepare(ctx, o, n_total, dtype, 0, k, keys, nullptr, a);
     if (st != BQS_OK) return st;
     a.offsets = offsets;
+    a.ticks = ctx->ticks;
     return finish(ctx, run_sort(ctx, o, a, true, dtype));
 }
 
@@ -1252,10 +1264,12 @@ bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offset
     const Ops* o = select_ops(ctx, key, val_bytes);
     if (!o) return BQS_EDTYPE;
     if (k == 0 || n_total <= 1) return BQS_OK;
+    if (ctx->ticks && ctx->ticks_count < k + 1) return BQS_EINVAL;
     Args a;
     bqs_status st = prepare(ctx, o, n_total, key, val_bytes, k, keys, vals, a);
     if (st != BQS_OK) return st;
     a.offsets = offsets;
+    a.ticks = ctx->ticks;
     return finish(ctx, run_sort(ctx, o, a, true, key));
 }
 
@@ -1347,6 +1361,14 @@ bqs_status bqs_ctx_sync_status(bqs_ctx* ctx) {
     const bqs_status st = ctx->latched;
     ctx->latched = BQS_OK;
     return st;
+}
+
+bqs_status bqs_ctx_set_segment_ticks(bqs_ctx* ctx, uint64_t* ticks, int64_t count) {
+    if (!ctx || (ticks && count < 1)) return BQS_EINVAL;
+    ctx->ticks = reinterpret_cast<unsigned long long*>(ticks);
+    ctx->ticks_count = ticks ? count : 0;
+    drop_graph(ctx);
+    return BQS_OK;
 }
 
 bqs_status bqs_ctx_poll_status(bqs_ctx* ctx) {

@@ -517,10 +517,12 @@ __device__ inline void ip_complete_body(const Args& a, int level, uint32_t bid, 
         const bool valid = si < nseg;
         int64_t clo[2] = {0, 0}, chi[2] = {0, 0};
         bool forced[2] = {false, false};
-        uint32_t depth = 0;
+        uint32_t depth = 0, origin = 0;
         uint64_t pv = 0, praw = 0;
+        bool dropped = false;  // a part of equal keys that is finished
         if (valid) {
             const SegDesc sd = a.segs[p][si];
+            origin = sd.origin;
             const int64_t nl = static_cast<int64_t>(sd.cursor & 0xffffffffull);
             const int64_t ne = static_cast<int64_t>(sd.cursor >> 32);
             const int64_t b = sd.lo + nl;
@@ -533,6 +535,7 @@ __device__ inline void ip_complete_body(const Args& a, int level, uint32_t bid, 
                 // left part: the keys equal to the pivot, finished
                 clo[1] = b;
                 chi[1] = sd.hi;
+                dropped = b > sd.lo;
             } else {
                 clo[0] = sd.lo;
                 chi[0] = b;
@@ -541,9 +544,12 @@ __device__ inline void ip_complete_body(const Args& a, int level, uint32_t bid, 
                     clo[1] = b;
                     chi[1] = sd.hi;
                     forced[1] = ne > 0 && (nl == 0 || 8 * ne >= right);
+                } else {
+                    dropped = right > 0;
                 }
             }
         }
+        if (dropped) mark_done(a, origin);
         int kind[2], cls[2];
         uint32_t nt[2];
 #pragma unroll
@@ -552,6 +558,7 @@ __device__ inline void ip_complete_body(const Args& a, int level, uint32_t bid, 
             kind[h] = m <= 1 ? 0 : (m > S ? 1 : 2);
             nt[h] = kind[h] == 1 ? seg_tiles(clo[h], chi[h], T) : 0u;
             cls[h] = kind[h] == 2 ? small_class(m) : -1;
+            if (m == 1) mark_done(a, origin);  // one key, in place
         }
         const uint64_t sinc = static_cast<uint64_t>((kind[0] == 1) + (kind[1] == 1)) |
                               (static_cast<uint64_t>(nt[0] + nt[1]) << 32);
@@ -571,6 +578,7 @@ __device__ inline void ip_complete_body(const Args& a, int level, uint32_t bid, 
                     d.t0 = static_cast<uint32_t>(t0);
                     d.nt = nt[h];
                     d.depth = depth;
+                    d.origin = origin;
                     if (forced[h]) {
                         d.pad = kSegForced;
                         d.pivot = pv;
@@ -598,7 +606,7 @@ __device__ inline void ip_complete_body(const Args& a, int level, uint32_t bid, 
             for (int h = 0; h < 2; ++h) {
                 if (cls[h] != k) continue;
                 if (idx >= a.cap_small) atomicOr(&c->error, ERR_OVERFLOW);
-                else dst[idx] = SmallItem{clo[h], chi[h]};
+                else dst[idx] = SmallItem{clo[h], chi[h], origin, 0u};
                 ++idx;
             }
         }

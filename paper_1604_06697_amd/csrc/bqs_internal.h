@@ -54,6 +54,8 @@ struct SegDesc {
     // In-place levels: low 32 bits class-L keys, high 32 bits keys equal to
     // the pivot (written by the scan step)
     unsigned long long cursor;
+    uint32_t origin;     // segmented calls: the input segment this one is part of
+    uint32_t pad2;
 };
 
 // SegDesc::pad bits of the in-place step.  kSegForced: the pivot was fixed
@@ -105,6 +107,8 @@ struct TileDesc {
 
 struct SmallItem {
     int64_t lo, hi;
+    uint32_t origin;  // segmented calls: the input segment this one is part of
+    uint32_t pad;
 };
 
 struct FillItem {
@@ -113,7 +117,7 @@ struct FillItem {
     int64_t side;    // first position of the run's payloads in the side buffer
     uint64_t raw;    // key bits of the pivot
     uint32_t chunk0; // first fill work unit of this item
-    uint32_t pad0;
+    uint32_t origin; // segmented calls: the input segment the run belongs to
     uint64_t pad1;
 };
 
@@ -190,6 +194,10 @@ struct Args {
     IpTile* iptile;          // in-place levels: per tile counts and running sums
     uint32_t* iprank;        // in-place levels: rank table (cap_tab entries)
     uint32_t cap_tab;
+    // segmented calls with a completion clock: per input segment the device
+    // wall clock (100 MHz) when its last key became final, and at [k] the
+    // call's start (nullptr: not recorded)
+    unsigned long long* ticks;
     uint64_t* splitters[2];  // per slot: 16 order keys per segment
     uint32_t* toff;          // per tile: offset of its keys inside each bucket
     uint32_t* bcur;          // per segment: bucket cursors (stride 32)

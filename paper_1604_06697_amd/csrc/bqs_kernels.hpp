@@ -192,71 +192,12 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 // ---------------------------------------------------------------------------
-// Work-list appends (one thread).  A segment of more than small_cut keys is
-// partitioned at the next level; a shorter one is finished by the small
-// sort; one key already in the caller's buffer needs nothing.
+// Completion clock of segmented calls: from now on a piece of input segment
+// `origin` is final (its keys are in place in X).  The latest such time of a
+// segment is its completion time.
 
-__device__ inline void push_segment(const Args& a, int slot, int64_t lo, int64_t hi,
-                                    uint32_t depth) {
-    const int64_t m = hi - lo;
-    if (m <= 0) return;
-    Ctl* c = a.ctl;
-    if (m > a.small_cut) {
-        const int64_t T = a.tile_keys;
-        const uint32_t nt = seg_tiles(lo, hi, T);
-        const unsigned long long r =
-            atomicAdd(&c->lc[slot].segs, (static_cast<unsigned long long>(nt) << 32) | 1ull);
-        const uint32_t idx = static_cast<uint32_t>(r);
-        const uint64_t t0 = r >> 32;
-        if (idx >= a.cap_seg || t0 + nt > a.cap_tile) {
-            atomicOr(&c->error, ERR_OVERFLOW);
-            return;
-        }
-        SegDesc d;
-        d.lo = lo;
-        d.hi = hi;
-        d.pivot = 0;
-        d.pivot_raw = 0;
-        d.t0 = static_cast<uint32_t>(t0);
-        d.nt = nt;
-        d.depth = depth;
-        d.pad = 0;
-        d.cursor = 0;
-        a.segs[slot][idx] = d;
-    } else {
-        if (m == 1 && slot == 0) return;
-        const int cls = small_class(m);
-        const uint32_t idx = atomicAdd(&c->lc[slot].smalls[cls], 1u);
-        if (idx >= a.cap_small) {
-            atomicOr(&c->error, ERR_OVERFLOW);
-            return;
-        }
-        a.smalls[slot][static_cast<size_t>(cls) * a.cap_small + idx] = SmallItem{lo, hi};
-    }
-}
-
-__device__ inline void push_fill(const Args& a, int slot, int64_t dst, int64_t len, int64_t side,
-                                 uint64_t raw) {
-    if (len <= 0) return;
-    Ctl* c = a.ctl;
-    const uint32_t nch = static_cast<uint32_t>((len + kFillChunk - 1) / kFillChunk);
-    const unsigned long long r =
-        atomicAdd(&c->lc[slot].fills, (static_cast<unsigned long long>(nch) << 32) | 1ull);
-    const uint32_t idx = static_cast<uint32_t>(r);
-    if (idx >= a.cap_fill) {
-        atomicOr(&c->error, ERR_OVERFLOW);
-        return;
-    }
-    FillItem f;
-    f.dst = dst;
-    f.len = len;
-    f.side = side;
-    f.raw = raw;
-    f.chunk0 = static_cast<uint32_t>(r >> 32);
-    f.pad0 = 0;
-    f.pad1 = 0;
-    a.fills[slot][idx] = f;
-    atomicAdd(&c->fill_keys, static_cast<unsigned long long>(len));
+__device__ __forceinline__ void mark_done(const Args& a, uint32_t origin) {
+    if (a.ticks) atomicMax(&a.ticks[origin], static_cast<unsigned long long>(wall_clock64()));
 }
 
 // Writes the equal-key runs recorded for level p into X: keys get the stored
@@ -291,6 +232,10 @@ __device__ void run_fills(const Args& a, int p, uint32_t bid, uint32_t nblk) {
             if constexpr (HV) {
                 static_cast<V*>(a.x_vals)[f.dst + t] = static_cast<const V*>(a.side)[f.side + t];
             }
+        }
+        if (a.ticks) {
+            __syncthreads();  // every thread's stores of the chunk are issued
+            if (tid == 0) mark_done(a, f.origin);
         }
     }
 }
@@ -987,7 +932,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
         const uint32_t si = base + threadIdx.x;
         const bool valid = si < nseg;
         int64_t lo = 0, hi = 0, Lt = 0, Gt = 0;
-        uint32_t depth = 0;
+        uint32_t depth = 0, origin = 0;
         uint64_t raw = 0;
         if (valid) {
             const SegDesc sd = a.segs[p][si];
@@ -995,6 +940,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
             hi = sd.hi;
             depth = sd.depth + 1;
             raw = sd.pivot_raw;
+            origin = sd.origin;
             if (cursor) {
                 Lt = static_cast<int64_t>(sd.cursor & 0xffffffffull);
                 Gt = static_cast<int64_t>(sd.cursor >> 32);
@@ -1023,6 +969,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
             kind[h] = m <= 0 ? 0 : (m > S ? 1 : ((m == 1 && q == 0) ? 0 : 2));
             nt[h] = kind[h] == 1 ? seg_tiles(clo[h], chi[h], T) : 0u;
             cls[h] = kind[h] == 2 ? small_class(m) : -1;
+            if (m == 1 && kind[h] == 0) mark_done(a, origin);  // one key, already in X
         }
         // segments of level L+1 (count | tiles << 32)
         const uint64_t sinc = static_cast<uint64_t>((kind[0] == 1) + (kind[1] == 1)) |
@@ -1043,6 +990,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
                     d.t0 = static_cast<uint32_t>(t0);
                     d.nt = nt[h];
                     d.depth = depth;
+                    d.origin = origin;
                     a.segs[q][idx] = d;
                 }
                 ++idx;
@@ -1071,7 +1019,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
             for (int h = 0; h < 2; ++h) {
                 if (cls[h] != k) continue;
                 if (idx >= a.cap_small) atomicOr(&c->error, ERR_OVERFLOW);
-                else dst[idx] = SmallItem{clo[h], chi[h]};
+                else dst[idx] = SmallItem{clo[h], chi[h], origin, 0u};
                 ++idx;
             }
         }
@@ -1092,7 +1040,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
                     f.side = lo;
                     f.raw = raw;
                     f.chunk0 = static_cast<uint32_t>(at >> 32);
-                    f.pad0 = 0;
+                    f.origin = origin;
                     f.pad1 = 0;
                     a.fills[q][idx] = f;
                 }
@@ -1777,7 +1725,8 @@ __device__ void small_all_body(const Args& a, int level, uint32_t bid, uint32_t 
         bucket_sort_segment<DT, V, NT, SMAX>(a, p, s.lo, m, L, pr);
         my_keys += static_cast<unsigned long long>(m);
         ++nseg;
-        __syncthreads();  // LDS is reused by the next segment
+        __syncthreads();  // LDS is reused by the next segment (and every store is issued)
+        if (threadIdx.x == 0) mark_done(a, s.origin);
     }
     if (threadIdx.x == 0 && my_keys) atomicAdd(&c->small_keys, my_keys);
     if (pr && threadIdx.x == 0 && nseg) {

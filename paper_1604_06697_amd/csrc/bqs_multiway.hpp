@@ -235,7 +235,9 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
             kind = m > S ? 1 : ((m == 1 && q == 0) ? 0 : 2);
             if (kind == 1) nt = seg_tiles(blo, blo + m, T);
             if (kind == 2) cls = small_class(m);
+            if (kind == 0) mark_done(a, sd.origin);  // one key, already in X
         }
+        if (used && eqb && m > 0 && q == 0) mark_done(a, sd.origin);  // equal keys scattered into X
         const uint64_t sinc = kind == 1 ? (1ull | (static_cast<uint64_t>(nt) << 32)) : 0ull;
         if (__ballot(sinc != 0)) {
             const uint64_t at = wave_append(&c->lc[q].segs, sinc, lane);
@@ -251,6 +253,7 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
                     d.t0 = static_cast<uint32_t>(t0);
                     d.nt = nt;
                     d.depth = sd.depth + 1;
+                    d.origin = sd.origin;
                     a.segs[q][idx] = d;
                 }
                 next_keys += static_cast<unsigned long long>(m);
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
             if (cls == k) {
                 const uint32_t idx = first + mbcnt(bm);
                 if (idx >= a.cap_small) atomicOr(&c->error, ERR_OVERFLOW);
-                else a.smalls[q][static_cast<size_t>(k) * a.cap_small + idx] = SmallItem{blo, blo + m};
+                else a.smalls[q][static_cast<size_t>(k) * a.cap_small + idx] = SmallItem{blo, blo + m, sd.origin, 0u};
             }
         }
         // keys equal to a splitter, left in the workspace buffer: written
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
                     f.side = blo;
                     f.raw = static_cast<uint64_t>(K::inv(static_cast<decltype(K::ord(typename K::raw()))>(o)));
                     f.chunk0 = static_cast<uint32_t>(at >> 32);
-                    f.pad0 = 0;
+                    f.origin = sd.origin;
                     f.pad1 = 0;
                     a.fills[q][idx] = f;
                 }

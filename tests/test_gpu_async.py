@@ -223,3 +223,49 @@ def test_depth_follows_the_last_call(torch_mod, bqs, oracle):
         else:
             assert st["levels"] == first["levels"]
             assert st["partition_launches"] >= st["levels"] + 1
+
+
+def test_segment_completion_clock(torch_mod, bqs, oracle):
+    """bqs_ctx_set_segment_ticks: every segment's completion time is at or
+    after the call's start, segments of at most one key complete at the
+    start, the latest completion is no later than the host saw the call end,
+    and the keys are the oracle's -- for the default, in-place, multiway,
+    host-driven, graph and persistent forms."""
+    torch = torch_mod
+    keys, offsets = W.segmented_i32(300, 48, 0.0, 17.0)
+    sizes = np.diff(offsets)
+    k = sizes.size
+    expect = oracle.sort_segments(keys, offsets)
+    off = torch.from_numpy(offsets).cuda()
+    forms = [("default", {}), ("in-place", {"inplace": 1}), ("multiway", {"multiway": 1}),
+             ("host-driven", {"mode": bqs.MODE_LEVELS}), ("graph", {"graph": 1}),
+             ("persistent", {"mode": bqs.MODE_PERSISTENT})]
+    for name, params in forms:
+        ctx = bqs.Context(**params)
+        ticks = torch.full((k + 1,), -1, dtype=torch.int64, device="cuda")
+        ctx.set_segment_ticks(ticks)
+        for rep in range(2 if params.get("graph") else 1):
+            note(f"completion clock, {name}, call {rep}")
+            t = to_dev(torch, keys)
+            ticks.fill_(-1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sort_segments(t, off)
+            ctx.synchronize()
+            torch.cuda.synchronize()
+            wall_ticks = (time.perf_counter() - t0) * 1e8  # 100 MHz
+            assert np.array_equal(host(t, np.int32), expect), name
+            tk = ticks.cpu().numpy()
+            start = tk[k]
+            assert start > 0, name
+            done = tk[:k]
+            assert np.all(done >= start), (name, np.flatnonzero(done < start)[:8])
+            assert np.all(done[sizes <= 1] == start), name
+            assert np.all(done[sizes > 4096] > start), name
+            assert done.max() - start <= wall_ticks, (name, done.max() - start, wall_ticks)
+        # too short an array is an argument error
+        ctx.set_segment_ticks(ticks[:k])
+        with pytest.raises(bqs.BqsError):
+            ctx.sort_segments(to_dev(torch, keys), off)
+        ctx.set_segment_ticks(None)
+        ctx.close()
