@@ -216,9 +216,13 @@ __device__ void run_fills(const Args& a, int p, uint32_t bid, uint32_t nblk) {
     if (nfill == 0) return;
     const uint32_t nchunk = static_cast<uint32_t>(fc >> 32);
     R* xk = static_cast<R*>(a.x_keys);
+    // every item has at least one chunk, so item i starts at a chunk in
+    // [i, i + extra]: the item of chunk ch lies in [ch - extra, ch]
+    const uint32_t extra = nchunk > nfill ? nchunk - nfill : 0u;
     for (uint32_t ch = bid; ch < nchunk; ch += nblk) {
         // items are ordered by chunk0: find the last one starting at or before ch
-        uint32_t lo_i = 0, hi_i = nfill;
+        uint32_t lo_i = ch > extra ? ch - extra : 0u;
+        uint32_t hi_i = ch + 1 < nfill ? ch + 1 : nfill;
         while (hi_i - lo_i > 1) {
             const uint32_t mid = (lo_i + hi_i) >> 1;
             if (a.fills[p][mid].chunk0 <= ch) lo_i = mid; else hi_i = mid;
@@ -271,6 +275,7 @@ struct PlanLds {
     typename KeyT<DT>::raw samp[NT / 64][kMaxSample + 1];
     typename KeyT<DT>::raw grp[NT / 64][8];  // group medians (medians of medians)
     typename KeyT<DT>::raw pick[NT / 64];
+    typename KeyT<DT>::raw bcast;            // wave 0's pivot, for the whole workgroup
 };
 
 // Sample of one segment of m keys at recursion depth `depth` (the paper's
@@ -318,22 +323,24 @@ __device__ inline PivotPlan pivot_plan(const Args& a, int64_t m, uint32_t depth)
     return pp;
 }
 
-// Element of rank `target` among the 256 order keys a wave holds, four per
-// lane (lane l holds positions 4l .. 4l+3): a bitonic sorting network over
-// the wave -- partners two or one apart inside a lane's registers, farther
-// ones in other lanes (lane xor) -- then the element at position `target`.
-template <class O>
-__device__ __forceinline__ O wave_rank_select(O (&v)[4], int target, int lane) {
+// Element of rank `target` among the 64*P order keys a wave holds, P per
+// lane (lane l holds positions P*l .. P*l+P-1): a bitonic sorting network
+// over the wave -- partners less than P apart inside a lane's registers,
+// farther ones in other lanes (lane xor) -- then the element at position
+// `target`.  P = 1, 2 or 4: the network is sized to the sample.
+template <class O, int P>
+__device__ __forceinline__ O wave_rank_select(O (&v)[P], int target, int lane) {
+    static_assert(P == 1 || P == 2 || P == 4, "one, two or four keys per lane");
 #pragma unroll
-    for (int size = 2; size <= 256; size <<= 1) {
+    for (int size = 2; size <= 64 * P; size <<= 1) {
 #pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            if (stride < 4) {
+            if (stride < P) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < P; ++r) {
                     const int pr = r ^ stride;
                     if (pr > r) {
-                        const bool up = ((4 * lane + r) & size) == 0;
+                        const bool up = ((P * lane + r) & size) == 0;
                         const O x = v[r], y = v[pr];
                         const O lo = x < y ? x : y, hi = x < y ? y : x;
                         v[r] = up ? lo : hi;
@@ -341,10 +348,10 @@ __device__ __forceinline__ O wave_rank_select(O (&v)[4], int target, int lane) {
                     }
                 }
             } else {
-                const int d = stride >> 2;
+                const int d = stride / P;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int pos = 4 * lane + r;
+                for (int r = 0; r < P; ++r) {
+                    const int pos = P * lane + r;
                     const O other = shfl_xor_o(v[r], d);
                     const bool keep_small = ((pos & stride) == 0) == ((pos & size) == 0);
                     v[r] = keep_small ? (other < v[r] ? other : v[r]) : (other > v[r] ? other : v[r]);
@@ -352,10 +359,27 @@ __device__ __forceinline__ O wave_rank_select(O (&v)[4], int target, int lane) {
             }
         }
     }
-    const int r = target & 3;
-    const O mine = r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3]));
-    if constexpr (sizeof(O) == 8) return static_cast<O>(bcast64(static_cast<uint64_t>(mine), target >> 2));
-    else return static_cast<O>(__shfl(static_cast<int>(mine), target >> 2, 64));
+    const int r = target % P;
+    O mine = v[0];
+#pragma unroll
+    for (int i = 1; i < P; ++i) mine = r == i ? v[i] : mine;
+    if constexpr (sizeof(O) == 8) return static_cast<O>(bcast64(static_cast<uint64_t>(mine), target / P));
+    else return static_cast<O>(__shfl(static_cast<int>(mine), target / P, 64));
+}
+
+// The sample of wave-held keys: sample i (of k <= 64*P) at position P*lane +
+// r, past the sample the largest order key; its element of rank `target`.
+template <class K, int P, class Pos>
+__device__ __forceinline__ auto sample_rank_select(const typename K::raw* src, int k, int target, int lane,
+                                                  Pos sample_pos) {
+    using O = decltype(K::ord(typename K::raw()));
+    O v[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const int i = P * lane + r;
+        v[r] = i < k ? K::ord(src[sample_pos(i)]) : static_cast<O>(~O(0));
+    }
+    return wave_rank_select<O, P>(v, target, lane);
 }
 
 // The pivot of segment [lo, hi) at recursion depth `depth`, picked by wave
@@ -382,15 +406,15 @@ __device__ typename KeyT<DT>::raw segment_pivot(const Args& a, const typename Ke
         return lo + i * stride + static_cast<int64_t>(h % static_cast<uint64_t>(stride));
     };
     if (pp.g == 0) {
-        // one sample: sorted in registers across the wave; the pick is the
-        // key of the target rank
-        O v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = 4 * lane + r;
-            v[r] = i < k ? K::ord(src[sample_pos(i)]) : static_cast<O>(~O(0));
+        // one sample: sorted in registers across the wave (a network of 64,
+        // 128 or 256 keys, the smallest that holds it; none for a wave
+        // without a segment); the pick is the key of the target rank
+        O pick = 0;
+        if (valid) {
+            if (k <= 64) pick = sample_rank_select<K, 1>(src, k, pp.rk, lane, sample_pos);
+            else if (k <= 128) pick = sample_rank_select<K, 2>(src, k, pp.rk, lane, sample_pos);
+            else pick = sample_rank_select<K, 4>(src, k, pp.rk, lane, sample_pos);
         }
-        const O pick = wave_rank_select(v, valid ? pp.rk : 0, lane);
         // the workgroup's barriers stay the same for every wave (a wave with
         // medians of medians may share the workgroup)
         __syncthreads();
@@ -440,11 +464,14 @@ __device__ typename KeyT<DT>::raw segment_pivot(const Args& a, const typename Ke
 
 // The plan step as workgroup `bid` of `nblk` (all NT threads).  Each
 // segment's pivot goes into its descriptor and into the descriptors of its
-// tiles (and the tiles' look-back words are cleared).  With at least two
-// workgroups per segment (the first levels) the workgroups of a segment each
-// pick its pivot -- the pick is deterministic -- and write a share of its
-// tile descriptors, so that a segment of many tiles is not left to one
-// wave; otherwise one wave per segment.
+// tiles (and the tiles' look-back words are cleared).  On the first levels,
+// whose few segments have many tiles each, several workgroups of a segment
+// each pick its pivot with one wave -- the pick is deterministic -- and write
+// a share of its tile descriptors, so that a segment of many tiles is not
+// left to one wave; otherwise one wave per segment.
+constexpr uint32_t kPlanParts = 64;   // most plan workgroups that share one segment's tile descriptors
+constexpr uint32_t kPlanDescs = 512;  // tile descriptors per plan workgroup on the first levels
+
 template <int DT, class V, int NT>
 __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk, PlanLds<DT, NT>& lds) {
     using K = KeyT<DT>;
@@ -455,20 +482,32 @@ __device__ void plan_body(const Args& a, int level, uint32_t bid, uint32_t nblk,
     Ctl* c = a.ctl;
     const int p = level & 1, q = p ^ 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
+    const unsigned long long lcs = c->lc[p].segs;
+    uint32_t nseg = static_cast<uint32_t>(lcs);
     reset_next_slot(c, q, nseg, bid);
     if (nseg > a.cap_seg) nseg = a.cap_seg;  // an overflow was latched
     const R* src = static_cast<const R*>(p ? a.y_keys : a.x_keys);
+    // workgroups per segment: one per kPlanDescs tile descriptors of the
+    // average segment, at most kPlanParts and nblk / nseg (the others only
+    // run the fills)
+    uint32_t parts = 0;
+    if (nseg > 0) {
+        parts = static_cast<uint32_t>(lcs >> 32) / nseg / kPlanDescs;
+        parts = parts < kPlanParts ? parts : kPlanParts;
+        parts = parts < nblk / nseg ? parts : nblk / nseg;
+    }
 
-    if (nseg > 0 && 2 * nseg <= nblk) {
-        const uint32_t parts = nblk / nseg;
+    if (parts >= 2) {
+        // in each workgroup of a segment, wave 0 picks the pivot
         const uint32_t si = bid % nseg, part = bid / nseg;
         if (part < parts) {
             SegDesc* sd = &a.segs[p][si];
             const int64_t lo = sd->lo, hi = sd->hi;
             const uint32_t t0 = sd->t0, nt = sd->nt;
-            // every wave picks the same pivot; wave 0's is used
-            const R pick = segment_pivot<DT, NT>(a, src, lo, hi, sd->depth, true, lds);
+            const R pick0 = segment_pivot<DT, NT>(a, src, lo, hi, sd->depth, wv == 0, lds);
+            if (tid == 0) lds.bcast = pick0;
+            __syncthreads();
+            const R pick = lds.bcast;
             // an in-place segment whose pivot its parent fixed keeps it
             const R piv = (sd->pad & kSegForced) ? static_cast<R>(sd->pivot_raw) : pick;
             const uint64_t po = static_cast<uint64_t>(K::ord(piv));
