@@ -576,6 +576,33 @@ __global__ __launch_bounds__(NT) void k_plan(Args a) {
     plan_body<DT, V, NT>(a, a.level, blockIdx.x, gridDim.x, s_lds);
 }
 
+// N consecutive elements of 4 or 8 bytes from a 4-byte aligned address, in
+// 16-byte (or 8-byte) vector loads; global memory takes unaligned vector
+// accesses.
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+template <class T, int N>
+__device__ __forceinline__ void load_run(const T* p, T* out) {
+    constexpr int B = N * static_cast<int>(sizeof(T));
+    static_assert(B % 8 == 0, "whole 8-byte words");
+    uint32_t w[B / 4];
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int q = 0; q < B / 16; ++q) {
+            const u32x4_a4 v = reinterpret_cast<const u32x4_a4*>(p)[q];
+            w[4 * q] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+    } else {
+        const u32x2_a4 v = *reinterpret_cast<const u32x2_a4*>(p);
+        w[0] = v.x;
+        w[1] = v.y;
+    }
+    __builtin_memcpy(out, w, B);
+}
+
 // ---------------------------------------------------------------------------
 // Partition tile, shared by the level-mode and persistent kernels.
 //
@@ -674,14 +701,21 @@ __device__ __forceinline__ TileOut tile_partition(const TileIO& io, unsigned lon
     const O piv = static_cast<O>(io.pivot);
     const R* tsrc = src + tbase;
 
-    // scanning phase: coalesced loads, item i of thread tid is key i*NT + tid
+    // scanning phase: coalesced loads.  A whole tile in 16-byte loads:
+    // thread tid holds the VW consecutive keys of vector u*NT + tid (u <
+    // EPT/VW) as items u*VW .. u*VW+VW-1 (the order of the items only decides
+    // the order of the keys inside the runs, the same on every run); a
+    // partial tile item i of thread tid is key i*NT + tid
     R key[EPT];
     VS val[EPT];
     if (full) {
+        constexpr int VW = 16 / static_cast<int>(sizeof(R));
+        static_assert(EPT % VW == 0, "whole vectors per thread");
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            key[i] = tsrc[i * NT + tid];
-            if constexpr (HV) val[i] = vsrc[tbase + i * NT + tid];
+        for (int u = 0; u < EPT / VW; ++u) {
+            const int64_t at = static_cast<int64_t>(u * NT + tid) * VW;
+            load_run<R, VW>(tsrc + at, key + u * VW);
+            if constexpr (HV) load_run<VS, VW>(vsrc + tbase + at, val + u * VW);
         }
     } else {
 #pragma unroll
@@ -906,8 +940,12 @@ __global__ __launch_bounds__(NT) void k_partition(Args a) {
     // fixed in advance); the surplus leaves before taking a ticket
     if (blockIdx.x >= ntiles || c->error) return;  // (an error latched by an earlier step: nothing runs)
     if (a.prof && tid < 6) s_prof[tid] = 0;
+    // the look-back needs tiles taken in order (a ticket); cursor claims
+    // wait for no other tile, so the workgroup index serves
+    constexpr bool HV = !std::is_same<V, NoVal>::value;
+    const bool ticket = HV || a.claim == 0 || a.shuffle;
     if (tid == 0) {
-        uint32_t t = atomicAdd(&c->lc[p].tile_next, 1u);
+        uint32_t t = ticket ? atomicAdd(&c->lc[p].tile_next, 1u) : blockIdx.x;
         if (a.shuffle && t < ntiles) {
             // stress test: tiles of each window of 64 tickets in reverse
             // order, so look-backs wait on tiles claimed after them (each
