@@ -840,7 +840,7 @@ def main():
                                       "correct": bok}
 
     # the multiway partition step (opt-in; same keys, fewer passes)
-    mctx = bqs.Context(timing=1, multiway=1, small_cutoff=8192)
+    mctx = bqs.Context(timing=1, multiway=1)
     mms, mst, _, mpart_ms, mpart_keys, mok = run_workload(
         torch, bqs, mctx, "i32_uniform", args.n, max(2, args.steps // 2), 1)
     # a multiway pass reads each key twice (count, scatter) and writes it once
