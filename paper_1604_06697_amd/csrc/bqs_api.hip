@@ -384,6 +384,15 @@ int64_t eff_tile_keys(const bqs_ctx* ctx, const Ops* o) {
     return ctx && ctx->multiway && o->mscan ? o->multi_tile_keys : o->tile_keys;
 }
 
+// Smallest tile a call may use (it sizes the tile lists): the two-way
+// keys-only levels of enqueued calls take half-size tiles on levels of many
+// segments.
+int64_t layout_tile_keys(const bqs_ctx* ctx, const Ops* o) {
+    const int64_t t = eff_tile_keys(ctx, o);
+    const bool two_way = !(ctx && (ctx->inplace || (ctx->multiway && o->mscan)));
+    return two_way && o->half_tile_keys > 0 ? std::min<int64_t>(t, o->half_tile_keys) : t;
+}
+
 int64_t eff_small_cut(const bqs_ctx* ctx, const Ops* o) {
     int64_t s = ctx && ctx->small_cut > 0 ? ctx->small_cut : o->small_default;
     if (s > o->small_max) s = o->small_max;
@@ -622,10 +631,17 @@ uint64_t seg_bound(const Args& a, int L) {
     return std::min<uint64_t>(segs, a.cap_seg);
 }
 
-// Most tiles level L can hold: n/T plus two partial tiles per segment.
+// Two-way keys-only levels whose segment bound reaches this take half-size
+// tiles (on 2^28 int32 keys: from level 8 on, 378-391 us a full level
+// against 403-410 us; with fewer segments the claims of the many small tiles
+// crowd onto few cursors, 818 us at level 0).
+constexpr uint64_t kHalfTileSegs = 256;
+
+// Most tiles level L can hold: its segments are disjoint, and each has at
+// most one partial tile, so n/T plus one per segment.
 uint64_t tile_bound(const Args& a, int L) {
     const uint64_t T = static_cast<uint64_t>(a.tile_keys);
-    return std::min<uint64_t>(static_cast<uint64_t>(a.n) / T + 2 * seg_bound(a, L) + 2, a.cap_tile);
+    return std::min<uint64_t>(static_cast<uint64_t>(a.n) / T + seg_bound(a, L) + 2, a.cap_tile);
 }
 
 // Enqueues init, the optional NaN check, `levels` recursion levels with
@@ -634,6 +650,13 @@ uint64_t tile_bound(const Args& a, int L) {
 // timing, e.g. under graph capture).
 bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int dtype, int levels,
                           hipStream_t s, Timer* tm) {
+    const bool half = o->half_tile_keys > 0 && !a.ways && !a.inplace && a.claim != 0 && !a.shuffle;
+    // (the last three enqueued levels carry little work, or none when the
+    // learned depth holds: their launches stay small with the default tiles)
+    auto tile_keys_of = [&](int L) {
+        return half && L + 3 < levels && seg_bound(a, L) >= kHalfTileSegs ? o->half_tile_keys : o->tile_keys;
+    };
+    if (!a.ways && !a.inplace) a.tile_keys = tile_keys_of(0);
     if (segmented) launch_init_segments(a, s);
     else launch_init_single(a, s);
     if (check && (dtype == BQS_F32 || dtype == BQS_F64))
@@ -642,6 +665,12 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
     const uint64_t n = static_cast<uint64_t>(a.n);
     for (int L = 0; L < levels; ++L) {
         a.level = L;
+        if (!a.ways && !a.inplace) {
+            // this level's tiles, and the tiles its completion gives the
+            // children (the tail takes the default tiles)
+            a.tile_keys = tile_keys_of(L);
+            a.next_tile_keys = tile_keys_of(L + 1);
+        }
         const uint64_t sb = seg_bound(a, L);
         const uint64_t sb_prev = L ? seg_bound(a, L - 1) : 0;
         // equal runs written at level L: at most one chunk per kFillChunk
@@ -680,7 +709,7 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
             o->mscatter(a, tg, s);
             if (tm) tm->stop(2, L);
         } else {
-            o->tile(a, tg, s);
+            (a.tile_keys == o->tile_keys ? o->tile : o->tile_half)(a, tg, s);
             if (tm) tm->stop(2, L);
             if (tm) tm->start_aux();
             o->complete(a, clamp_grid((sb + 255) / 256, 1024), s);
@@ -694,7 +723,8 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
     t.ways = 0;
     if (!a.inplace) {
         t.tile_keys = o->tile_keys;
-        t.retile = a.tile_keys != o->tile_keys ? 1 : 0;
+        t.next_tile_keys = o->tile_keys;
+        t.retile = a.next_tile_keys != o->tile_keys ? 1 : 0;
     }
     if (tm) tm->start_aux();
     if (a.inplace) o->ip_tail(t, s);
@@ -931,7 +961,7 @@ bqs_status prepare_in(const bqs_ctx* ctx, void* ws, size_t ws_bytes, const Ops* 
     const int64_t S = eff_small_cut(ctx, o);
     const bool inplace = ctx && ctx->inplace;
     const bool multiway = ctx && ctx->multiway && o->mscan && !inplace;
-    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, eff_tile_keys(ctx, o), S, multiway, inplace);
+    const Layout L = make_layout(n, kb, static_cast<size_t>(vb), k, layout_tile_keys(ctx, o), S, multiway, inplace);
     if (L.cap_tile > 0xffffffffull || L.cap_seg > 0xffffffffull || L.cap_small > 0xffffffffull ||
         L.cap_tab > 0xffffffffull)
         return BQS_EINVAL;
@@ -996,6 +1026,7 @@ bqs_status prepare_in(const bqs_ctx* ctx, void* ws, size_t ws_bytes, const Ops* 
         a.cap_fill = std::min(a.cap_fill, c);
     }
     a.tile_keys = static_cast<int>(eff_tile_keys(ctx, o));
+    a.next_tile_keys = a.tile_keys;
     a.prof = ctx ? static_cast<int>(ctx->profile) : 0;
     a.claim = ctx && ctx->lookback ? 0 : 1;
     a.ways = multiway ? 1 : 0;
@@ -1210,7 +1241,7 @@ size_t bqs_workspace_bytes(const bqs_ctx* ctx, int64_t n_total, bqs_dtype key, i
     const Ops* o = select_ops(ctx, key, val_bytes);
     if (!o) return 0;
     const Layout L = make_layout(n_total, key_bytes(key), static_cast<size_t>(val_bytes),
-                                 std::max<int64_t>(k_segments, 1), eff_tile_keys(ctx, o), eff_small_cut(ctx, o),
+                                 std::max<int64_t>(k_segments, 1), layout_tile_keys(ctx, o), eff_small_cut(ctx, o),
                                  ctx && ctx->multiway && o->mscan && !ctx->inplace, ctx && ctx->inplace);
     return L.total;
 }

@@ -183,7 +183,8 @@ struct Args {
     int pivot_mode;
     int pivot_skew;  // >= 2: pivot = the sample's 1/skew quantile (skewed-pivot study)
     int depth_limit;
-    int tile_keys;
+    int tile_keys;       // keys per tile of this level
+    int next_tile_keys;  // keys per tile of the next level (the completion tiles the children)
     int prof;
     int claim;  // 1: keys-only tiles claim their ranges with the segment's cursor
     int ways;   // 1: multiway partition levels (keys only)
@@ -239,6 +240,10 @@ struct Ops {
     void (*ip_exchange)(const Args&, int grid, hipStream_t);
     void (*ip_complete)(const Args&, int grid, hipStream_t);
     void (*ip_tail)(const Args&, hipStream_t);
+    // keys-only two-way levels with many segments: half-size tiles (more
+    // workgroups in flight; their claims spread over many cursors), or 0
+    int half_tile_keys;
+    void (*tile_half)(const Args&, int grid, hipStream_t);
 };
 
 // The map step of level `level`, as thread `gtid` of `gstride`: every tile

@@ -999,7 +999,7 @@ __device__ void complete_body(const Args& a, int level, uint32_t bid, uint32_t n
     const bool cursor = !HV && a.claim != 0;
     uint32_t nseg = static_cast<uint32_t>(c->lc[p].segs);
     if (nseg > a.cap_seg) nseg = a.cap_seg;  // an overflow was latched
-    const int64_t T = a.tile_keys;
+    const int64_t T = a.next_tile_keys;
     const int64_t S = a.small_cut;
     // statistics of this thread's appends: equal keys, and keys / tiles the
     // next level partitions
@@ -2100,6 +2100,12 @@ struct Launch {
     static void tile(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_partition<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
     }
+    // half-size tiles for keys-only levels of many segments (4-byte keys)
+    static constexpr bool kHalf = std::is_same<V, NoVal>::value && EPT == 32;
+    static constexpr int kHalfEpt = kHalf ? EPT / 2 : EPT;
+    static void tile_half(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_partition<DT, V, NT, kHalfEpt>), dim3(grid), dim3(NT), 0, s, a);
+    }
     static void complete(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_complete<V>), dim3(grid), dim3(256), 0, s, a);
     }
@@ -2179,7 +2185,9 @@ struct Launch {
             &ip_scan,
             &ip_exchange,
             &ip_complete,
-            &ip_tail};
+            &ip_tail,
+            kHalf ? NT * EPT / 2 : 0,
+            kHalf ? &tile_half : nullptr};
         return &o;
     }
 };
