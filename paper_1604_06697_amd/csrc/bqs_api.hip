@@ -636,6 +636,12 @@ uint64_t seg_bound(const Args& a, int L) {
 // against 403-410 us; with fewer segments the claims of the many small tiles
 // crowd onto few cursors, 818 us at level 0).
 constexpr uint64_t kHalfTileSegs = 256;
+// Levels of fewer segments take double-size tiles on 512 threads when the
+// array fills at least kDoubleTileMin of them (the first levels of 2^28
+// int32 keys: about 425 us a level against 450 us, half the claims on their
+// one to sixteen cursors).
+constexpr uint64_t kDoubleTileSegs = 32;
+constexpr uint64_t kDoubleTileMin = 2048;
 
 // Most tiles level L can hold: its segments are disjoint, and each has at
 // most one partial tile, so n/T plus one per segment.
@@ -650,11 +656,16 @@ uint64_t tile_bound(const Args& a, int L) {
 // timing, e.g. under graph capture).
 bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int dtype, int levels,
                           hipStream_t s, Timer* tm) {
-    const bool half = o->half_tile_keys > 0 && !a.ways && !a.inplace && a.claim != 0 && !a.shuffle;
+    const bool alt = o->half_tile_keys > 0 && !a.ways && !a.inplace && a.claim != 0 && !a.shuffle;
     // (the last three enqueued levels carry little work, or none when the
     // learned depth holds: their launches stay small with the default tiles)
     auto tile_keys_of = [&](int L) {
-        return half && L + 3 < levels && seg_bound(a, L) >= kHalfTileSegs ? o->half_tile_keys : o->tile_keys;
+        if (!alt || L + 3 >= levels) return o->tile_keys;
+        const uint64_t sb = seg_bound(a, L);
+        if (sb >= kHalfTileSegs) return o->half_tile_keys;
+        if (sb < kDoubleTileSegs && static_cast<uint64_t>(a.n) / o->double_tile_keys >= kDoubleTileMin)
+            return o->double_tile_keys;
+        return o->tile_keys;
     };
     if (!a.ways && !a.inplace) a.tile_keys = tile_keys_of(0);
     if (segmented) launch_init_segments(a, s);
@@ -709,7 +720,10 @@ bqs_status enqueue_levels(const Ops* o, Args a, bool segmented, bool check, int 
             o->mscatter(a, tg, s);
             if (tm) tm->stop(2, L);
         } else {
-            (a.tile_keys == o->tile_keys ? o->tile : o->tile_half)(a, tg, s);
+            const auto tile = a.tile_keys == o->half_tile_keys     ? o->tile_half
+                              : a.tile_keys == o->double_tile_keys ? o->tile_double
+                                                                   : o->tile;
+            tile(a, tg, s);
             if (tm) tm->stop(2, L);
             if (tm) tm->start_aux();
             o->complete(a, clamp_grid((sb + 255) / 256, 1024), s);

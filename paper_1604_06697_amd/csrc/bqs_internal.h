@@ -244,6 +244,10 @@ struct Ops {
     // workgroups in flight; their claims spread over many cursors), or 0
     int half_tile_keys;
     void (*tile_half)(const Args&, int grid, hipStream_t);
+    // keys-only two-way levels of few, large segments: double-size tiles on
+    // twice the threads (half the claims on the few cursors), or 0
+    int double_tile_keys;
+    void (*tile_double)(const Args&, int grid, hipStream_t);
 };
 
 // The map step of level `level`, as thread `gtid` of `gstride`: every tile

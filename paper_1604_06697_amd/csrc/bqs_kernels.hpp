@@ -2106,6 +2106,12 @@ struct Launch {
     static void tile_half(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_partition<DT, V, NT, kHalfEpt>), dim3(grid), dim3(NT), 0, s, a);
     }
+    // double-size tiles on twice the threads for keys-only levels of few,
+    // large segments
+    static constexpr int kDoubleNt = kHalf ? 2 * NT : NT;
+    static void tile_double(const Args& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_partition<DT, V, kDoubleNt, EPT>), dim3(grid), dim3(kDoubleNt), 0, s, a);
+    }
     static void complete(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_complete<V>), dim3(grid), dim3(256), 0, s, a);
     }
@@ -2187,7 +2193,9 @@ struct Launch {
             &ip_complete,
             &ip_tail,
             kHalf ? NT * EPT / 2 : 0,
-            kHalf ? &tile_half : nullptr};
+            kHalf ? &tile_half : nullptr,
+            kHalf ? 2 * NT * EPT : 0,
+            kHalf ? &tile_double : nullptr};
         return &o;
     }
 };
