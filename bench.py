@@ -814,7 +814,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": measured_traffic(),
-            "kernel": f"k_partition (int32 keys, {st['tile_keys']}-key tiles of 256 threads)",
+            "kernel": "k_partition (int32 keys; by level 16384-key tiles of 512 threads, 8192 or 4096 of 256)",
             "bytes_per_launch": round(2 * r * part_keys / max(launches, 1)),
             "avg_launch_ms": round(part_ms / max(launches, 1), 4),
         },

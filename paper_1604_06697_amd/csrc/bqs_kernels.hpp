@@ -2100,8 +2100,10 @@ struct Launch {
     static void tile(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_partition<DT, V, NT, EPT>), dim3(grid), dim3(NT), 0, s, a);
     }
-    // half-size tiles for keys-only levels of many segments (4-byte keys)
-    static constexpr bool kHalf = std::is_same<V, NoVal>::value && EPT == 32;
+    // half-size tiles for keys-only levels of many segments (tiles of 32 KB
+    // of keys: 8192 4-byte or 4096 8-byte keys)
+    static constexpr bool kHalf =
+        std::is_same<V, NoVal>::value && NT * EPT * sizeof(typename KeyT<DT>::raw) == 32768 && EPT % 2 == 0;
     static constexpr int kHalfEpt = kHalf ? EPT / 2 : EPT;
     static void tile_half(const Args& a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_partition<DT, V, NT, kHalfEpt>), dim3(grid), dim3(NT), 0, s, a);
