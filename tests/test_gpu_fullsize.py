@@ -7,7 +7,10 @@ element by element with the CPU oracle on the same seeded input.
   2^26 uint64 keys with uint32 payloads (payload = original index);
 * 20,000 int32 arrays of log-uniform sizes in [16, 2^20] (about 1.9e9 keys),
   sorted by one segmented call with the default plan and by graph replays of
-  the multiway plan, against the oracle's per-segment sort.
+  the multiway plan, against the oracle's per-segment sort;
+* 2^25 + 4097 uint32, float32 and int64 keys, large enough for every
+  per-level partition tile size, in the default, graph and host-driven
+  modes.
 
 The oracle is single-threaded; independent oracle sorts run in threads (its
 ctypes calls release the interpreter lock), so a test takes seconds.
@@ -53,7 +56,8 @@ def pool():
         yield ex
 
 
-_KT = {np.dtype(np.int32): "i32", np.dtype(np.float64): "f64", np.dtype(np.uint64): "u64"}
+_KT = {np.dtype(np.int32): "i32", np.dtype(np.float64): "f64", np.dtype(np.uint64): "u64",
+       np.dtype(np.uint32): "u32", np.dtype(np.float32): "f32", np.dtype(np.int64): "i64"}
 _HOLD = {np.dtype(np.uint64): np.int64, np.dtype(np.uint32): np.int32}
 
 
@@ -125,6 +129,37 @@ def test_2p26_u64_u32_pairs_match_oracle(torch_mod, bqs, oracle, pool):
     assert np.array_equal(ko, ref), first_difference(ko, ref)
     assert np.array_equal(np.sort(vo), np.arange(n))
     assert np.array_equal(k[vo], ko)
+
+
+@pytest.mark.parametrize("mode", ["default", "graph", "levels"])
+def test_per_level_tiles_match_oracle(torch_mod, bqs, oracle, pool, mode):
+    """Arrays large enough for every partition tile size of the enqueued
+    levels (16384-key tiles on the first levels, 4096-key tiles once a level
+    can hold 256 segments, 8192 in between and on the last levels): uint32,
+    float32 and int64 keys of a ragged length, bit for bit the oracle's.
+    Graph mode replays its captured levels twice on refilled buffers; the
+    host-driven mode keeps one tile size, the same keys."""
+    n = (1 << 25) + 4097
+    cases = [np.random.default_rng(31).integers(0, 2**32, n, dtype=np.uint32),
+             W.normal_f64(n, 32).astype(np.float32),
+             W.few_distinct_i32(n, 33).astype(np.int64) * 7919 - (1 << 40)]
+    expects = [pool.submit(oracle.sort, a) for a in cases]
+    plan = {"default": {}, "graph": {"graph": 1}, "levels": {"mode": bqs.MODE_LEVELS}}[mode]
+    torch = torch_mod
+    for a, expect in zip(cases, expects):
+        ctx = bqs.Context(**plan)
+        ref = expect.result()
+        src = to_dev(torch, a)
+        t = torch.empty_like(src)
+        for rep in range(2 if mode == "graph" else 1):
+            note(f"per-level tiles, {mode}, {a.dtype} n={n}, call {rep}")
+            t.copy_(src)
+            ctx.sort(t, key_type=_KT[a.dtype])
+            torch.cuda.synchronize()
+            got = t.cpu().numpy().view(a.dtype)
+            assert np.array_equal(got.view(f"u{a.itemsize}"), ref.view(f"u{a.itemsize}")), first_difference(got, ref)
+        ctx.close()
+        del src, t
 
 
 def oracle_segments_parallel(oracle, pool, keys, offsets, chunks=16):
