@@ -335,7 +335,7 @@ bqs_status bqs_sort_segments_pairs(void* keys, void* vals, const int64_t* offset
  *                    the stream reaches the end of the sort; NULL: none.
  * Returns BQS_ETOOBIG, with nothing enqueued, when the sort needs more than
  * the scratch: n up to bqs_workspace_bytes(NULL, n, dtype, 0, 1) <= 64 MiB,
- * about 16.5 million 4-byte or 8.16 million 8-byte keys.  Other argument
+ * about 16.4 million 4-byte or 8.08 million 8-byte keys.  Other argument
  * errors as for bqs_sort.  Every call on a GPU shares that GPU's scratch
  * (which keeps the last call's contents; every call starts by clearing what
  * must start at zero): calls that overlap on one GPU -- on different
