@@ -28,7 +28,7 @@ import torch
 from . import BqsError, Context, _key_code
 
 EPT_CHOICES = (8, 16, 32)
-CUTOFF_CHOICES = (1024, 2048, 4096, 8192)
+CUTOFF_CHOICES = (1024, 2048, 4096, 8192, 16384)
 PIVOT_CHOICES = (0, 55)
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")
 

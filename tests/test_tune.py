@@ -28,7 +28,8 @@ def test_candidates_follow_compiled_shapes(tune):
     # two-way plans with each pivot strategy, multiway plans with the default
     assert {c["pivot_mode"] for c in i32 if not c["multiway"]} == set(tune.PIVOT_CHOICES)
     assert {c["pivot_mode"] for c in i32 if c["multiway"]} == {0}
-    assert len(i32) == 12 * len(tune.PIVOT_CHOICES) + 12
+    per_step = len(tune.EPT_CHOICES) * len(tune.CUTOFF_CHOICES)
+    assert len(i32) == per_step * len(tune.PIVOT_CHOICES) + per_step
     # other key types and pairs compile one tile shape (0 = library default)
     assert {c["tile_ept"] for c in tune.candidates(6, 0)} == {0}
     assert {c["tile_ept"] for c in tune.candidates(1, 4)} == {0}
