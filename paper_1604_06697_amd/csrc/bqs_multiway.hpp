@@ -97,16 +97,29 @@ __global__ __launch_bounds__(NT) void k_plan_multi(Args a) {
             ws[i] = src[lo + i * stride + static_cast<int64_t>(h % static_cast<uint64_t>(stride))];
         }
         __syncthreads();
-        // sample ranks (ties broken by sample index) place the sample in order
-        for (int i = lane; i < k; i += 64) {
-            const auto om = K::ord(ws[i]);
-            int rank = 0;
-#pragma unroll 8
-            for (int j = 0; j < k; ++j) {
-                const auto oj = K::ord(ws[j]);
-                rank += (oj < om) | ((oj == om) & (j < i));
+        // sample ranks (ties broken by sample index) place the sample in
+        // order; each lane ranks its up to four samples in one pass over
+        // the sample (one LDS read serves four comparisons)
+        {
+            using O = decltype(K::ord(R()));
+            O om[4];
+            int rank[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = lane + 64 * r;
+                om[r] = i < k ? K::ord(ws[i]) : O(0);
+                rank[r] = 0;
             }
-            so[rank] = ws[i];
+#pragma unroll 4
+            for (int j = 0; j < k; ++j) {
+                const O oj = K::ord(ws[j]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    rank[r] += (oj < om[r]) | ((oj == om[r]) & (j < lane + 64 * r));
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (lane + 64 * r < k) so[rank[r]] = ws[lane + 64 * r];
         }
         __syncthreads();
         // splitters: the sample's order statistics at ranks (j+1)*k/16, then
