@@ -211,12 +211,16 @@ __global__ __launch_bounds__(NT) void k_mcount(Args a) {
 // (the bucket totals), and the next level's lists.  Even buckets are appended
 // like the children of the two-way step; odd buckets are final (keys equal to
 // a splitter) and, when they sit in the workspace buffer, become equal runs
-// written into X by the next level.
+// written into X by the next level.  The appends of a workgroup's waves take
+// one atomic add per list, issued by different threads at once.
 template <int DT, int NT>
 __global__ __launch_bounds__(NT) void k_mscan(Args a) {
     using K = KeyT<DT>;
     constexpr int NW = NT / 64;
+    constexpr int kLists = 2 + kSmallClasses;
     __shared__ unsigned long long s_stat[NW][3];
+    __shared__ unsigned long long s_w[NW][kLists];  // per wave: its total of each list's appends
+    __shared__ unsigned long long s_base[kLists];   // per list: the workgroup's first slot
     Ctl* c = a.ctl;
     if (c->error) return;  // an earlier step latched an error: the rest of the call does nothing
     const int p = a.level & 1, q = p ^ 1;
@@ -251,65 +255,89 @@ __global__ __launch_bounds__(NT) void k_mscan(Args a) {
             if (kind == 0) mark_done(a, sd.origin);  // one key, already in X
         }
         if (used && eqb && m > 0 && q == 0) mark_done(a, sd.origin);  // equal keys scattered into X
+        // the appends of the whole workgroup, one atomic add per list and
+        // workgroup (list 0: segments of level L+1, count | tiles << 32; 1:
+        // equal runs, count | chunks << 32; 2 + k: small segments of class k)
         const uint64_t sinc = kind == 1 ? (1ull | (static_cast<uint64_t>(nt) << 32)) : 0ull;
-        if (__ballot(sinc != 0)) {
-            const uint64_t at = wave_append(&c->lc[q].segs, sinc, lane);
-            const uint32_t idx = static_cast<uint32_t>(at);
-            const uint64_t t0 = at >> 32;
-            if (kind == 1) {
-                if (idx >= a.cap_seg || t0 + nt > a.cap_tile) {
-                    atomicOr(&c->error, ERR_OVERFLOW);
-                } else {
-                    SegDesc d{};
-                    d.lo = blo;
-                    d.hi = blo + m;
-                    d.t0 = static_cast<uint32_t>(t0);
-                    d.nt = nt;
-                    d.depth = sd.depth + 1;
-                    d.origin = sd.origin;
-                    a.segs[q][idx] = d;
-                }
-                next_keys += static_cast<unsigned long long>(m);
-                next_tiles += nt;
-            }
-        }
-        for (int k = 0; k < kSmallClasses; ++k) {
-            const uint64_t bm = __ballot(cls == k);
-            if (!bm) continue;
-            uint32_t first = 0;
-            if (lane == 0) first = atomicAdd(&c->lc[q].smalls[k], static_cast<uint32_t>(__popcll(bm)));
-            first = static_cast<uint32_t>(__shfl(static_cast<int>(first), 0, 64));
-            if (cls == k) {
-                const uint32_t idx = first + mbcnt(bm);
-                if (idx >= a.cap_small) atomicOr(&c->error, ERR_OVERFLOW);
-                else a.smalls[q][static_cast<size_t>(k) * a.cap_small + idx] = SmallItem{blo, blo + m, sd.origin, 0u};
-            }
-        }
-        // keys equal to a splitter, left in the workspace buffer: written
-        // into X by the next level (as the pivot's run of the two-way step)
         const bool fill = used && eqb && m > 0 && q == 1;
         const uint32_t nch = fill ? static_cast<uint32_t>((m + kFillChunk - 1) / kFillChunk) : 0u;
         const uint64_t finc = fill ? (1ull | (static_cast<uint64_t>(nch) << 32)) : 0ull;
-        if (__ballot(finc != 0)) {
-            const uint64_t at = wave_append(&c->lc[q].fills, finc, lane);
-            if (fill) {
-                const uint32_t idx = static_cast<uint32_t>(at);
-                if (idx >= a.cap_fill) {
-                    atomicOr(&c->error, ERR_OVERFLOW);
-                } else {
-                    const uint64_t o = a.splitters[p][static_cast<size_t>(si) * 16 + (lane >> 1)];
-                    FillItem f;
-                    f.dst = blo;
-                    f.len = m;
-                    f.side = blo;
-                    f.raw = static_cast<uint64_t>(K::inv(static_cast<decltype(K::ord(typename K::raw()))>(o)));
-                    f.chunk0 = static_cast<uint32_t>(at >> 32);
-                    f.origin = sd.origin;
-                    f.pad1 = 0;
-                    a.fills[q][idx] = f;
-                }
+        const uint64_t sin = wave_inclusive_sum(sinc, lane);
+        const uint64_t fin = wave_inclusive_sum(finc, lane);
+        if (lane == 63) {
+            s_w[wv][0] = sin;
+            s_w[wv][1] = fin;
+        }
+        uint64_t bm_own = 0;
+#pragma unroll
+        for (int k = 0; k < kSmallClasses; ++k) {
+            const uint64_t bm = __ballot(cls == k);
+            if (cls == k) bm_own = bm;
+            if (lane == 0) s_w[wv][2 + k] = static_cast<unsigned long long>(__popcll(bm));
+        }
+        __syncthreads();
+        if (tid < kLists) {
+            unsigned long long total = 0;
+            for (int w = 0; w < NW; ++w) total += s_w[w][tid];
+            unsigned long long at = 0;
+            if (total) {
+                if (tid == 0) at = atomicAdd(&c->lc[q].segs, total);
+                else if (tid == 1) at = atomicAdd(&c->lc[q].fills, total);
+                else at = atomicAdd(&c->lc[q].smalls[tid - 2], static_cast<uint32_t>(total));
+            }
+            s_base[tid] = at;
+        }
+        __syncthreads();
+        auto wave_base = [&](int list) {
+            unsigned long long b = s_base[list];
+            for (int w = 0; w < wv; ++w) b += s_w[w][list];
+            return b;
+        };
+        if (kind == 1) {
+            const uint64_t at = wave_base(0) + sin - sinc;
+            const uint32_t idx = static_cast<uint32_t>(at);
+            const uint64_t t0 = at >> 32;
+            if (idx >= a.cap_seg || t0 + nt > a.cap_tile) {
+                atomicOr(&c->error, ERR_OVERFLOW);
+            } else {
+                SegDesc d{};
+                d.lo = blo;
+                d.hi = blo + m;
+                d.t0 = static_cast<uint32_t>(t0);
+                d.nt = nt;
+                d.depth = sd.depth + 1;
+                d.origin = sd.origin;
+                a.segs[q][idx] = d;
+            }
+            next_keys += static_cast<unsigned long long>(m);
+            next_tiles += nt;
+        }
+        if (cls >= 0) {
+            const uint32_t idx = static_cast<uint32_t>(wave_base(2 + cls)) + mbcnt(bm_own);
+            if (idx >= a.cap_small) atomicOr(&c->error, ERR_OVERFLOW);
+            else a.smalls[q][static_cast<size_t>(cls) * a.cap_small + idx] = SmallItem{blo, blo + m, sd.origin, 0u};
+        }
+        // keys equal to a splitter, left in the workspace buffer: written
+        // into X by the next level (as the pivot's run of the two-way step)
+        if (fill) {
+            const uint64_t at = wave_base(1) + fin - finc;
+            const uint32_t idx = static_cast<uint32_t>(at);
+            if (idx >= a.cap_fill) {
+                atomicOr(&c->error, ERR_OVERFLOW);
+            } else {
+                const uint64_t o = a.splitters[p][static_cast<size_t>(si) * 16 + (lane >> 1)];
+                FillItem f;
+                f.dst = blo;
+                f.len = m;
+                f.side = blo;
+                f.raw = static_cast<uint64_t>(K::inv(static_cast<decltype(K::ord(typename K::raw()))>(o)));
+                f.chunk0 = static_cast<uint32_t>(at >> 32);
+                f.origin = sd.origin;
+                f.pad1 = 0;
+                a.fills[q][idx] = f;
             }
         }
+        __syncthreads();  // s_w and s_base are reused by the next round
         if (used && eqb && m > 0) fill_keys += static_cast<unsigned long long>(m);
     }
     // statistics: one set of atomics per workgroup
