@@ -762,8 +762,8 @@ def main():
         return
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        print("bench.py: the sort runs on one GPU; --gpus must be 1 "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 
